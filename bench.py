@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the whole per-block path on one MI355X.
+
+Workload: FAST-shaped block, 19 beams x 4096 channels of uint8 total power,
+49.152 us samples, 10 s of data (203,450 samples), 2048-sample sub-intervals
+(99 full sub-intervals; the 698-sample tail is not a full cell), synthetic
+(seeded, generated on the GPU, device-resident before timing). One step is
+one pass of the whole path over the block:
+
+    rfi_ccm_accumulate -> rfi_eig_batched -> rfi_flag
+
+Metric: beam-sample GB/s = nbeam * nchan * nsub * L bytes / step time.
+Prints one JSON line (see the keys below).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+FP32_VALU_PEAK = 78.6e12       # non-packed FP32 FMA: 256 CU x 64 lanes x 2 x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(spec, nsub_sample: int):
+    """The FP64 oracle, as it stands, on a bounded sample: every channel of
+    the first nsub_sample sub-intervals (bytes regenerated on the CPU)."""
+    from oracle import pipeline
+    from paper_2512_16278_amd import synth
+    L = spec.L
+    t0 = time.perf_counter()
+    x = synth.generate(spec, 0, nsub_sample * L)
+    tgen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cr, res, _ = pipeline.block(x, L, nsub_sample)
+    dt = time.perf_counter() - t0
+    nbytes = x.size
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return {
+        "value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+        "sample": f"all {spec.nchan} channels x {nsub_sample} sub-ints of {L} samples x "
+                  f"{spec.nbeam} beams ({nbytes / 1e6:.0f} MB, {nsub_sample * spec.nchan} cells); "
+                  f"oracle {dt:.2f} s, input generation {tgen:.1f} s not timed",
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variant", default="mfma", choices=["mfma", "valu"])
+    ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
+    ap.add_argument("--cpu-sample-subints", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(cells are independent; sharding by channel range is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_16278_amd import rfi, synth
+
+    dev = torch.device("cuda:0")
+    spec = synth.fast_spec(seconds=args.seconds)
+    nb, nc, ns, L = spec.nbeam, spec.nchan, spec.nsamp, spec.L
+    nsub = ns // L
+    ncell = nsub * nc
+    npair = nb * (nb + 1) // 2
+    stride = (nc + 15) // 16 * 16
+    log(f"workload: {nb} beams x {nc} ch x {ns} samples, L={L}, {nsub} sub-ints, "
+        f"{spec.nbytes() / 1e9:.2f} GB")
+    data = torch.empty((nb, ns, stride), dtype=torch.uint8, device=dev)
+    ds = rfi.DeviceSynth(spec, dev)
+    for b in range(nb):
+        ds.fill(data[b], b)
+    torch.cuda.synchronize()
+    log("input generated on the GPU")
+
+    blk = rfi.make_block(data, nc)
+    sx = torch.empty((nb, ncell), dtype=torch.int32, device=dev)
+    sxy = torch.empty((npair, ncell), dtype=torch.int32, device=dev)
+    cnt = torch.empty(nsub, dtype=torch.int32, device=dev)
+    stat = torch.empty(ncell, dtype=torch.float64, device=dev)
+    status = torch.empty(ncell, dtype=torch.uint8, device=dev)
+    mask = torch.empty(ncell, dtype=torch.uint8, device=dev)
+    fstats = torch.zeros(48, dtype=torch.uint8, device=dev)
+    variant = rfi.RFI_CCM_MFMA if args.variant == "mfma" else rfi.RFI_CCM_VALU
+    stream = torch.cuda.current_stream()
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def step(timed=None):
+        if timed is not None:
+            ev[0].record(stream)
+        rfi.rfi_ccm_accumulate(blk, 0, L, nsub, sx, sxy, cnt, variant=variant)
+        if timed is not None:
+            ev[1].record(stream)
+        rfi.rfi_eig_batched(nb, nsub, nc, sx, sxy, cnt, stat, status, precision=args.precision)
+        if timed is not None:
+            ev[2].record(stream)
+        rfi.rfi_flag(nsub, nc, stat, status, mask, out=fstats)
+        if timed is not None:
+            ev[3].record(stream)
+            torch.cuda.synchronize()
+            timed.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # whole-step timing: K steps back to back between two synchronisations
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        step()
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
+
+    # per-stage timing (events between the calls of each step)
+    stages = []
+    for _ in range(max(3, min(args.steps, 10))):
+        step(stages)
+    st = np.array(stages)
+    ms_ccm, ms_eig, ms_flag = np.median(st, axis=0)
+    lat = st.sum(axis=1)
+    log(f"stages (median ms): ccm {ms_ccm:.3f}  eig {ms_eig:.3f}  flag {ms_flag:.3f}")
+
+    nbytes_in = nb * nc * nsub * L
+    value = nbytes_in / (ms_step / 1e3) / 1e9
+    # dominant kernel and its roofline
+    ccm_bytes = nbytes_in + 4 * (nb + npair) * ncell          # bytes in + sums out
+    ccm_gbs = ccm_bytes / (ms_ccm / 1e3) / 1e9
+    flags = rfi.flag_stats_from_bytes(fstats.cpu().numpy().tobytes())
+    if ms_ccm >= ms_eig:
+        roof = {"kernel": "ccm_mfma_kernel" if variant == rfi.RFI_CCM_MFMA else "ccm_valu_kernel",
+                "bound": "hbm", "achieved": round(ccm_gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ccm_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "ms": round(float(ms_ccm), 4)}
+    else:
+        # algorithmic FP32 flops of the Jacobi: per sweep n(n-1)/2 rotations of
+        # 6(n-2) + 12 flops; sweep count taken as 6
+        flop = ncell * 6 * (nb * (nb - 1) / 2) * (6 * (nb - 2) + 12)
+        ach = flop / (ms_eig / 1e3)
+        roof = {"kernel": "eig_lane_jacobi", "bound": "alu", "achieved": round(ach / 1e12, 2),
+                "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_VALU_PEAK, 4), "traffic": None,
+                "ms": round(float(ms_eig), 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(spec, args.cpu_sample_subints)
+        log(f"cpu baseline: {cpu['value'] * 1e3:.2f} MB/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "beam-sample GB/s through CCM+eigen+flag at 1 GPU; p50/p99 block latency",
+        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded FAST-shaped, generated on the GPU)",
+        "config": {"workload": f"FAST-shaped block: {nb} beams x {nc} channels x {ns} samples "
+                               f"(10 s at 49.152 us), L={L}, {nsub} sub-ints, "
+                               f"{nbytes_in / 1e9:.2f} GB", "nbeam": nb, "nchan": nc,
+                   "L": L, "nsub": nsub, "ccm": args.variant, "jacobi": f"fp{args.precision}"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4)},
+        "stages_ms": {"ccm": round(float(ms_ccm), 4), "eig": round(float(ms_eig), 4),
+                      "flag": round(float(ms_flag), 4)},
+        "hbm_frac_whole_path": round(value / HBM_PEAK_GBS, 4),
+        "flagged_cells": int(flags["nflag"]), "clip_iterations": int(flags["iterations"]),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

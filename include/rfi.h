@@ -1,0 +1,195 @@
+/*
+ * rfi.h -- C ABI of librfi: multi-beam RFI identification by eigenvalue
+ * decomposition of per-cell cross-correlation matrices, on one MI355X (gfx950).
+ *
+ * Method: Bai et al., "Radio frequency interference identification using
+ * eigenvalue decomposition for multi-beam observations" (arXiv 2512.16278).
+ * A cell is one (sub-interval k, frequency channel j). For every cell the
+ * library forms the nbeam x nbeam cross-correlation matrix of the beams'
+ * total power (Sec. 3.2, Eq. 1), eigendecomposes it (Sec. 3.3, Eq. 2), forms
+ * the normalised dominant eigenvalue lambda_1^2 / sum_i lambda_i^2 (Sec. 3.3),
+ * and turns it into an RFI mask by iterative Gaussian clipping (Sec. 3.3,
+ * threshold multiple kappa of Sec. 4.5), optionally refined per beam with the
+ * dominant eigenvector (Sec. 3.3 last paragraph, kappa_v of Sec. 4.5).
+ *
+ * Conventions for every call:
+ *  - Every array argument is a DEVICE pointer unless marked "host". The
+ *    caller owns all of them; the library never frees caller memory.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    rfi_stream_t; NULL is the null stream). Argument errors are returned
+ *    synchronously and nothing is launched; rfi_last_error() then holds a
+ *    message for the calling thread. Device-side conditions are reported
+ *    through per-cell status bits and the stats structs.
+ *  - ncell = nsub * nchan and cell = k * nchan + j. Per-cell arrays are
+ *    "structure of arrays": element e of cell c is at [e * ncell + c].
+ *  - Packed upper triangle of an nbeam x nbeam symmetric matrix, a <= b:
+ *        pair(a, b) = a * nbeam - a * (a - 1) / 2 + (b - a),
+ *    npair = nbeam * (nbeam + 1) / 2.
+ */
+#ifndef RFI_H
+#define RFI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rfi_status;
+enum {
+  RFI_OK = 0,
+  RFI_E_INVALID = -1,    /* bad argument (message in rfi_last_error) */
+  RFI_E_OVERFLOW = -2,   /* sums would leave the exact int32 range */
+  RFI_E_NOMEM = -3,      /* device or host allocation failed */
+  RFI_E_BUDGET = -4,     /* block larger than the session's HBM budget */
+  RFI_E_DEVICE = -5,     /* HIP runtime error */
+  RFI_E_NOT_READY = -6,  /* result not yet available */
+  RFI_E_CANCELLED = -7,  /* request cancelled before it ran */
+  RFI_E_TIMEOUT = -8     /* wait timed out */
+};
+
+/* per-cell status bits (uint8) */
+enum {
+  RFI_CELL_DEGENERATE = 1,     /* a beam has zero variance in the cell */
+  RFI_CELL_NOT_CONVERGED = 2,  /* Jacobi still rotating after max_sweeps */
+  RFI_CELL_PROTECTED = 4,      /* channel preserved by the caller */
+  RFI_CELL_REFINE_FAILED = 8,  /* FP64 refinement fell back to the FP32 value */
+  RFI_CELL_BAD_COUNT = 16      /* fewer than 2 or more than RFI_MAX_COUNT samples */
+};
+
+typedef void* rfi_stream_t;            /* hipStream_t */
+
+#define RFI_MAX_BEAMS 79
+/* Largest number of samples a cell may accumulate: 255^2 * count < 2^31. */
+#define RFI_MAX_COUNT 33025
+
+/* One observation block (Sec. 2 data layout): per beam, a time-major
+ * filterbank of uint8 total power, channels contiguous within a time row.
+ * beam[b] points to beam b's [nsamp][row_stride] bytes. row_stride >= nchan
+ * and a multiple of 16; every beam[b] 16-byte aligned. Bytes of a row past
+ * nchan are read but never used. Pointers are device pointers held in this
+ * host struct. */
+typedef struct {
+  int32_t nbeam;                 /* 2 .. RFI_MAX_BEAMS */
+  int32_t nchan;                 /* >= 1 */
+  int64_t nsamp;                 /* time rows in the block */
+  int64_t row_stride;            /* bytes between consecutive time rows */
+  const uint8_t* beam[RFI_MAX_BEAMS];
+} rfi_block;
+
+enum { RFI_CCM_AUTO = 0, RFI_CCM_MFMA = 1, RFI_CCM_VALU = 2 };
+
+/* Per-cell sums of Eq. 1 (Sec. 3.2) for sub-intervals [t0 + kL, t0 + (k+1)L),
+ * k < nsub, of every channel:
+ *     sum_x [b][cell]        = sum_t x_b(t)                (nbeam rows)
+ *     sum_xy[pair(a,b)][cell] = sum_t x_a(t) x_b(t), a <= b (npair rows)
+ *     count [k]              = samples accumulated into sub-interval k
+ * exact in int32. accumulate = 0 overwrites the outputs; 1 adds into them
+ * (a sub-interval spanning two blocks is accumulated in two calls; the
+ * caller keeps the accumulated count <= RFI_MAX_COUNT). variant selects the
+ * engine: int8 MFMA on x - 128 (exact: the offset is removed again in
+ * integer arithmetic) or plain VALU dot products (nbeam <= 20 only).
+ * Errors: RFI_E_INVALID for bad shapes or alignment, t0 + nsub*L > nsamp,
+ * L < 1; RFI_E_OVERFLOW for L > RFI_MAX_COUNT. */
+rfi_status rfi_ccm_accumulate(const rfi_block* blk /* host */, int64_t t0, int32_t L,
+                              int32_t nsub, int32_t* sum_x, int32_t* sum_xy,
+                              int32_t* count, int32_t accumulate, int32_t variant,
+                              rfi_stream_t stream);
+
+/* Eigen solver selection */
+enum { RFI_EIG_AUTO = 0, RFI_EIG_LANE = 1, RFI_EIG_WAVE = 2 };
+
+typedef struct {
+  int32_t precision;     /* 32: FP32 Jacobi (default); 64: FP64 Jacobi */
+  int32_t max_sweeps;    /* cyclic Jacobi sweep cap, 1..30 (default 12) */
+  int32_t refine;        /* 1: lambda_1 by an FP64 Rayleigh quotient (default) */
+  int32_t solver;        /* RFI_EIG_AUTO | _LANE (nbeam <= 20, FP32) | _WAVE */
+} rfi_eig_params;
+
+/* Per cell (Sec. 3.2-3.3): the Pearson correlation matrix
+ *     r_ab = N_ab / sqrt(N_aa N_bb),  N_ab = count * S_ab - S_a S_b
+ * (N exact in int64, r in FP64; a beam with N_aa = 0 gets r_ab = 0 off the
+ * diagonal and the cell RFI_CELL_DEGENERATE), its eigenvalues by cyclic
+ * Jacobi (eps-relative skip rule, stop after a sweep without rotations or
+ * max_sweeps), and
+ *     stat[cell] = lambda_1^2 / ||r||_F^2         (FP64)
+ * with lambda_1 the eigenvalue of largest magnitude, refined in FP64 by the
+ * Rayleigh quotient of its eigenvector when p->refine. Optional outputs
+ * (NULL = not computed): eigvals[i][cell] (FP32, |lambda| descending) and
+ * v1[b][cell] (FP32 unit dominant eigenvector, sign: sum_b v1_b >= 0).
+ * status[cell] gets RFI_CELL_* bits. Inputs are the outputs of
+ * rfi_ccm_accumulate for the same nbeam, nsub, nchan. p may be NULL
+ * (defaults). */
+rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan,
+                           const int32_t* sum_x, const int32_t* sum_xy,
+                           const int32_t* count, const rfi_eig_params* p /* host */,
+                           float* eigvals, double* stat, float* v1, uint8_t* status,
+                           rfi_stream_t stream);
+
+/* Clip summary written by rfi_flag (device struct). */
+typedef struct {
+  double mu, sigma, thr;   /* last fit: mean, population sigma, mu + kappa sigma */
+  int32_t iterations;      /* fits computed */
+  int32_t converged;       /* 1 if the last fit masked nothing new */
+  int64_t nflag;           /* cells masked */
+  int64_t nfit;            /* eligible cells left unmasked (this block) */
+} rfi_flag_stats;
+
+#define RFI_HIST_CAP 1024
+typedef struct {
+  double mu, sigma, thr;
+  int32_t iterations, converged;
+} rfi_hist_entry;
+
+/* Per-stream pooled clip state (device struct, zero-initialise to start a
+ * stream). Exact sums over every unmasked cell of the stream's earlier
+ * blocks: n, q1 = sum q, q2 = sum q^2 with q = rint(stat * 2^40), 128-bit
+ * little-endian limbs; and the ring of the last RFI_HIST_CAP fits. */
+typedef struct {
+  int64_t n;
+  uint64_t q1[2];
+  uint64_t q2[2];
+  int64_t nblocks;
+  rfi_hist_entry hist[RFI_HIST_CAP];
+} rfi_stream_state;
+
+/* Iterative one-sided Gaussian clip of stat over the nsub x nchan cells
+ * (Sec. 3.3; kappa of Sec. 4.5; preserved ranges of Sec. 4.3). Eligible
+ * cells: status without RFI_CELL_DEGENERATE / RFI_CELL_BAD_COUNT and channel
+ * not protected (protect_chan[j] != 0; NULL = none). On the statistic
+ * quantised to q = rint(stat * 2^40): mu = Q1 / (N 2^40),
+ * sigma^2 = (N Q2 - Q1^2) / (N^2 2^80) from exact integer sums over the
+ * eligible unmasked cells (pooled with *state when state != NULL), mask
+ * every such cell with q * 2^-40 > mu + kappa sigma, repeat until a fit masks
+ * nothing new or max_iter fits. mask[cell] = 1 for masked cells, else 0. If
+ * state != NULL the block's final unmasked sums are folded into it and the
+ * fit appended to its history. out (nullable) receives the summary.
+ * Errors: RFI_E_INVALID for bad sizes, kappa < 0 or max_iter < 1. */
+rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8_t* status,
+                    const uint8_t* protect_chan, double kappa, int32_t max_iter,
+                    rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
+                    rfi_stream_t stream);
+
+/* Per-beam eigenvector stage (Sec. 3.3 last paragraph; kappa_v of Sec. 4.5):
+ * for each beam b, mu_b and sigma_b (population) of |v1_b| over eligible
+ * unmasked cells; beam_mask[b][cell] = mask[cell] && |v1_b| > mu_b +
+ * kappa_v sigma_b. Eligibility as in rfi_flag. beam_mu / beam_sigma
+ * (nullable, [nbeam] FP64) receive the fits. */
+rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const float* v1,
+                           const uint8_t* mask, const uint8_t* status,
+                           const uint8_t* protect_chan, double kappa_v,
+                           uint8_t* beam_mask, double* beam_mu, double* beam_sigma,
+                           rfi_stream_t stream);
+
+/* Message for the last error returned on the calling thread ("" if none). */
+const char* rfi_last_error(void);
+
+/* Library version string. */
+const char* rfi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFI_H */

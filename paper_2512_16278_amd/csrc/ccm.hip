@@ -1,0 +1,376 @@
+// Per-cell exact sums of Eq. 1 (Sec. 3.2): S_a = sum_t x_a(t) and
+// S_ab = sum_t x_a(t) x_b(t), a <= b, for every (sub-interval, channel) cell.
+//
+// Main engine (ccm_mfma_kernel): the cell's beams x time samples form a small
+// integer matrix X and the sums are X X^T, a dense contraction over time. The
+// kernel feeds it to the int8 matrix cores (v_mfma_i32_16x16x32_i8) on
+// x' = x - 128 (a byte XOR with 0x80), which is exact; the offset is removed
+// again in integer arithmetic:
+//     S_a  = S'_a + 128 L
+//     S_ab = S'_ab + 128 (S'_a + S'_b) + 16384 L.
+// S'_a comes out of the same products: one padding row of X is all ones.
+//
+// Data path: a workgroup owns CW consecutive channels of one sub-interval and
+// walks its L samples in chunks of 32 rows. Each chunk of every beam
+// (32 rows x CW channel bytes, coalesced 16-byte loads) is staged in LDS, two
+// chunks deep, with the next chunk's global loads in flight while the current
+// one is consumed. A wave reads the rows of its channels back from LDS as
+// dwords (4 channels x 1 time), transposes 4x4 bytes in registers (v_perm) to
+// time-packed operands, and issues one MFMA per (channel, 16x16 beam block
+// pair). Workgroups whose channel tiles share 128-byte lines are dispatched
+// to the same XCD (same L2).
+//
+// Comparison engine (ccm_valu_kernel, nbeam <= 20): one lane per channel, all
+// pair accumulators in registers, four samples per v_dot4_u32_u8.
+#include "internal.h"
+
+namespace rfi {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int TC = 32;              // rows per chunk = K of one MFMA
+constexpr uint32_t OFFSET_XOR = 0x80808080u;
+
+__device__ __forceinline__ void transpose4x4(uint32_t r0, uint32_t r1, uint32_t r2, uint32_t r3,
+                                             uint32_t& o0, uint32_t& o1, uint32_t& o2,
+                                             uint32_t& o3) {
+  // rows r_i hold bytes (channel 0..3) of time i; o_c holds bytes (time 0..3)
+  // of channel c.
+  uint32_t t0 = __builtin_amdgcn_perm(r1, r0, 0x05010400u);
+  uint32_t t1 = __builtin_amdgcn_perm(r3, r2, 0x05010400u);
+  uint32_t t2 = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
+  uint32_t t3 = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+  o0 = __builtin_amdgcn_perm(t1, t0, 0x05040100u);
+  o1 = __builtin_amdgcn_perm(t1, t0, 0x07060302u);
+  o2 = __builtin_amdgcn_perm(t3, t2, 0x05040100u);
+  o3 = __builtin_amdgcn_perm(t3, t2, 0x07060302u);
+}
+
+__device__ __forceinline__ int block_pair(int b1, int b2, int nb) {
+  // index of (b1 <= b2) in row-major upper-triangle order of nb blocks
+  return b1 * nb - b1 * (b1 - 1) / 2 + (b2 - b1);
+}
+
+template <int NB, int CW, int CPW>
+struct MfmaCfg {
+  static constexpr int NBP = NB * (NB + 1) / 2;        // 16x16 block pairs
+  static constexpr int NWAVE = CW / CPW;
+  static constexpr int NTHR = 64 * NWAVE;
+  static constexpr int SEGS = CW / 16;                 // 16-byte segments per row
+  static constexpr int PLANE = TC * CW + 16;           // LDS bytes per beam and chunk
+  static constexpr int MAXBEAM = 16 * NB - 1;
+  static constexpr int NLOAD = (MAXBEAM * TC * SEGS + NTHR - 1) / NTHR;
+  static constexpr int NGRP = CPW >= 4 ? CPW / 4 : 1;  // dword groups of 4 channels
+};
+
+template <int NB, int CW, int CPW>
+__global__ __launch_bounds__((MfmaCfg<NB, CW, CPW>::NTHR), 1) void ccm_mfma_kernel(
+    BeamPtrs bp, int nbeam, int nchan, int64_t row_stride, int64_t t0, int L, int nsub,
+    int nct, int32_t* __restrict__ sum_x, int32_t* __restrict__ sum_xy,
+    int32_t* __restrict__ count, int accumulate) {
+  using C = MfmaCfg<NB, CW, CPW>;
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+
+  // workgroup -> tile, grouping the tiles that share 128-byte lines on one XCD
+  const int ntiles = nsub * nct;
+  int w = blockIdx.x;
+  constexpr int G = 128 / CW;
+  const int full = (ntiles / (8 * G)) * (8 * G);
+  int tile = w;
+  if (w < full) {
+    const int u = w / (8 * G), rem = w % (8 * G);
+    const int h = rem / 8, x = rem % 8;
+    tile = G * (8 * u + x) + h;
+  }
+  const int k = tile / nct;
+  const int c0 = (tile % nct) * CW;
+  const int64_t ncell = (int64_t)nsub * nchan;
+  const int64_t row0 = t0 + (int64_t)k * L;
+  const int nchunk = (L + TC - 1) / TC;
+  const int bufbytes = nbeam * C::PLANE;
+
+  v4i acc[CPW][C::NBP];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c)
+#pragma unroll
+    for (int p = 0; p < C::NBP; ++p) acc[c][p] = v4i{0, 0, 0, 0};
+
+  // slot i of this thread covers (beam, row, 16-byte segment) of a chunk
+  const uint8_t* const* beam_tab = (const uint8_t* const*)__builtin_amdgcn_kernarg_segment_ptr();
+  uint4 stage[C::NLOAD];
+#pragma unroll
+  for (int i = 0; i < C::NLOAD; ++i) stage[i] = uint4{0, 0, 0, 0};
+  const int li = lane & 15;     // row (beam) within a 16-row block
+  const int kg = lane >> 4;     // which 8 of the chunk's 32 rows this lane supplies
+  const int cb = wave * CPW;    // first channel of this wave within the tile
+
+  auto compute_chunk = [&](int buf, int rows) {
+    const uint8_t* src = lds + buf * bufbytes;
+#pragma unroll
+    for (int grp = 0; grp < C::NGRP; ++grp) {
+      const int ch4 = (CPW >= 4) ? (cb + 4 * grp) : (cb & ~3);
+      long op[NB][4];
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) {
+        const int beam = 16 * bb + li;
+        uint32_t r[8];
+        if (beam < nbeam) {
+          const uint8_t* p = src + beam * C::PLANE + (8 * kg) * CW + ch4;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) r[j] = *(const uint32_t*)(p + j * CW) ^ OFFSET_XOR;
+        } else {
+          const uint32_t v = (beam == nbeam) ? 0x01010101u : 0u;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) r[j] = v;
+        }
+        if (rows < TC) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (8 * kg + j >= rows) r[j] = 0;
+        }
+        uint32_t o[8];
+        transpose4x4(r[0], r[1], r[2], r[3], o[0], o[1], o[2], o[3]);
+        transpose4x4(r[4], r[5], r[6], r[7], o[4], o[5], o[6], o[7]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          op[bb][c] = (long)(((uint64_t)o[4 + c] << 32) | (uint64_t)o[c]);
+      }
+      if constexpr (CPW >= 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int slot = 4 * grp + c;
+#pragma unroll
+          for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+            for (int b2 = b1; b2 < NB; ++b2) {
+              const int p = block_pair(b1, b2, NB);
+              acc[slot][p] = __builtin_amdgcn_mfma_i32_16x16x32_i8(op[b1][c], op[b2][c],
+                                                                   acc[slot][p], 0, 0, 0);
+            }
+        }
+      } else {
+        // this wave owns channels (cb & 3) .. (cb & 3) + CPW - 1 of the dword
+        const int coff = cb & 3;
+#pragma unroll
+        for (int slot = 0; slot < CPW; ++slot) {
+          const int c = coff + slot;                 // wave-uniform
+          long sel[NB];
+#pragma unroll
+          for (int bb = 0; bb < NB; ++bb)
+            sel[bb] = c == 0 ? op[bb][0] : c == 1 ? op[bb][1] : c == 2 ? op[bb][2] : op[bb][3];
+#pragma unroll
+          for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+            for (int b2 = b1; b2 < NB; ++b2) {
+              const int p = block_pair(b1, b2, NB);
+              acc[slot][p] = __builtin_amdgcn_mfma_i32_16x16x32_i8(sel[b1], sel[b2],
+                                                                   acc[slot][p], 0, 0, 0);
+            }
+        }
+      }
+    }
+  };
+
+  for (int chunk = -1; chunk < nchunk; ++chunk) {
+    const int next = chunk + 1;
+    if (next < nchunk) {
+      const int rows = min(TC, L - next * TC);
+#pragma unroll
+      for (int i = 0; i < C::NLOAD; ++i) {
+        const int s = tid + i * C::NTHR;
+        const int g = s % C::SEGS;
+        const int r = (s / C::SEGS) % TC;
+        const int b = s / (C::SEGS * TC);
+        const int64_t col = c0 + 16 * g;
+        if (b < nbeam && r < rows && col < row_stride) {
+          const uint8_t* src = beam_tab[b] + (row0 + (int64_t)next * TC + r) * row_stride + col;
+          stage[i] = *(const uint4*)src;
+        }
+      }
+    }
+    if (chunk >= 0) compute_chunk(chunk & 1, min(TC, L - chunk * TC));
+    if (next < nchunk) {
+      uint8_t* dst = lds + (next & 1) * bufbytes;
+#pragma unroll
+      for (int i = 0; i < C::NLOAD; ++i) {
+        const int s = tid + i * C::NTHR;
+        const int g = s % C::SEGS;
+        const int r = (s / C::SEGS) % TC;
+        const int b = s / (C::SEGS * TC);
+        if (b < nbeam) *(uint4*)(dst + b * C::PLANE + r * CW + 16 * g) = stage[i];
+      }
+    }
+    __syncthreads();
+  }
+
+  // Epilogue: offset sums S'_a sit in the ones column; share them through LDS,
+  // then every lane converts its entries to raw sums and stores them.
+  int32_t* sxl = (int32_t*)lds;                      // [nbeam][CW]
+  const int jn = nbeam & 15, bn = nbeam >> 4;
+  if (li == jn) {
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+      for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+        for (int b2 = b1; b2 < NB; ++b2) {
+          if (b2 != bn) continue;
+          const int p = block_pair(b1, b2, NB);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int a = 16 * b1 + 4 * kg + r;
+            if (a < nbeam) sxl[a * CW + cb + c] = acc[c][p][r];
+          }
+        }
+  }
+  __syncthreads();
+  const uint32_t cnt = (uint32_t)L;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int chl = cb + c;
+    const int chan = c0 + chl;
+    if (chan >= nchan) continue;
+    const int64_t cell = (int64_t)k * nchan + chan;
+#pragma unroll
+    for (int b1 = 0; b1 < NB; ++b1)
+#pragma unroll
+      for (int b2 = b1; b2 < NB; ++b2) {
+        const int p = block_pair(b1, b2, NB);
+        const int b = 16 * b2 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 16 * b1 + 4 * kg + r;
+          const uint32_t v = (uint32_t)acc[c][p][r];
+          if (a <= b && b < nbeam) {
+            const uint32_t raw = v + 128u * ((uint32_t)sxl[a * CW + chl] + (uint32_t)sxl[b * CW + chl]) +
+                                 16384u * cnt;
+            const int64_t idx = (int64_t)a * nbeam - (int64_t)a * (a - 1) / 2 + (b - a);
+            int32_t* dst = sum_xy + idx * ncell + cell;
+            *dst = accumulate ? (int32_t)((uint32_t)*dst + raw) : (int32_t)raw;
+          } else if (b == nbeam && a < nbeam) {
+            const uint32_t raw = v + 128u * cnt;
+            int32_t* dst = sum_x + (int64_t)a * ncell + cell;
+            *dst = accumulate ? (int32_t)((uint32_t)*dst + raw) : (int32_t)raw;
+          }
+        }
+      }
+  }
+  if (c0 == 0 && tid == 0) count[k] = accumulate ? count[k] + L : L;
+}
+
+template <int NB, int CW, int CPW>
+hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
+                           int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
+                           int32_t* count, int accumulate, hipStream_t s) {
+  using C = MfmaCfg<NB, CW, CPW>;
+  const int nct = (nchan + CW - 1) / CW;
+  const size_t lds = 2 * (size_t)nbeam * C::PLANE;
+  const size_t epi = (size_t)nbeam * CW * 4;
+  const size_t shm = lds > epi ? lds : epi;
+  const auto kern = ccm_mfma_kernel<NB, CW, CPW>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e != hipSuccess) return e;
+  const int64_t ntiles = (int64_t)nsub * nct;
+  hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), shm, s, bp, nbeam, nchan,
+                     row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// VALU comparison engine: one lane per channel, nbeam <= 20.
+constexpr int VN = 20;
+constexpr int VNP = VN * (VN + 1) / 2;
+
+__global__ __launch_bounds__(256) void ccm_valu_kernel(BeamPtrs bp, int nbeam, int nchan,
+                                                       int64_t row_stride, int64_t t0, int L,
+                                                       int nsub, int32_t* __restrict__ sum_x,
+                                                       int32_t* __restrict__ sum_xy,
+                                                       int32_t* __restrict__ count,
+                                                       int accumulate) {
+  const int chan = blockIdx.x * 256 + threadIdx.x;
+  const int k = blockIdx.y;
+  if (blockIdx.x == 0 && threadIdx.x == 0) count[k] = accumulate ? count[k] + L : L;
+  if (chan >= nchan) return;
+  const int64_t row0 = t0 + (int64_t)k * L;
+  uint32_t acc[VNP];
+  uint32_t sx[VN];
+#pragma unroll
+  for (int i = 0; i < VNP; ++i) acc[i] = 0;
+#pragma unroll
+  for (int i = 0; i < VN; ++i) sx[i] = 0;
+  for (int t = 0; t < L; t += 4) {
+    uint32_t x[VN];
+#pragma unroll
+    for (int b = 0; b < VN; ++b) {
+      uint32_t v = 0;
+      if (b < nbeam) {
+        const uint8_t* p = bp.p[b] + (row0 + t) * row_stride + chan;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (t + i < L) v |= (uint32_t)p[i * row_stride] << (8 * i);
+      }
+      x[b] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < VN; ++a) {
+      sx[a] = __builtin_amdgcn_udot4(x[a], 0x01010101u, sx[a], false);
+#pragma unroll
+      for (int b = a; b < VN; ++b) {
+        const int idx = a * VN - a * (a - 1) / 2 + (b - a);
+        acc[idx] = __builtin_amdgcn_udot4(x[a], x[b], acc[idx], false);
+      }
+    }
+  }
+  const int64_t ncell = (int64_t)nsub * nchan;
+  const int64_t cell = (int64_t)k * nchan + chan;
+#pragma unroll
+  for (int a = 0; a < VN; ++a) {
+    if (a >= nbeam) continue;
+    int32_t* d = sum_x + a * ncell + cell;
+    *d = accumulate ? (int32_t)((uint32_t)*d + sx[a]) : (int32_t)sx[a];
+#pragma unroll
+    for (int b = a; b < VN; ++b) {
+      if (b >= nbeam) continue;
+      const int idx = a * VN - a * (a - 1) / 2 + (b - a);
+      const int64_t out = (int64_t)a * nbeam - (int64_t)a * (a - 1) / 2 + (b - a);
+      int32_t* q = sum_xy + out * ncell + cell;
+      *q = accumulate ? (int32_t)((uint32_t)*q + acc[idx]) : (int32_t)acc[idx];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
+                           int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
+                           int32_t* count, int accumulate, hipStream_t s) {
+  const int nb = (nbeam + 1 + 15) / 16;   // 16-row blocks incl. the ones row
+#define RFI_CCM(NB, CW, CPW) \
+  launch_mfma_cfg<NB, CW, CPW>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, sum_xy, count, accumulate, s)
+  switch (nb) {
+    case 1: return RFI_CCM(1, 64, 8);
+    case 2: return RFI_CCM(2, 64, 8);
+    case 3: return RFI_CCM(3, 32, 4);
+    case 4: return RFI_CCM(4, 16, 2);
+    case 5: return RFI_CCM(5, 16, 2);
+    default: return hipErrorInvalidValue;
+  }
+#undef RFI_CCM
+}
+
+hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
+                           int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
+                           int32_t* count, int accumulate, hipStream_t s) {
+  if (nbeam > VN) return hipErrorInvalidValue;
+  dim3 grid((nchan + 255) / 256, nsub);
+  hipLaunchKernelGGL(ccm_valu_kernel, grid, dim3(256), 0, s, bp, nbeam, nchan, row_stride, t0,
+                     L, nsub, sum_x, sum_xy, count, accumulate);
+  return hipGetLastError();
+}
+
+}  // namespace rfi

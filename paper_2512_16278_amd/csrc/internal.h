@@ -1,0 +1,50 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rfi.h"
+
+namespace rfi {
+
+// Device pointers of a block's beams, passed to kernels by value.
+struct BeamPtrs {
+  const uint8_t* p[RFI_MAX_BEAMS];
+};
+
+inline int npair_of(int n) { return n * (n + 1) / 2; }
+
+// Kernel launchers (return a HIP error code; arguments already validated).
+hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
+                           int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
+                           int32_t* count, int accumulate, hipStream_t s);
+hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
+                           int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
+                           int32_t* count, int accumulate, hipStream_t s);
+
+struct EigArgs {
+  int nbeam, nsub, nchan;
+  const int32_t* sum_x;
+  const int32_t* sum_xy;
+  const int32_t* count;
+  int max_sweeps, refine;
+  float* eigvals;
+  double* stat;
+  float* v1;
+  uint8_t* status;
+};
+hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s);       // FP32, nbeam <= 20
+hipError_t launch_eig_wave(const EigArgs& a, int precision, hipStream_t s);  // any nbeam
+
+hipError_t launch_flag(int nsub, int nchan, const double* stat, const uint8_t* status,
+                       const uint8_t* protect_chan, double kappa, int max_iter,
+                       rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
+                       hipStream_t s);
+hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float* v1,
+                              const uint8_t* mask, const uint8_t* status,
+                              const uint8_t* protect_chan, double kappa_v,
+                              uint8_t* beam_mask, double* beam_mu, double* beam_sigma,
+                              hipStream_t s);
+
+}  // namespace rfi

@@ -1,0 +1,231 @@
+"""Thin ctypes binding of librfi (include/rfi.h) and librfi_synth (include/rfi_synth.h).
+
+Argument marshalling only: every step runs in the HIP library. Tensors are
+PyTorch device tensors (used for device memory and streams); their data
+pointers and the current HIP stream are passed straight through the C ABI.
+Loading fails loudly if the built library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+RFI_OK = 0
+RFI_E_INVALID, RFI_E_OVERFLOW, RFI_E_NOMEM, RFI_E_BUDGET = -1, -2, -3, -4
+RFI_E_DEVICE, RFI_E_NOT_READY, RFI_E_CANCELLED, RFI_E_TIMEOUT = -5, -6, -7, -8
+RFI_CELL_DEGENERATE, RFI_CELL_NOT_CONVERGED, RFI_CELL_PROTECTED = 1, 2, 4
+RFI_CELL_REFINE_FAILED, RFI_CELL_BAD_COUNT = 8, 16
+RFI_MAX_BEAMS = 79
+RFI_MAX_COUNT = 33025
+RFI_HIST_CAP = 1024
+RFI_CCM_AUTO, RFI_CCM_MFMA, RFI_CCM_VALU = 0, 1, 2
+RFI_EIG_AUTO, RFI_EIG_LANE, RFI_EIG_WAVE = 0, 1, 2
+
+
+class RfiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librfi error {code}: {msg}")
+        self.code = code
+
+
+class rfi_block(C.Structure):
+    _fields_ = [("nbeam", C.c_int32), ("nchan", C.c_int32), ("nsamp", C.c_int64),
+                ("row_stride", C.c_int64), ("beam", C.c_void_p * RFI_MAX_BEAMS)]
+
+
+class rfi_eig_params(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_sweeps", C.c_int32), ("refine", C.c_int32),
+                ("solver", C.c_int32)]
+
+
+class rfi_flag_stats(C.Structure):
+    _fields_ = [("mu", C.c_double), ("sigma", C.c_double), ("thr", C.c_double),
+                ("iterations", C.c_int32), ("converged", C.c_int32), ("nflag", C.c_int64),
+                ("nfit", C.c_int64)]
+
+
+class rfi_hist_entry(C.Structure):
+    _fields_ = [("mu", C.c_double), ("sigma", C.c_double), ("thr", C.c_double),
+                ("iterations", C.c_int32), ("converged", C.c_int32)]
+
+
+class rfi_stream_state(C.Structure):
+    _fields_ = [("n", C.c_int64), ("q1", C.c_uint64 * 2), ("q2", C.c_uint64 * 2),
+                ("nblocks", C.c_int64), ("hist", rfi_hist_entry * RFI_HIST_CAP)]
+
+
+class rfi_synth_spec(C.Structure):
+    _fields_ = [("nbeam", C.c_int32), ("nchan", C.c_int32), ("nsamp", C.c_int64),
+                ("row_stride", C.c_int64), ("key0", C.c_uint32), ("key1", C.c_uint32),
+                ("cdf", C.c_void_p), ("sin_of_chan", C.c_void_p), ("sin_meta", C.c_void_p),
+                ("sin_tab", C.c_void_p), ("sin_gain", C.c_void_p), ("pmax", C.c_int32),
+                ("nburst", C.c_int32), ("burst_meta", C.c_void_p), ("burst_amp", C.c_void_p),
+                ("npulse", C.c_int32), ("pulse_meta", C.c_void_p), ("pulse_delay", C.c_void_p)]
+
+
+_LIB = None
+_SYN = None
+
+
+def lib_path(name: str = "librfi.so") -> str:
+    return os.path.join(PKG, name)
+
+
+def _load(name):
+    path = lib_path(name)
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() "
+                           f"(python -c 'import __graft_entry__ as g; g.build()')")
+    return C.CDLL(path)
+
+
+def lib():
+    """The loaded librfi (ctypes.CDLL), with argument types declared."""
+    global _LIB
+    if _LIB is None:
+        L = _load("librfi.so")
+        vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.rfi_ccm_accumulate.argtypes = [C.POINTER(rfi_block), i64, i32, i32, vp, vp, vp, i32, i32, vp]
+        L.rfi_eig_batched.argtypes = [i32, i32, i32, vp, vp, vp, C.POINTER(rfi_eig_params),
+                                      vp, vp, vp, vp, vp]
+        L.rfi_flag.argtypes = [i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
+        L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
+        for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_eigvec_flag"):
+            getattr(L, f).restype = i32
+        L.rfi_last_error.restype = C.c_char_p
+        L.rfi_version.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def synth_lib():
+    global _SYN
+    if _SYN is None:
+        S = _load("librfi_synth.so")
+        S.rfi_synth_fill.argtypes = [C.POINTER(rfi_synth_spec), C.c_int32, C.c_int64, C.c_int64,
+                                     C.c_void_p, C.c_void_p]
+        S.rfi_synth_fill.restype = C.c_int32
+        _SYN = S
+    return _SYN
+
+
+def _check(code):
+    if code != RFI_OK:
+        raise RfiError(code, lib().rfi_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_block(data, nchan=None) -> rfi_block:
+    """rfi_block for a device uint8 tensor [nbeam, nsamp, row_stride] (or a
+    list of per-beam [nsamp, row_stride] tensors) holding nchan channels per
+    row (default: the whole row)."""
+    blk = rfi_block()
+    beams = list(data) if isinstance(data, (list, tuple)) else [data[b] for b in range(data.shape[0])]
+    blk.nbeam = len(beams)
+    blk.nsamp = beams[0].shape[0]
+    blk.row_stride = beams[0].stride(0)
+    blk.nchan = beams[0].shape[1] if nchan is None else int(nchan)
+    for b, t in enumerate(beams):
+        blk.beam[b] = t.data_ptr()
+    return blk
+
+
+def rfi_ccm_accumulate(blk: rfi_block, t0, L, nsub, sum_x, sum_xy, count, accumulate=0,
+                       variant=RFI_CCM_AUTO, stream=None):
+    _check(lib().rfi_ccm_accumulate(C.byref(blk), int(t0), int(L), int(nsub), _ptr(sum_x),
+                                    _ptr(sum_xy), _ptr(count), int(accumulate), int(variant),
+                                    _stream(stream)))
+
+
+def rfi_eig_batched(nbeam, nsub, nchan, sum_x, sum_xy, count, stat, status, eigvals=None,
+                    v1=None, precision=32, max_sweeps=12, refine=1, solver=RFI_EIG_AUTO,
+                    stream=None):
+    p = rfi_eig_params(precision, max_sweeps, refine, solver)
+    _check(lib().rfi_eig_batched(int(nbeam), int(nsub), int(nchan), _ptr(sum_x), _ptr(sum_xy),
+                                 _ptr(count), C.byref(p), _ptr(eigvals), _ptr(stat), _ptr(v1),
+                                 _ptr(status), _stream(stream)))
+
+
+def rfi_flag(nsub, nchan, stat, status, mask, protect_chan=None, kappa=3.0, max_iter=50,
+             state=None, out=None, stream=None):
+    _check(lib().rfi_flag(int(nsub), int(nchan), _ptr(stat), _ptr(status), _ptr(protect_chan),
+                          float(kappa), int(max_iter), _ptr(state), _ptr(mask), _ptr(out),
+                          _stream(stream)))
+
+
+def rfi_eigvec_flag(nbeam, nsub, nchan, v1, mask, status, beam_mask, protect_chan=None,
+                    kappa_v=1.0, beam_mu=None, beam_sigma=None, stream=None):
+    _check(lib().rfi_eigvec_flag(int(nbeam), int(nsub), int(nchan), _ptr(v1), _ptr(mask),
+                                 _ptr(status), _ptr(protect_chan), float(kappa_v), _ptr(beam_mask),
+                                 _ptr(beam_mu), _ptr(beam_sigma), _stream(stream)))
+
+
+def flag_stats_from_bytes(raw: bytes) -> dict:
+    s = rfi_flag_stats.from_buffer_copy(raw)
+    return dict(mu=s.mu, sigma=s.sigma, thr=s.thr, iterations=s.iterations,
+                converged=s.converged, nflag=s.nflag, nfit=s.nfit)
+
+
+def stream_state_from_bytes(raw: bytes) -> rfi_stream_state:
+    return rfi_stream_state.from_buffer_copy(raw)
+
+
+# --- GPU input generator -----------------------------------------------------
+
+class DeviceSynth:
+    """Device copies of a SynthSpec's integer tables and rfi_synth_fill calls."""
+
+    def __init__(self, spec, device="cuda"):
+        import torch
+        from . import synth as _s
+        tabs = _s.device_tables(spec)
+        self.spec = spec
+        self._keep = {}
+
+        def dev(a, dtype):
+            t = torch.from_numpy(np.ascontiguousarray(a).astype(dtype)).to(device)
+            self._keep[id(t)] = t
+            return t
+
+        cdf = dev(tabs["cdf"].astype(np.uint32).view(np.int32), np.int32)
+        self.c = rfi_synth_spec()
+        c = self.c
+        c.nbeam, c.nchan, c.nsamp = spec.nbeam, spec.nchan, spec.nsamp
+        c.key0, c.key1 = spec.key
+        c.cdf = cdf.data_ptr()
+        c.sin_of_chan = dev(tabs["sin_of_chan"], np.int32).data_ptr()
+        c.sin_meta = dev(tabs["sin_meta"], np.int64).data_ptr()
+        c.sin_tab = dev(tabs["sin_tab"], np.int32).data_ptr()
+        c.sin_gain = dev(tabs["sin_gain"], np.int32).data_ptr()
+        c.pmax = int(tabs["pmax"])
+        c.nburst = int(tabs["nburst"])
+        c.burst_meta = dev(tabs["burst_meta"], np.int64).data_ptr()
+        c.burst_amp = dev(tabs["burst_amp"], np.int32).data_ptr()
+        c.npulse = int(tabs["npulse"])
+        c.pulse_meta = dev(tabs["pulse_meta"], np.int64).data_ptr()
+        c.pulse_delay = dev(tabs["pulse_delay"], np.int32).data_ptr()
+
+    def fill(self, beam_tensor, beam, t_lo=0, t_hi=None, stream=None):
+        """Write rows [t_lo, t_hi) of `beam` into beam_tensor[t_lo:t_hi] (a
+        device uint8 [nsamp, row_stride] tensor)."""
+        t_hi = self.spec.nsamp if t_hi is None else t_hi
+        self.c.row_stride = beam_tensor.stride(0)
+        dst = beam_tensor.data_ptr() + t_lo * beam_tensor.stride(0)
+        r = synth_lib().rfi_synth_fill(C.byref(self.c), int(beam), int(t_lo), int(t_hi),
+                                       C.c_void_p(dst), _stream(stream))
+        if r != 0:
+            raise RuntimeError(f"rfi_synth_fill failed ({r})")
