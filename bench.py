@@ -33,15 +33,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(spec, nsub_sample: int):
-    """The FP64 oracle, as it stands, on a bounded sample: every channel of
-    the first nsub_sample sub-intervals (bytes regenerated on the CPU)."""
+def cpu_baseline(spec, nsub_sample: int, nchan_sample: int):
+    """The FP64 oracle, as it stands, on a bounded sample: the first
+    nchan_sample channels of the first nsub_sample sub-intervals (bytes
+    regenerated on the CPU)."""
     from oracle import pipeline
     from paper_2512_16278_amd import synth
     L = spec.L
     t0 = time.perf_counter()
-    x = synth.generate(spec, 0, nsub_sample * L)
+    x = synth.generate(spec, 0, nsub_sample * L, 0, nchan_sample)
     tgen = time.perf_counter() - t0
+    log(f"cpu baseline: sample generated in {tgen:.1f} s; running the oracle")
     t0 = time.perf_counter()
     cr, res, _ = pipeline.block(x, L, nsub_sample)
     dt = time.perf_counter() - t0
@@ -54,8 +56,8 @@ def cpu_baseline(spec, nsub_sample: int):
         cores = os.cpu_count() or 1
     return {
         "value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(cores), "kind": "oracle",
-        "sample": f"all {spec.nchan} channels x {nsub_sample} sub-ints of {L} samples x "
-                  f"{spec.nbeam} beams ({nbytes / 1e6:.0f} MB, {nsub_sample * spec.nchan} cells); "
+        "sample": f"channels 0..{nchan_sample - 1} x {nsub_sample} sub-int(s) of {L} samples x "
+                  f"{spec.nbeam} beams ({nbytes / 1e6:.0f} MB, {nsub_sample * nchan_sample} cells); "
                   f"oracle {dt:.2f} s, input generation {tgen:.1f} s not timed",
         "seconds": dt,
     }
@@ -68,7 +70,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--variant", default="mfma", choices=["mfma", "valu"])
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
-    ap.add_argument("--cpu-sample-subints", type=int, default=2)
+    ap.add_argument("--cpu-sample-subints", type=int, default=1)
+    ap.add_argument("--cpu-sample-chans", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seconds", type=float, default=10.0)
     args = ap.parse_args()
@@ -105,6 +108,7 @@ def main():
     status = torch.empty(ncell, dtype=torch.uint8, device=dev)
     mask = torch.empty(ncell, dtype=torch.uint8, device=dev)
     fstats = torch.zeros(48, dtype=torch.uint8, device=dev)
+    fws = torch.empty(rfi.rfi_flag_workspace_size(nsub, nc), dtype=torch.uint8, device=dev)
     variant = rfi.RFI_CCM_MFMA if args.variant == "mfma" else rfi.RFI_CCM_VALU
     stream = torch.cuda.current_stream()
 
@@ -119,7 +123,7 @@ def main():
         rfi.rfi_eig_batched(nb, nsub, nc, sx, sxy, cnt, stat, status, precision=args.precision)
         if timed is not None:
             ev[2].record(stream)
-        rfi.rfi_flag(nsub, nc, stat, status, mask, out=fstats)
+        rfi.rfi_flag(nsub, nc, stat, status, mask, out=fstats, workspace=fws)
         if timed is not None:
             ev[3].record(stream)
             torch.cuda.synchronize()
@@ -176,7 +180,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(spec, args.cpu_sample_subints)
+        cpu = cpu_baseline(spec, args.cpu_sample_subints, args.cpu_sample_chans)
         log(f"cpu baseline: {cpu['value'] * 1e3:.2f} MB/s on {cpu['cores']} threads")
 
     out = {

@@ -164,12 +164,17 @@ typedef struct {
  * every such cell with q * 2^-40 > mu + kappa sigma, repeat until a fit masks
  * nothing new or max_iter fits. mask[cell] = 1 for masked cells, else 0. If
  * state != NULL the block's final unmasked sums are folded into it and the
- * fit appended to its history. out (nullable) receives the summary.
+ * fit appended to its history. out (nullable) receives the summary
+ * (iterations = -1 if the grid-wide kernel's bounded barrier gave up).
+ * workspace: device scratch of rfi_flag_workspace_size() bytes, owned by the
+ * caller and used by one call at a time; NULL = the library takes it from
+ * the stream-ordered allocator for this call.
  * Errors: RFI_E_INVALID for bad sizes, kappa < 0 or max_iter < 1. */
+size_t rfi_flag_workspace_size(int32_t nsub, int32_t nchan);
 rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8_t* status,
                     const uint8_t* protect_chan, double kappa, int32_t max_iter,
                     rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
-                    rfi_stream_t stream);
+                    void* workspace, rfi_stream_t stream);
 
 /* Per-beam eigenvector stage (Sec. 3.3 last paragraph; kappa_v of Sec. 4.5):
  * for each beam b, mu_b and sigma_b (population) of |v1_b| over eligible

@@ -119,18 +119,29 @@ rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan, const int
   return check_hip(e, "rfi_eig_batched launch");
 }
 
+size_t rfi_flag_workspace_size(int32_t nsub, int32_t nchan) {
+  return rfi::flag_workspace_size(nsub, nchan);
+}
+
 rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8_t* status,
                     const uint8_t* protect_chan, double kappa, int32_t max_iter,
                     rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
-                    rfi_stream_t stream) {
+                    void* workspace, rfi_stream_t stream) {
   g_err.clear();
   if (nsub < 0 || nchan < 1) return fail(RFI_E_INVALID, "rfi_flag: bad nsub/nchan");
   if (!stat || !status || !mask) return fail(RFI_E_INVALID, "rfi_flag: NULL input or output");
   if (!(kappa >= 0.0)) return fail(RFI_E_INVALID, "rfi_flag: kappa must be >= 0");
   if (max_iter < 1) return fail(RFI_E_INVALID, "rfi_flag: max_iter %d < 1", max_iter);
-  return check_hip(rfi::launch_flag(nsub, nchan, stat, status, protect_chan, kappa, max_iter,
-                                    state, mask, out, (hipStream_t)stream),
-                   "rfi_flag launch");
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = workspace;
+  if (!ws) {
+    const hipError_t e = hipMallocAsync(&ws, rfi::flag_workspace_size(nsub, nchan), s);
+    if (e != hipSuccess) return fail(RFI_E_NOMEM, "rfi_flag: workspace: %s", hipGetErrorString(e));
+  }
+  const hipError_t e = rfi::launch_flag(nsub, nchan, stat, status, protect_chan, kappa, max_iter,
+                                        state, mask, out, ws, s);
+  if (!workspace) (void)hipFreeAsync(ws, s);
+  return check_hip(e, "rfi_flag launch");
 }
 
 rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const float* v1,

@@ -11,14 +11,21 @@
 // S'_a comes out of the same products: one padding row of X is all ones.
 //
 // Data path: a workgroup owns CW consecutive channels of one sub-interval and
-// walks its L samples in chunks of 32 rows. Each chunk of every beam
-// (32 rows x CW channel bytes, coalesced 16-byte loads) is staged in LDS, two
-// chunks deep, with the next chunk's global loads in flight while the current
-// one is consumed. A wave reads the rows of its channels back from LDS as
-// dwords (4 channels x 1 time), transposes 4x4 bytes in registers (v_perm) to
-// time-packed operands, and issues one MFMA per (channel, 16x16 beam block
-// pair). Workgroups whose channel tiles share 128-byte lines are dispatched
-// to the same XCD (same L2).
+// walks its L samples in chunks of 32 rows. A chunk of every beam (32 rows x
+// CW channel bytes) goes from HBM straight into LDS with the direct
+// global-to-LDS loads (global_load_lds_dwordx4: lane l of a wave instruction
+// fills bytes [16 l, 16 l + 16) of a 1 KB LDS window), into a ring of NST
+// chunk buffers, so NST - 1 chunks are in flight while one is consumed and no
+// registers hold staged data. The 16-byte units of a chunk are XOR-swizzled
+// (unit ^= (beam + 2 (row / 8)) mod 8) so that the 64 lanes reading one row
+// dword of 16 beams x 4 row groups hit every LDS bank group equally. A wave
+// reads the rows of its channels back as dwords (4 channels x 1 time),
+// transposes 4x4 bytes in registers (v_perm) to time-packed operands, and
+// issues one MFMA per (channel, 16x16 beam block pair). Waits on the DMA use
+// explicit vmcnt counts (every wave issues the same number of loads per
+// chunk), not the workgroup fence, so later chunks stay in flight across the
+// per-chunk barrier. Workgroups whose channel tiles share 128-byte lines are
+// dispatched to the same XCD (same L2).
 //
 // Comparison engine (ccm_valu_kernel, nbeam <= 20): one lane per channel, all
 // pair accumulators in registers, four samples per v_dot4_u32_u8.
@@ -52,46 +59,106 @@ __device__ __forceinline__ int block_pair(int b1, int b2, int nb) {
   return b1 * nb - b1 * (b1 - 1) / 2 + (b2 - b1);
 }
 
-template <int NB, int CW, int CPW>
+template <int NB, int CW, int CPW, int IPW, int NST>
 struct MfmaCfg {
   static constexpr int NBP = NB * (NB + 1) / 2;        // 16x16 block pairs
   static constexpr int NWAVE = CW / CPW;
   static constexpr int NTHR = 64 * NWAVE;
-  static constexpr int SEGS = CW / 16;                 // 16-byte segments per row
-  static constexpr int PLANE = TC * CW + 16;           // LDS bytes per beam and chunk
-  static constexpr int MAXBEAM = 16 * NB - 1;
-  static constexpr int NLOAD = (MAXBEAM * TC * SEGS + NTHR - 1) / NTHR;
+  static constexpr int SEGS = CW / 16;                 // 16-byte units per row
+  static constexpr int UPB = TC * SEGS;                // units per beam per chunk
+  static constexpr int STAGE = IPW * NWAVE * 1024;     // bytes per chunk buffer
   static constexpr int NGRP = CPW >= 4 ? CPW / 4 : 1;  // dword groups of 4 channels
 };
 
-template <int NB, int CW, int CPW>
-__global__ __launch_bounds__((MfmaCfg<NB, CW, CPW>::NTHR), 1) void ccm_mfma_kernel(
+// LDS unit (16 bytes) of (beam, row, segment) inside a chunk buffer
+template <int UPB, int SEGS>
+__device__ __forceinline__ int unit_of(int beam, int row, int seg) {
+  const int lin = beam * UPB + row * SEGS + seg;
+  return lin ^ ((beam + 2 * (row >> 3)) & 7);
+}
+
+// wait until at most N vector-memory operations of this wave are in flight,
+// then meet the workgroup; the memory clobber keeps LDS accesses on their side
+template <int N>
+__device__ __forceinline__ void vm_wait_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+template <int IPW, int NST>
+__device__ __forceinline__ void wait_chunk(int ahead) {
+  // 'ahead' chunks were requested after the one about to be consumed
+  if constexpr (NST >= 4) {
+    if (ahead >= 2) { vm_wait_barrier<2 * IPW>(); return; }
+  }
+  if constexpr (NST >= 3) {
+    if (ahead >= 1) { vm_wait_barrier<IPW>(); return; }
+  }
+  vm_wait_barrier<0>();
+}
+
+template <int NB, int CW, int CPW, int IPW, int NST>
+__global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm_mfma_kernel(
     BeamPtrs bp, int nbeam, int nchan, int64_t row_stride, int64_t t0, int L, int nsub,
     int nct, int32_t* __restrict__ sum_x, int32_t* __restrict__ sum_xy,
     int32_t* __restrict__ count, int accumulate) {
-  using C = MfmaCfg<NB, CW, CPW>;
-  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
+  extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
 
   // workgroup -> tile, grouping the tiles that share 128-byte lines on one XCD
   const int ntiles = nsub * nct;
-  int w = blockIdx.x;
+  const int w = blockIdx.x;
   constexpr int G = 128 / CW;
   const int full = (ntiles / (8 * G)) * (8 * G);
   int tile = w;
   if (w < full) {
     const int u = w / (8 * G), rem = w % (8 * G);
-    const int h = rem / 8, x = rem % 8;
-    tile = G * (8 * u + x) + h;
+    tile = G * (8 * u + rem % 8) + rem / 8;
   }
   const int k = tile / nct;
   const int c0 = (tile % nct) * CW;
   const int64_t ncell = (int64_t)nsub * nchan;
   const int64_t row0 = t0 + (int64_t)k * L;
   const int nchunk = (L + TC - 1) / TC;
-  const int bufbytes = nbeam * C::PLANE;
+
+  // the beam pointer table is the first kernel argument: index it in place
+  const uint8_t* const* beam_tab = (const uint8_t* const*)__builtin_amdgcn_kernarg_segment_ptr();
+
+  // Per chunk this thread's lane fills unit (64 q + lane) of the buffer for
+  // q = wave + NWAVE i, i < IPW; decode which (beam, row, seg) lands there.
+  // Units past the beams, rows past the sub-interval and segments past the
+  // row read a valid dummy address (never consumed), so every wave issues
+  // exactly IPW loads per chunk and vmcnt counts stay uniform.
+  int64_t src_off[IPW];
+  const uint8_t* src_base[IPW];
+  int src_row[IPW];
+#pragma unroll
+  for (int i = 0; i < IPW; ++i) {
+    const int s = 64 * (wave + C::NWAVE * i) + lane;
+    const int hi = s & ~7;
+    const int bh = hi / C::UPB, rh = (hi % C::UPB) / C::SEGS;
+    const int lin = s ^ ((bh + 2 * (rh >> 3)) & 7);
+    const int b = lin / C::UPB, r = (lin % C::UPB) / C::SEGS, g = lin % C::SEGS;
+    const int64_t col = c0 + 16 * g;
+    const bool ok = b < nbeam && col < row_stride;
+    src_base[i] = beam_tab[ok ? b : 0];
+    src_off[i] = ok ? col : 0;
+    src_row[i] = ok ? r : -1;
+  }
+  auto issue = [&](int chunk) {
+    uint8_t* buf = lds + (chunk % NST) * C::STAGE;
+    const int rows = min(TC, L - chunk * TC);
+#pragma unroll
+    for (int i = 0; i < IPW; ++i) {
+      const int r = (src_row[i] >= 0 && src_row[i] < rows) ? src_row[i] : 0;
+      const uint8_t* src = src_base[i] + (row0 + (int64_t)chunk * TC + r) * row_stride + src_off[i];
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)src,
+          (__attribute__((address_space(3))) void*)(buf + 1024 * (wave + C::NWAVE * i)), 16, 0, 0);
+    }
+  };
 
   v4i acc[CPW][C::NBP];
 #pragma unroll
@@ -99,29 +166,28 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW>::NTHR), 1) void ccm_mfma_kern
 #pragma unroll
     for (int p = 0; p < C::NBP; ++p) acc[c][p] = v4i{0, 0, 0, 0};
 
-  // slot i of this thread covers (beam, row, 16-byte segment) of a chunk
-  const uint8_t* const* beam_tab = (const uint8_t* const*)__builtin_amdgcn_kernarg_segment_ptr();
-  uint4 stage[C::NLOAD];
-#pragma unroll
-  for (int i = 0; i < C::NLOAD; ++i) stage[i] = uint4{0, 0, 0, 0};
   const int li = lane & 15;     // row (beam) within a 16-row block
   const int kg = lane >> 4;     // which 8 of the chunk's 32 rows this lane supplies
   const int cb = wave * CPW;    // first channel of this wave within the tile
 
-  auto compute_chunk = [&](int buf, int rows) {
-    const uint8_t* src = lds + buf * bufbytes;
+  auto compute_chunk = [&](int chunk) {
+    const uint8_t* src = lds + (chunk % NST) * C::STAGE;
+    const int rows = min(TC, L - chunk * TC);
 #pragma unroll
     for (int grp = 0; grp < C::NGRP; ++grp) {
       const int ch4 = (CPW >= 4) ? (cb + 4 * grp) : (cb & ~3);
+      const int seg = ch4 >> 4, wrd = (ch4 & 15) >> 2;
       long op[NB][4];
 #pragma unroll
       for (int bb = 0; bb < NB; ++bb) {
         const int beam = 16 * bb + li;
         uint32_t r[8];
         if (beam < nbeam) {
-          const uint8_t* p = src + beam * C::PLANE + (8 * kg) * CW + ch4;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) r[j] = *(const uint32_t*)(p + j * CW) ^ OFFSET_XOR;
+          for (int j = 0; j < 8; ++j) {
+            const int u = unit_of<C::UPB, C::SEGS>(beam, 8 * kg + j, seg);
+            r[j] = *(const uint32_t*)(src + 16 * u + 4 * wrd) ^ OFFSET_XOR;
+          }
         } else {
           const uint32_t v = (beam == nbeam) ? 0x01010101u : 0u;
 #pragma unroll
@@ -175,37 +241,16 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW>::NTHR), 1) void ccm_mfma_kern
     }
   };
 
-  for (int chunk = -1; chunk < nchunk; ++chunk) {
-    const int next = chunk + 1;
-    if (next < nchunk) {
-      const int rows = min(TC, L - next * TC);
-#pragma unroll
-      for (int i = 0; i < C::NLOAD; ++i) {
-        const int s = tid + i * C::NTHR;
-        const int g = s % C::SEGS;
-        const int r = (s / C::SEGS) % TC;
-        const int b = s / (C::SEGS * TC);
-        const int64_t col = c0 + 16 * g;
-        if (b < nbeam && r < rows && col < row_stride) {
-          const uint8_t* src = beam_tab[b] + (row0 + (int64_t)next * TC + r) * row_stride + col;
-          stage[i] = *(const uint4*)src;
-        }
-      }
-    }
-    if (chunk >= 0) compute_chunk(chunk & 1, min(TC, L - chunk * TC));
-    if (next < nchunk) {
-      uint8_t* dst = lds + (next & 1) * bufbytes;
-#pragma unroll
-      for (int i = 0; i < C::NLOAD; ++i) {
-        const int s = tid + i * C::NTHR;
-        const int g = s % C::SEGS;
-        const int r = (s / C::SEGS) % TC;
-        const int b = s / (C::SEGS * TC);
-        if (b < nbeam) *(uint4*)(dst + b * C::PLANE + r * CW + 16 * g) = stage[i];
-      }
-    }
-    __syncthreads();
+  // ring of NST buffers: chunks c+1 .. c+NST-2 (and c+NST-1 once issued) are
+  // in flight while chunk c is consumed
+  for (int c = 0; c < NST - 1 && c < nchunk; ++c) issue(c);
+  for (int c = 0; c < nchunk; ++c) {
+    const int last_issued = min(c + NST - 2, nchunk - 1);
+    wait_chunk<IPW, NST>(last_issued - c);           // chunk c complete in LDS
+    if (c + NST - 1 < nchunk) issue(c + NST - 1);     // reuses the buffer of chunk c - 1
+    compute_chunk(c);
   }
+  __syncthreads();
 
   // Epilogue: offset sums S'_a sit in the ones column; share them through LDS,
   // then every lane converts its entries to raw sums and stores them.
@@ -262,16 +307,17 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW>::NTHR), 1) void ccm_mfma_kern
   if (c0 == 0 && tid == 0) count[k] = accumulate ? count[k] + L : L;
 }
 
-template <int NB, int CW, int CPW>
+template <int NB, int CW, int CPW, int IPW, int NST>
 hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, hipStream_t s) {
-  using C = MfmaCfg<NB, CW, CPW>;
+  using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
+  if ((int64_t)nbeam * C::UPB > (int64_t)64 * IPW * C::NWAVE) return hipErrorInvalidValue;
   const int nct = (nchan + CW - 1) / CW;
-  const size_t lds = 2 * (size_t)nbeam * C::PLANE;
+  const size_t ring = (size_t)NST * C::STAGE;
   const size_t epi = (size_t)nbeam * CW * 4;
-  const size_t shm = lds > epi ? lds : epi;
-  const auto kern = ccm_mfma_kernel<NB, CW, CPW>;
+  const size_t shm = ring > epi ? ring : epi;
+  const auto kern = ccm_mfma_kernel<NB, CW, CPW, IPW, NST>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
@@ -279,6 +325,17 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
   hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), shm, s, bp, nbeam, nchan,
                      row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate);
   return hipGetLastError();
+}
+
+// Largest ring (<= 4 buffers) of IPW KB-per-wave chunk buffers within 160 KB.
+template <int NB, int CW, int CPW, int IPW>
+hipError_t launch_ipw(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride, int64_t t0,
+                      int L, int nsub, int32_t* sum_x, int32_t* sum_xy, int32_t* count,
+                      int accumulate, hipStream_t s) {
+  constexpr int stage_kb = IPW * (CW / CPW);
+  constexpr int NST = (4 * stage_kb <= 160) ? 4 : (3 * stage_kb <= 160) ? 3 : 2;
+  return launch_mfma_cfg<NB, CW, CPW, IPW, NST>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
+                                                sum_xy, count, accumulate, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,17 +407,28 @@ hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, hipStream_t s) {
   const int nb = (nbeam + 1 + 15) / 16;   // 16-row blocks incl. the ones row
-#define RFI_CCM(NB, CW, CPW) \
-  launch_mfma_cfg<NB, CW, CPW>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, sum_xy, count, accumulate, s)
+  // tile shape per block count: (CW channels, CPW channels per wave), 8 waves
+  int cw, cpw;
   switch (nb) {
-    case 1: return RFI_CCM(1, 64, 8);
-    case 2: return RFI_CCM(2, 64, 8);
-    case 3: return RFI_CCM(3, 32, 4);
-    case 4: return RFI_CCM(4, 16, 2);
-    case 5: return RFI_CCM(5, 16, 2);
+    case 1: case 2: cw = 64; cpw = 8; break;
+    case 3: cw = 32; cpw = 4; break;
+    case 4: case 5: cw = 16; cpw = 2; break;
     default: return hipErrorInvalidValue;
   }
+  const int units = nbeam * 32 * (cw / 16);        // 16-byte units per chunk
+  const int ipw = (units + 64 * 8 - 1) / (64 * 8);  // loads per wave per chunk
+#define RFI_CCM(NB, CW, CPW, IPW)                                                          \
+  if (nb == NB && ipw == IPW)                                                            \
+    return launch_ipw<NB, CW, CPW, IPW>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, \
+                                        sum_xy, count, accumulate, s);
+  RFI_CCM(1, 64, 8, 1) RFI_CCM(1, 64, 8, 2) RFI_CCM(1, 64, 8, 3) RFI_CCM(1, 64, 8, 4)
+  RFI_CCM(2, 64, 8, 4) RFI_CCM(2, 64, 8, 5) RFI_CCM(2, 64, 8, 6) RFI_CCM(2, 64, 8, 7)
+  RFI_CCM(2, 64, 8, 8)
+  RFI_CCM(3, 32, 4, 4) RFI_CCM(3, 32, 4, 5) RFI_CCM(3, 32, 4, 6)
+  RFI_CCM(4, 16, 2, 3) RFI_CCM(4, 16, 2, 4)
+  RFI_CCM(5, 16, 2, 4) RFI_CCM(5, 16, 2, 5)
 #undef RFI_CCM
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,

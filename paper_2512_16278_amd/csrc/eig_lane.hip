@@ -236,8 +236,14 @@ __global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
         A[Sym<N>::idx(i, j)] = x * rinv[j];
       });
     });
+    // start vector with no exact linear relation to any eigenvector that a
+    // correlation matrix can have (all-ones is orthogonal to (1, -1) for two
+    // anticorrelated beams): components 0.5 + frac(0.5 + i g), g = 0.7548...
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = i < n ? 1.0f : 0.0f;
+    for (int i = 0; i < N; ++i) {
+      const float f = 0.5f + 0.7548776662466927f * (float)i;
+      v[i] = i < n ? 0.5f + (f - floorf(f)) : 0.0f;
+    }
     for (int it = 0; it < 4; ++it) {
       // R y = v (forward), then R^T w = y (backward), in place
       static_for<0, N>([&](auto I) {

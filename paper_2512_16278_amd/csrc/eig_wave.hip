@@ -9,7 +9,8 @@
 // same skip rule as the per-lane solver is used (|a_pq| <= eps sqrt(|a_pp
 // a_qq|), eps the unit of the working precision), sweeps stop after one
 // without rotations or at max_sweeps. The dominant eigenvector is a column of
-// the accumulated V, and lambda_1 is refined by its FP64 Rayleigh quotient.
+// the accumulated V, and lambda_1 is refined by its FP64 Rayleigh quotient;
+// when all eigenvalues are requested each is refined the same way.
 #include <math.h>
 
 #include "internal.h"
@@ -167,6 +168,47 @@ __global__ __launch_bounds__(64) void eig_wave_kernel(EigArgs g) {
     }
     last = rot_sweep;
     if (!rot_sweep) break;
+  }
+
+  if (g.eigvals) {
+    // every eigenvalue as the FP64 Rayleigh quotient of its column of V on the
+    // FP64 correlation matrix: the error becomes second order in the
+    // eigenvector error, instead of the O(n eps) of the FP32 sweeps. Rows of C
+    // are formed one at a time in LDS and shared by all lanes.
+    double* row = red;                          // n <= 79 <= 128 doubles
+    double lam[2] = {0.0, 0.0};
+    for (int a = 0; a < n; ++a) {
+      __syncthreads();
+      for (int b = lane; b < n; b += 64) {
+        double cab = 1.0;
+        if (b != a) {
+          const int lo = a < b ? a : b, hi = a < b ? b : a;
+          const int64_t Sab = g.sum_xy[pidx(lo, hi, n) * ncell + cell];
+          const int64_t Nab = cnt * Sab - (int64_t)S[lo] * S[hi];
+          cab = (double)Nab * d[lo] * d[hi];
+        }
+        row[b] = cab;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int i = lane + 64 * k;
+        if (i >= n) continue;
+        double tsum = 0.0;
+        for (int b = 0; b < n; ++b) tsum += row[b] * (double)V[b * n + i];
+        lam[k] += (double)V[a * n + i] * tsum;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = lane + 64 * k;
+      if (i >= n) continue;
+      double nrm = 0.0;
+      for (int a = 0; a < n; ++a) nrm += (double)V[a * n + i] * (double)V[a * n + i];
+      A[i * n + i] = (T)(lam[k] / nrm);
+    }
+    __syncthreads();
   }
 
   // dominant eigenvalue (largest |lambda|, lowest index on ties)

@@ -37,10 +37,11 @@ struct EigArgs {
 hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s);       // FP32, nbeam <= 20
 hipError_t launch_eig_wave(const EigArgs& a, int precision, hipStream_t s);  // any nbeam
 
+size_t flag_workspace_size(int nsub, int nchan);
 hipError_t launch_flag(int nsub, int nchan, const double* stat, const uint8_t* status,
                        const uint8_t* protect_chan, double kappa, int max_iter,
                        rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
-                       hipStream_t s);
+                       void* workspace, hipStream_t s);
 hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float* v1,
                               const uint8_t* mask, const uint8_t* status,
                               const uint8_t* protect_chan, double kappa_v,

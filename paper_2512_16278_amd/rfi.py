@@ -92,7 +92,9 @@ def lib():
         L.rfi_ccm_accumulate.argtypes = [C.POINTER(rfi_block), i64, i32, i32, vp, vp, vp, i32, i32, vp]
         L.rfi_eig_batched.argtypes = [i32, i32, i32, vp, vp, vp, C.POINTER(rfi_eig_params),
                                       vp, vp, vp, vp, vp]
-        L.rfi_flag.argtypes = [i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
+        L.rfi_flag.argtypes = [i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp]
+        L.rfi_flag_workspace_size.argtypes = [i32, i32]
+        L.rfi_flag_workspace_size.restype = C.c_size_t
         L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
         for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_eigvec_flag"):
             getattr(L, f).restype = i32
@@ -160,11 +162,15 @@ def rfi_eig_batched(nbeam, nsub, nchan, sum_x, sum_xy, count, stat, status, eigv
                                  _ptr(status), _stream(stream)))
 
 
+def rfi_flag_workspace_size(nsub, nchan):
+    return int(lib().rfi_flag_workspace_size(int(nsub), int(nchan)))
+
+
 def rfi_flag(nsub, nchan, stat, status, mask, protect_chan=None, kappa=3.0, max_iter=50,
-             state=None, out=None, stream=None):
+             state=None, out=None, workspace=None, stream=None):
     _check(lib().rfi_flag(int(nsub), int(nchan), _ptr(stat), _ptr(status), _ptr(protect_chan),
                           float(kappa), int(max_iter), _ptr(state), _ptr(mask), _ptr(out),
-                          _stream(stream)))
+                          _ptr(workspace), _stream(stream)))
 
 
 def rfi_eigvec_flag(nbeam, nsub, nchan, v1, mask, status, beam_mask, protect_chan=None,

@@ -150,7 +150,13 @@ def _check_eig(x, L, nsub, out, lam_tol, stat_tol):
     gap = (w[:, 0] - w[:, 1]) / lam1
     clear = gap > 0.05
     vo = cr.v1.reshape(ncell, nb)
-    assert np.abs(v1.T[clear] - vo[clear]).max() < 1e-4
+    # the sign convention (sum > 0) is decided by rounding when sum(v1) ~ 0:
+    # there either sign is valid and the comparison is up to sign
+    tie = np.abs(vo.sum(axis=1)) < 1e-5
+    d_same = np.abs(v1.T - vo).max(axis=1)
+    d_flip = np.abs(v1.T + vo).max(axis=1)
+    d = np.where(tie, np.minimum(d_same, d_flip), d_same)
+    assert d[clear].max() < 1e-4
     assert np.allclose(np.linalg.norm(v1, axis=0), 1.0, atol=1e-5)
     return status, cr
 
@@ -202,9 +208,13 @@ def test_eig_degenerate_cells(dev):
         assert np.abs(stat - cr.stat.ravel()).max() < 1e-9
 
 
-def _flag_case(dev, s, status, nsub, nchan, kappa=3.0, max_iter=50, protect=None, state=None):
+def _flag_case(dev, s, status, nsub, nchan, kappa=3.0, max_iter=50, protect=None, state=None,
+               own_workspace=True):
     import torch
     from paper_2512_16278_amd import rfi
+    ws = None
+    if own_workspace:
+        ws = torch.empty(rfi.rfi_flag_workspace_size(nsub, nchan), dtype=torch.uint8, device=dev)
     st = torch.from_numpy(s.astype(np.float64)).to(dev)
     stt = torch.from_numpy(status.astype(np.uint8)).to(dev)
     mask = torch.full((nsub * nchan,), 9, dtype=torch.uint8, device=dev)
@@ -212,7 +222,7 @@ def _flag_case(dev, s, status, nsub, nchan, kappa=3.0, max_iter=50, protect=None
     pr = None if protect is None else torch.from_numpy(protect.astype(np.uint8)).to(dev)
     say("flag", nsub, nchan, kappa, max_iter)
     rfi.rfi_flag(nsub, nchan, st, stt, mask, protect_chan=pr, kappa=kappa, max_iter=max_iter,
-                 state=state, out=out)
+                 state=state, out=out, workspace=ws)
     torch.cuda.synchronize()
     return mask.cpu().numpy().astype(bool), rfi.flag_stats_from_bytes(out.cpu().numpy().tobytes())
 
@@ -234,7 +244,8 @@ def test_flag_matches_oracle(dev, seed):
     status[rng.choice(s.size, 50, replace=False)] = 1          # degenerate
     protect = (rng.uniform(size=nchan) < 0.02).astype(np.uint8)
     for kappa, max_iter in ((3.0, 50), (5.0, 50), (2.0, 2)):
-        mask, st = _flag_case(dev, s, status, nsub, nchan, kappa, max_iter, protect)
+        mask, st = _flag_case(dev, s, status, nsub, nchan, kappa, max_iter, protect,
+                              own_workspace=kappa != 5.0)
         elig = (status == 0) & ~np.tile(protect.astype(bool), nsub)
         ref = clip.clip_iterative(s, elig, kappa, max_iter)
         assert np.array_equal(mask, ref.mask)

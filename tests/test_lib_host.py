@@ -68,9 +68,10 @@ def test_argument_errors_are_synchronous():
     assert L.rfi_eig_batched(19, 1, 64, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16),
                              C.byref(p), None, C.c_void_p(16), None, C.c_void_p(16), None) == rfi.RFI_E_INVALID
     assert L.rfi_flag(1, 64, C.c_void_p(16), C.c_void_p(16), None, -1.0, 50, None,
-                      C.c_void_p(16), None, None) == rfi.RFI_E_INVALID
+                      C.c_void_p(16), None, None, None) == rfi.RFI_E_INVALID
     assert L.rfi_flag(1, 64, C.c_void_p(16), C.c_void_p(16), None, 3.0, 0, None,
-                      C.c_void_p(16), None, None) == rfi.RFI_E_INVALID
+                      C.c_void_p(16), None, None, None) == rfi.RFI_E_INVALID
+    assert rfi.rfi_flag_workspace_size(99, 4096) > 0
 
 
 def test_struct_layouts_match_header():
