@@ -24,11 +24,13 @@
 // issues one MFMA per (channel, 16x16 beam block pair). Waits on the DMA use
 // explicit vmcnt counts (every wave issues the same number of loads per
 // chunk), not the workgroup fence, so later chunks stay in flight across the
-// per-chunk barrier. Workgroups whose channel tiles share 128-byte lines are
-// dispatched to the same XCD (same L2).
+// per-chunk barrier. The workgroups of 1 KB of adjacent channels are
+// dispatched back to back on one XCD, so the rows are fetched in long runs.
 //
 // Comparison engine (ccm_valu_kernel, nbeam <= 20): one lane per channel, all
 // pair accumulators in registers, four samples per v_dot4_u32_u8.
+#include <stdlib.h>
+
 #include "internal.h"
 
 namespace rfi {
@@ -100,18 +102,21 @@ template <int NB, int CW, int CPW, int IPW, int NST>
 __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm_mfma_kernel(
     BeamPtrs bp, int nbeam, int nchan, int64_t row_stride, int64_t t0, int L, int nsub,
     int nct, int32_t* __restrict__ sum_x, int32_t* __restrict__ sum_xy,
-    int32_t* __restrict__ count, int accumulate) {
+    int32_t* __restrict__ count, int accumulate, int remap) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
 
-  // workgroup -> tile, grouping the tiles that share 128-byte lines on one XCD
+  // workgroup -> tile: G consecutive channel tiles of a sub-interval (G CW
+  // contiguous bytes of every row) go to G workgroups that are dispatched
+  // back to back on the same XCD (workgroup ids w, w + 8, w + 16, ...), so
+  // each row is fetched as one long run per XCD (DRAM page locality, shared L2)
   const int ntiles = nsub * nct;
   const int w = blockIdx.x;
-  constexpr int G = 128 / CW;
-  const int full = (ntiles / (8 * G)) * (8 * G);
+  const int G = remap;
+  const int full = G > 1 ? (ntiles / (8 * G)) * (8 * G) : 0;
   int tile = w;
   if (w < full) {
     const int u = w / (8 * G), rem = w % (8 * G);
@@ -183,11 +188,17 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
         const int beam = 16 * bb + li;
         uint32_t r[8];
         if (beam < nbeam) {
+          // rows 8 kg + j: the swizzle only permutes units within aligned
+          // groups of 8, so unit(j) = unit(j mod P) + 8 (j / P), P = 8 / SEGS,
+          // and the 8 reads need P base addresses plus immediate offsets
+          constexpr int P = 8 / C::SEGS;
+          const uint8_t* basep[P];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int u = unit_of<C::UPB, C::SEGS>(beam, 8 * kg + j, seg);
-            r[j] = *(const uint32_t*)(src + 16 * u + 4 * wrd) ^ OFFSET_XOR;
-          }
+          for (int m = 0; m < P; ++m)
+            basep[m] = src + 16 * unit_of<C::UPB, C::SEGS>(beam, 8 * kg + m, seg) + 4 * wrd;
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            r[j] = *(const uint32_t*)(basep[j % P] + 128 * (j / P)) ^ OFFSET_XOR;
         } else {
           const uint32_t v = (beam == nbeam) ? 0x01010101u : 0u;
 #pragma unroll
@@ -322,8 +333,16 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (e != hipSuccess) return e;
   const int64_t ntiles = (int64_t)nsub * nct;
+  // tiles per XCD group: 1 KB of contiguous row bytes by default (measured
+  // best for the 4 KB-row FAST layout); RFI_CCM_GROUP_BYTES overrides
+  static const int group_bytes = [] {
+    const char* e = getenv("RFI_CCM_GROUP_BYTES");
+    const int v = e ? atoi(e) : 1024;
+    return v < 16 ? 16 : v;
+  }();
+  const int remap = group_bytes / CW > 1 ? group_bytes / CW : 1;
   hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), shm, s, bp, nbeam, nchan,
-                     row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate);
+                     row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate, remap);
   return hipGetLastError();
 }
 
@@ -331,11 +350,19 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
 template <int NB, int CW, int CPW, int IPW>
 hipError_t launch_ipw(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride, int64_t t0,
                       int L, int nsub, int32_t* sum_x, int32_t* sum_xy, int32_t* count,
-                      int accumulate, hipStream_t s) {
+                      int accumulate, int max_stages, hipStream_t s) {
   constexpr int stage_kb = IPW * (CW / CPW);
   constexpr int NST = (4 * stage_kb <= 160) ? 4 : (3 * stage_kb <= 160) ? 3 : 2;
-  return launch_mfma_cfg<NB, CW, CPW, IPW, NST>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
-                                                sum_xy, count, accumulate, s);
+  if (NST >= 4 && max_stages >= 4)
+    return launch_mfma_cfg<NB, CW, CPW, IPW, (NST >= 4 ? 4 : 2)>(bp, nbeam, nchan, row_stride, t0,
+                                                                  L, nsub, sum_x, sum_xy, count,
+                                                                  accumulate, s);
+  if (NST >= 3 && max_stages >= 3)
+    return launch_mfma_cfg<NB, CW, CPW, IPW, (NST >= 3 ? 3 : 2)>(bp, nbeam, nchan, row_stride, t0,
+                                                                  L, nsub, sum_x, sum_xy, count,
+                                                                  accumulate, s);
+  return launch_mfma_cfg<NB, CW, CPW, IPW, 2>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
+                                              sum_xy, count, accumulate, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -415,12 +442,18 @@ hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
     case 4: case 5: cw = 16; cpw = 2; break;
     default: return hipErrorInvalidValue;
   }
+  // ring depth cap (tuning knob; default: the largest ring that fits)
+  static const int max_stages = [] {
+    const char* e = getenv("RFI_CCM_STAGES");
+    const int v = e ? atoi(e) : 4;
+    return v < 2 ? 2 : v;
+  }();
   const int units = nbeam * 32 * (cw / 16);        // 16-byte units per chunk
   const int ipw = (units + 64 * 8 - 1) / (64 * 8);  // loads per wave per chunk
 #define RFI_CCM(NB, CW, CPW, IPW)                                                          \
   if (nb == NB && ipw == IPW)                                                            \
     return launch_ipw<NB, CW, CPW, IPW>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, \
-                                        sum_xy, count, accumulate, s);
+                                        sum_xy, count, accumulate, max_stages, s);
   RFI_CCM(1, 64, 8, 1) RFI_CCM(1, 64, 8, 2) RFI_CCM(1, 64, 8, 3) RFI_CCM(1, 64, 8, 4)
   RFI_CCM(2, 64, 8, 4) RFI_CCM(2, 64, 8, 5) RFI_CCM(2, 64, 8, 6) RFI_CCM(2, 64, 8, 7)
   RFI_CCM(2, 64, 8, 8)
