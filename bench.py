@@ -5,12 +5,18 @@ Workload: FAST-shaped block, 19 beams x 4096 channels of uint8 total power,
 49.152 us samples, 10 s of data (203,450 samples), 2048-sample sub-intervals
 (99 full sub-intervals; the 698-sample tail is not a full cell), synthetic
 (seeded, generated on the GPU, device-resident before timing). One step is
-one pass of the whole path over the block:
+one pass of the whole path over the block, by default the single call
+
+    rfi_process_block   (sums -> eigen -> clip, sub-interval groups pipelined)
+
+or, with --path stages, the three calls
 
     rfi_ccm_accumulate -> rfi_eig_batched -> rfi_flag
 
 Metric: beam-sample GB/s = nbeam * nchan * nsub * L bytes / step time.
-Prints one JSON line (see the keys below).
+The roofline object is for the dominant kernel, timed with HIP events around
+its own launches in the three-call path (one launch per step over the whole
+block). Prints one JSON line (see the keys below).
 """
 from __future__ import annotations
 
@@ -74,6 +80,8 @@ def main():
     ap.add_argument("--cpu-sample-chans", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seconds", type=float, default=10.0)
+    ap.add_argument("--path", default="fused", choices=["fused", "stages"])
+    ap.add_argument("--group", type=int, default=0, help="sub-intervals per pipeline group")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -119,8 +127,10 @@ def main():
     stream = torch.cuda.current_stream()
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    pp = rfi.process_params(L, nsub, group=args.group, eig_precision=args.precision)
+    pws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, pp), dtype=torch.uint8, device=dev)
 
-    def step(timed=None):
+    def step_stages(timed=None):
         if timed is not None:
             ev[0].record(stream)
         rfi.rfi_ccm_accumulate(blk, 0, L, nsub, sx, sxy, cnt, variant=variant)
@@ -135,6 +145,10 @@ def main():
             torch.cuda.synchronize()
             timed.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
 
+    def step_fused():
+        rfi.rfi_process_block(blk, pp, stat, status, mask, pws, out=fstats)
+
+    step = step_fused if args.path == "fused" else step_stages
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -151,16 +165,29 @@ def main():
     torch.cuda.synchronize()
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
+    log(f"timed {args.steps} steps ({args.path}): {ms_step:.3f} ms/step")
 
-    # per-stage timing (events between the calls of each step)
+    # block latency: each step alone, from an event before it to one after it
+    lat = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(max(10, min(args.steps, 30))):
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat)
+
+    # per-kernel timing in the three-call path (events between the calls)
     stages = []
     for _ in range(max(3, min(args.steps, 10))):
-        step(stages)
+        step_stages(stages)
     st = np.array(stages)
     ms_ccm, ms_eig, ms_flag = np.median(st, axis=0)
-    lat = st.sum(axis=1)
     log(f"stages (median ms): ccm {ms_ccm:.3f}  eig {ms_eig:.3f}  flag {ms_flag:.3f}")
+    # the timed path's own outputs, for the summary
+    step()
+    torch.cuda.synchronize()
 
     nbytes_in = nb * nc * nsub * L
     value = nbytes_in / (ms_step / 1e3) / 1e9
@@ -169,7 +196,8 @@ def main():
     ccm_gbs = ccm_bytes / (ms_ccm / 1e3) / 1e9
     flags = rfi.flag_stats_from_bytes(fstats.cpu().numpy().tobytes())
     if ms_ccm >= ms_eig:
-        roof = {"kernel": "ccm_mfma_kernel" if variant == rfi.RFI_CCM_MFMA else "ccm_valu_kernel",
+        roof = {"kernel": "ccm_mfma_kernel (64-channel tile, one launch per block)"
+                          if variant == rfi.RFI_CCM_MFMA else "ccm_valu_kernel",
                 "bound": "hbm", "achieved": round(ccm_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ccm_gbs / HBM_PEAK_GBS, 4), "traffic": None,
                 "ms": round(float(ms_ccm), 4)}
@@ -198,11 +226,12 @@ def main():
         "config": {"workload": f"FAST-shaped block: {nb} beams x {nc} channels x {ns} samples "
                                f"(10 s at 49.152 us), L={L}, {nsub} sub-ints, "
                                f"{nbytes_in / 1e9:.2f} GB", "nbeam": nb, "nchan": nc,
-                   "L": L, "nsub": nsub, "ccm": args.variant, "jacobi": f"fp{args.precision}"},
+                   "L": L, "nsub": nsub, "path": args.path, "ccm": args.variant,
+                   "jacobi": f"fp{args.precision}"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
-        "stages_ms": {"ccm": round(float(ms_ccm), 4), "eig": round(float(ms_eig), 4),
-                      "flag": round(float(ms_flag), 4)},
+        "stages_ms": {"path": "three calls", "ccm": round(float(ms_ccm), 4),
+                      "eig": round(float(ms_eig), 4), "flag": round(float(ms_flag), 4)},
         "hbm_frac_whole_path": round(value / HBM_PEAK_GBS, 4),
         "flagged_cells": int(flags["nflag"]), "clip_iterations": int(flags["iterations"]),
         "roofline": roof,

@@ -187,6 +187,50 @@ rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const flo
                            uint8_t* beam_mask, double* beam_mu, double* beam_sigma,
                            rfi_stream_t stream);
 
+/* The whole per-block path in one call: the sums of Eq. 1, the eigen stage
+ * of Eq. 2 and the statistic (as rfi_eig_batched, FP32 Jacobi unless
+ * eig_precision = 64), then the clip (as rfi_flag), for the nsub full
+ * sub-intervals of L samples that start at sample t0 of blk. Sub-intervals
+ * are processed in groups of `group`: the sums of group g are formed on
+ * `stream` while earlier groups are eigendecomposed on a library-owned
+ * helper stream, and the sums of at most three groups live in the workspace
+ * at once, so the workspace stays bounded for any block length. group = 0
+ * takes the whole block as one group while its sums fit in 1 GiB (the
+ * fastest schedule measured: the two stages contend for the same vector ALU
+ * when they overlap), else the largest group that keeps the ring within
+ * 1 GiB. The results equal those of the three separate calls bit for bit
+ * (same arithmetic, whatever the grouping).
+ * Outputs: stat, status, mask [ncell] as in rfi_eig_batched / rfi_flag;
+ * eigvals [nbeam][ncell] and v1 [nbeam][ncell] are optional (NULL). state,
+ * protect_chan and out as in rfi_flag. The call is asynchronous on `stream`
+ * (all work, including the helper stream's, completes before later work on
+ * `stream` starts). Calls that run concurrently from several host threads
+ * are serialised while they enqueue. workspace: rfi_process_workspace_size()
+ * bytes of device memory, 256-byte aligned, owned by the caller and used by
+ * one call at a time.
+ * nsub = 0 launches nothing and accepts NULL outputs and workspace.
+ * Errors: as rfi_ccm_accumulate, rfi_eig_batched and rfi_flag;
+ * RFI_E_INVALID if workspace is NULL or misaligned, or group < 0. */
+typedef struct {
+  int64_t t0;            /* first sample of the first sub-interval */
+  int32_t L;             /* samples per sub-interval, 1..RFI_MAX_COUNT */
+  int32_t nsub;          /* full sub-intervals to process */
+  int32_t group;         /* sub-intervals per pipeline group; 0 = automatic */
+  int32_t eig_precision; /* 32 (default) or 64 */
+  int32_t max_sweeps;    /* 0 = 12 */
+  int32_t max_iter;      /* clip fits, 0 = 50 */
+  double kappa;          /* clip multiple (Sec. 4.5), >= 0 */
+} rfi_process_params;
+
+size_t rfi_process_workspace_size(int32_t nbeam, int32_t nchan,
+                                  const rfi_process_params* p /* host */);
+rfi_status rfi_process_block(const rfi_block* blk /* host */,
+                             const rfi_process_params* p /* host */,
+                             const uint8_t* protect_chan, rfi_stream_state* state,
+                             double* stat, uint8_t* status, uint8_t* mask, float* eigvals,
+                             float* v1, rfi_flag_stats* out, void* workspace,
+                             rfi_stream_t stream);
+
 /* Message for the last error returned on the calling thread ("" if none). */
 const char* rfi_last_error(void);
 

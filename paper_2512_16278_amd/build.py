@@ -1,6 +1,6 @@
 """Build the HIP libraries in-tree for gfx950 (hipcc cross-compiles; no GPU needed).
 
-librfi.so       -- the method (csrc/api.cpp, ccm.hip, eig_lane.hip, eig_wave.hip,
+librfi.so       -- the method (csrc/api.cpp, pipeline.cpp, ccm.hip, eig_lane.hip, eig_wave.hip,
                    flag.hip, serve.cpp)
 librfi_synth.so -- the GPU input generator (csrc/synth.hip)
 
@@ -29,7 +29,8 @@ COMMON = [
 ]
 
 LIBS = {
-    "librfi.so": ["api.cpp", "ccm.hip", "eig_lane.hip", "eig_wave.hip", "flag.hip", "serve.cpp"],
+    "librfi.so": ["api.cpp", "pipeline.cpp", "ccm.hip", "eig_lane.hip", "eig_wave.hip", "flag.hip",
+                  "serve.cpp"],
     "librfi_synth.so": ["synth.hip"],
 }
 

@@ -3,15 +3,20 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
 #include "internal.h"
 #include "rfi.h"
 
-namespace {
+namespace rfi {
 
+namespace {
 thread_local std::string g_err;
+}
+
+void clear_error() { rfi::clear_error(); }
 
 rfi_status fail(rfi_status code, const char* fmt, ...) {
   char buf[512];
@@ -28,54 +33,88 @@ rfi_status check_hip(hipError_t e, const char* what) {
   return fail(RFI_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-}  // namespace
+rfi_status validate_block(const rfi_block* blk, int64_t t0, int32_t L, int32_t nsub,
+                          const char* who, BeamPtrs* bp) {
+  if (!blk) return fail(RFI_E_INVALID, "%s: blk is NULL", who);
+  const int n = blk->nbeam;
+  if (n < 2 || n > RFI_MAX_BEAMS)
+    return fail(RFI_E_INVALID, "%s: nbeam %d outside 2..%d", who, n, RFI_MAX_BEAMS);
+  if (blk->nchan < 1) return fail(RFI_E_INVALID, "%s: nchan %d < 1", who, blk->nchan);
+  if (blk->row_stride < blk->nchan || blk->row_stride % 16 != 0)
+    return fail(RFI_E_INVALID, "%s: row_stride %lld must be >= nchan and a multiple of 16", who,
+                (long long)blk->row_stride);
+  if (L < 1) return fail(RFI_E_INVALID, "%s: L %d < 1", who, L);
+  if (L > RFI_MAX_COUNT)
+    return fail(RFI_E_OVERFLOW, "%s: L %d exceeds the exact int32 bound %d", who, L,
+                RFI_MAX_COUNT);
+  if (nsub < 0) return fail(RFI_E_INVALID, "%s: nsub %d < 0", who, nsub);
+  if (t0 < 0 || t0 + (int64_t)nsub * L > blk->nsamp)
+    return fail(RFI_E_INVALID, "%s: samples [%lld, %lld) outside the block of %lld", who,
+                (long long)t0, (long long)(t0 + (int64_t)nsub * L), (long long)blk->nsamp);
+  if ((int64_t)nsub * blk->nchan > (int64_t)1 << 30)
+    return fail(RFI_E_INVALID, "%s: nsub * nchan exceeds 2^30 cells", who);
+  std::memset(bp, 0, sizeof(*bp));
+  for (int b = 0; b < n; ++b) {
+    if (!blk->beam[b]) return fail(RFI_E_INVALID, "%s: beam %d is NULL", who, b);
+    if (((uintptr_t)blk->beam[b]) % 16 != 0)
+      return fail(RFI_E_INVALID, "%s: beam %d not 16-byte aligned", who, b);
+    bp->p[b] = blk->beam[b];
+  }
+  return RFI_OK;
+}
+
+rfi_status resolve_eig(int nbeam, const rfi_eig_params* p, rfi_eig_params* out,
+                       const char* who) {
+  rfi_eig_params prm{32, 12, 1, RFI_EIG_AUTO};
+  if (p) prm = *p;
+  if (prm.precision != 32 && prm.precision != 64)
+    return fail(RFI_E_INVALID, "%s: precision %d not 32 or 64", who, prm.precision);
+  if (prm.max_sweeps < 1 || prm.max_sweeps > 30)
+    return fail(RFI_E_INVALID, "%s: max_sweeps %d outside 1..30", who, prm.max_sweeps);
+  if (prm.solver == RFI_EIG_AUTO)
+    prm.solver = (prm.precision == 32 && nbeam <= 20) ? RFI_EIG_LANE : RFI_EIG_WAVE;
+  if (prm.solver == RFI_EIG_LANE && (prm.precision != 32 || nbeam > 20))
+    return fail(RFI_E_INVALID, "%s: the per-lane solver is FP32 and nbeam <= 20", who);
+  if (prm.solver != RFI_EIG_LANE && prm.solver != RFI_EIG_WAVE)
+    return fail(RFI_E_INVALID, "%s: unknown solver %d", who, prm.solver);
+  *out = prm;
+  return RFI_OK;
+}
+
+}  // namespace rfi
+
+using rfi::check_hip;
+using rfi::fail;
 
 extern "C" {
 
-const char* rfi_last_error(void) { return g_err.c_str(); }
+const char* rfi_last_error(void) { return rfi::g_err.c_str(); }
 
 const char* rfi_version(void) { return "librfi 0.1 (gfx950)"; }
 
 rfi_status rfi_ccm_accumulate(const rfi_block* blk, int64_t t0, int32_t L, int32_t nsub,
                               int32_t* sum_x, int32_t* sum_xy, int32_t* count,
                               int32_t accumulate, int32_t variant, rfi_stream_t stream) {
-  g_err.clear();
-  if (!blk) return fail(RFI_E_INVALID, "rfi_ccm_accumulate: blk is NULL");
+  rfi::clear_error();
+  rfi::BeamPtrs bp;
+  const rfi_status st = rfi::validate_block(blk, t0, L, nsub, "rfi_ccm_accumulate", &bp);
+  if (st != RFI_OK) return st;
   const int n = blk->nbeam;
-  if (n < 2 || n > RFI_MAX_BEAMS)
-    return fail(RFI_E_INVALID, "rfi_ccm_accumulate: nbeam %d outside 2..%d", n, RFI_MAX_BEAMS);
-  if (blk->nchan < 1) return fail(RFI_E_INVALID, "rfi_ccm_accumulate: nchan %d < 1", blk->nchan);
-  if (blk->row_stride < blk->nchan || blk->row_stride % 16 != 0)
-    return fail(RFI_E_INVALID, "rfi_ccm_accumulate: row_stride %lld must be >= nchan and a multiple of 16",
-                (long long)blk->row_stride);
-  if (L < 1) return fail(RFI_E_INVALID, "rfi_ccm_accumulate: L %d < 1", L);
-  if (L > RFI_MAX_COUNT)
-    return fail(RFI_E_OVERFLOW, "rfi_ccm_accumulate: L %d exceeds the exact int32 bound %d", L,
-                RFI_MAX_COUNT);
-  if (nsub < 0) return fail(RFI_E_INVALID, "rfi_ccm_accumulate: nsub %d < 0", nsub);
-  if (t0 < 0 || t0 + (int64_t)nsub * L > blk->nsamp)
-    return fail(RFI_E_INVALID, "rfi_ccm_accumulate: samples [%lld, %lld) outside the block of %lld",
-                (long long)t0, (long long)(t0 + (int64_t)nsub * L), (long long)blk->nsamp);
-  if ((int64_t)nsub * blk->nchan > (int64_t)1 << 30)
-    return fail(RFI_E_INVALID, "rfi_ccm_accumulate: nsub * nchan exceeds 2^30 cells");
   if (!sum_x || !sum_xy || !count)
     return fail(RFI_E_INVALID, "rfi_ccm_accumulate: NULL output");
-  rfi::BeamPtrs bp;
-  std::memset(&bp, 0, sizeof(bp));
-  for (int b = 0; b < n; ++b) {
-    if (!blk->beam[b]) return fail(RFI_E_INVALID, "rfi_ccm_accumulate: beam %d is NULL", b);
-    if (((uintptr_t)blk->beam[b]) % 16 != 0)
-      return fail(RFI_E_INVALID, "rfi_ccm_accumulate: beam %d not 16-byte aligned", b);
-    bp.p[b] = blk->beam[b];
-  }
   if (nsub == 0) return RFI_OK;
   int v = variant;
   if (v == RFI_CCM_AUTO) v = RFI_CCM_MFMA;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if (v == RFI_CCM_MFMA) {
+    // tuning knob: RFI_CCM_SHARED=1 selects the tile of the pipelined path
+    static const int shared = [] {
+      const char* e = getenv("RFI_CCM_SHARED");
+      return e && atoi(e) == 1 ? 1 : 0;
+    }();
     e = rfi::launch_ccm_mfma(bp, n, blk->nchan, blk->row_stride, t0, L, nsub, sum_x, sum_xy,
-                             count, accumulate ? 1 : 0, s);
+                             count, accumulate ? 1 : 0, shared, s);
   } else if (v == RFI_CCM_VALU) {
     if (n > 20) return fail(RFI_E_INVALID, "rfi_ccm_accumulate: VALU variant needs nbeam <= 20");
     e = rfi::launch_ccm_valu(bp, n, blk->nchan, blk->row_stride, t0, L, nsub, sum_x, sum_xy,
@@ -90,7 +129,7 @@ rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan, const int
                            const int32_t* sum_xy, const int32_t* count, const rfi_eig_params* p,
                            float* eigvals, double* stat, float* v1, uint8_t* status,
                            rfi_stream_t stream) {
-  g_err.clear();
+  rfi::clear_error();
   if (nbeam < 2 || nbeam > RFI_MAX_BEAMS)
     return fail(RFI_E_INVALID, "rfi_eig_batched: nbeam %d outside 2..%d", nbeam, RFI_MAX_BEAMS);
   if (nsub < 0 || nchan < 1) return fail(RFI_E_INVALID, "rfi_eig_batched: bad nsub/nchan");
@@ -98,24 +137,21 @@ rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan, const int
     return fail(RFI_E_INVALID, "rfi_eig_batched: nsub * nchan exceeds 2^30 cells");
   if (!sum_x || !sum_xy || !count || !stat || !status)
     return fail(RFI_E_INVALID, "rfi_eig_batched: NULL input or output");
-  rfi_eig_params prm{32, 12, 1, RFI_EIG_AUTO};
-  if (p) prm = *p;
-  if (prm.precision != 32 && prm.precision != 64)
-    return fail(RFI_E_INVALID, "rfi_eig_batched: precision %d not 32 or 64", prm.precision);
-  if (prm.max_sweeps < 1 || prm.max_sweeps > 30)
-    return fail(RFI_E_INVALID, "rfi_eig_batched: max_sweeps %d outside 1..30", prm.max_sweeps);
-  int solver = prm.solver;
-  if (solver == RFI_EIG_AUTO) solver = (prm.precision == 32 && nbeam <= 20) ? RFI_EIG_LANE : RFI_EIG_WAVE;
-  if (solver == RFI_EIG_LANE && (prm.precision != 32 || nbeam > 20))
-    return fail(RFI_E_INVALID, "rfi_eig_batched: the per-lane solver is FP32 and nbeam <= 20");
-  if (solver != RFI_EIG_LANE && solver != RFI_EIG_WAVE)
-    return fail(RFI_E_INVALID, "rfi_eig_batched: unknown solver %d", prm.solver);
+  rfi_eig_params prm;
+  const rfi_status st = rfi::resolve_eig(nbeam, p, &prm, "rfi_eig_batched");
+  if (st != RFI_OK) return st;
   if (nsub == 0) return RFI_OK;
   rfi::EigArgs a{nbeam, nsub, nchan, sum_x, sum_xy, count, prm.max_sweeps, prm.refine ? 1 : 0,
-                 eigvals, stat, v1, status};
+                 eigvals, stat, v1, status, (int64_t)nsub * nchan};
   hipStream_t s = (hipStream_t)stream;
-  const hipError_t e = solver == RFI_EIG_LANE ? rfi::launch_eig_lane(a, s)
-                                              : rfi::launch_eig_wave(a, prm.precision, s);
+  // tuning knob: RFI_EIG_WG = cells per workgroup of the per-lane solver
+  static const int wg = [] {
+    const char* e = getenv("RFI_EIG_WG");
+    const int v = e ? atoi(e) : 256;
+    return v == 64 || v == 128 ? v : 256;
+  }();
+  const hipError_t e = prm.solver == RFI_EIG_LANE ? rfi::launch_eig_lane(a, s, wg)
+                                                  : rfi::launch_eig_wave(a, prm.precision, s);
   return check_hip(e, "rfi_eig_batched launch");
 }
 
@@ -127,7 +163,7 @@ rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8
                     const uint8_t* protect_chan, double kappa, int32_t max_iter,
                     rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
                     void* workspace, rfi_stream_t stream) {
-  g_err.clear();
+  rfi::clear_error();
   if (nsub < 0 || nchan < 1) return fail(RFI_E_INVALID, "rfi_flag: bad nsub/nchan");
   if (!stat || !status || !mask) return fail(RFI_E_INVALID, "rfi_flag: NULL input or output");
   if (!(kappa >= 0.0)) return fail(RFI_E_INVALID, "rfi_flag: kappa must be >= 0");
@@ -148,7 +184,7 @@ rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const flo
                            const uint8_t* mask, const uint8_t* status,
                            const uint8_t* protect_chan, double kappa_v, uint8_t* beam_mask,
                            double* beam_mu, double* beam_sigma, rfi_stream_t stream) {
-  g_err.clear();
+  rfi::clear_error();
   if (nbeam < 2 || nbeam > RFI_MAX_BEAMS || nsub < 0 || nchan < 1)
     return fail(RFI_E_INVALID, "rfi_eigvec_flag: bad sizes");
   if (!v1 || !mask || !status || !beam_mask)

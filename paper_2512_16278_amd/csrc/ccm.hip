@@ -432,12 +432,22 @@ __global__ __launch_bounds__(256) void ccm_valu_kernel(BeamPtrs bp, int nbeam, i
 
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
-                           int32_t* count, int accumulate, hipStream_t s) {
+                           int32_t* count, int accumulate, int shared_cu, hipStream_t s) {
   const int nb = (nbeam + 1 + 15) / 16;   // 16-row blocks incl. the ones row
-  // tile shape per block count: (CW channels, CPW channels per wave), 8 waves
+  // tile shape per block count: (CW channels, CPW channels per wave). With
+  // shared_cu the tile is 32 channels on 8 waves of ~120 VGPRs, which leaves
+  // every SIMD room for one wave of the register-resident eigensolver, so the
+  // two kernels run side by side on each CU.
   int cw, cpw;
+  static const int cpw2 = [] {
+    const char* e = getenv("RFI_CCM_CPW");
+    return e && atoi(e) == 4 ? 4 : 8;
+  }();
   switch (nb) {
-    case 1: case 2: cw = 64; cpw = 8; break;
+    case 1: cw = 64; cpw = 8; break;
+    case 2:
+      if (shared_cu) { cw = 32; cpw = 4; } else { cw = 64; cpw = cpw2; }
+      break;
     case 3: cw = 32; cpw = 4; break;
     case 4: case 5: cw = 16; cpw = 2; break;
     default: return hipErrorInvalidValue;
@@ -448,15 +458,18 @@ hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
     const int v = e ? atoi(e) : 4;
     return v < 2 ? 2 : v;
   }();
+  const int nwave = cw / cpw;
   const int units = nbeam * 32 * (cw / 16);        // 16-byte units per chunk
-  const int ipw = (units + 64 * 8 - 1) / (64 * 8);  // loads per wave per chunk
+  const int ipw = (units + 64 * nwave - 1) / (64 * nwave);  // loads per wave per chunk
 #define RFI_CCM(NB, CW, CPW, IPW)                                                          \
-  if (nb == NB && ipw == IPW)                                                            \
+  if (nb == NB && cw == CW && cpw == CPW && ipw == IPW)                                \
     return launch_ipw<NB, CW, CPW, IPW>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, \
                                         sum_xy, count, accumulate, max_stages, s);
   RFI_CCM(1, 64, 8, 1) RFI_CCM(1, 64, 8, 2) RFI_CCM(1, 64, 8, 3) RFI_CCM(1, 64, 8, 4)
   RFI_CCM(2, 64, 8, 4) RFI_CCM(2, 64, 8, 5) RFI_CCM(2, 64, 8, 6) RFI_CCM(2, 64, 8, 7)
   RFI_CCM(2, 64, 8, 8)
+  RFI_CCM(2, 64, 4, 2) RFI_CCM(2, 64, 4, 3) RFI_CCM(2, 64, 4, 4)
+  RFI_CCM(2, 32, 4, 2) RFI_CCM(2, 32, 4, 3) RFI_CCM(2, 32, 4, 4)
   RFI_CCM(3, 32, 4, 4) RFI_CCM(3, 32, 4, 5) RFI_CCM(3, 32, 4, 6)
   RFI_CCM(4, 16, 2, 3) RFI_CCM(4, 16, 2, 4)
   RFI_CCM(5, 16, 2, 4) RFI_CCM(5, 16, 2, 5)

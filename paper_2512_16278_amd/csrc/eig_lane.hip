@@ -57,17 +57,21 @@ template <int N>
 __device__ __forceinline__ void load_corr32(const EigArgs& g, int64_t ncell, int64_t cell,
                                             int n, int64_t cnt, float (&A)[Sym<N>::NP],
                                             bool& degenerate) {
-  int32_t S[N];
+  // N_ab = cnt S_ab - S_a S_b is formed exactly in FP64: cnt S_ab < 2^47 and
+  // S_a S_b < 2^48 are integers held exactly, and the FMA's one rounding is
+  // exact too (|N_ab| < 2^48 < 2^53) -- cheaper than int64 arithmetic.
+  double Sd[N];
   float dinv[N];
   degenerate = false;
+  const double cd = (double)cnt;
   static_for<0, N>([&](auto Ai) {
     constexpr int a = RFI_CI(Ai);
     const int aa = a < n ? a : 0;                    // clamped: always a valid address
-    S[a] = g.sum_x[aa * ncell + cell];
-    const int64_t Saa = g.sum_xy[pidx(aa, aa, n) * ncell + cell];
-    const int64_t Naa = cnt * Saa - (int64_t)S[a] * S[a];
-    dinv[a] = (a < n && Naa > 0) ? __builtin_amdgcn_rsqf((float)Naa) : 0.f;
-    degenerate |= (a < n && Naa <= 0);
+    Sd[a] = (double)g.sum_x[aa * ncell + cell];
+    const double Saa = (double)g.sum_xy[pidx(aa, aa, n) * ncell + cell];
+    const double Naa = fma(cd, Saa, -Sd[a] * Sd[a]);
+    dinv[a] = (a < n && Naa > 0.0) ? __builtin_amdgcn_rsqf((float)Naa) : 0.f;
+    degenerate |= (a < n && Naa <= 0.0);
     A[Sym<N>::idx(a, a)] = 1.0f;
   });
   // one row at a time, so that only a row's raw sums are in flight at once
@@ -77,8 +81,8 @@ __device__ __forceinline__ void load_corr32(const EigArgs& g, int64_t ncell, int
     static_for<a + 1, N>([&](auto Bi) {
       constexpr int b = RFI_CI(Bi);
       const int64_t p = b < n ? pidx(a, b, n) : 0;   // b < n implies a < n
-      const int64_t Sab = g.sum_xy[p * ncell + cell];
-      const int64_t Nab = cnt * Sab - (int64_t)S[a] * S[b];
+      const double Sab = (double)g.sum_xy[p * ncell + cell];
+      const double Nab = fma(cd, Sab, -Sd[a] * Sd[b]);
       A[Sym<N>::idx(a, b)] = b < n ? (float)Nab * dinv[a] * dinv[b] : 0.f;
     });
   });
@@ -100,9 +104,10 @@ __device__ __forceinline__ bool jacobi_sweep(float (&A)[Sym<N>::NP]) {
         // symmetric 2x2 Schur: theta = (a_qq - a_pp) / (2 a_pq); hardware
         // rcp / sqrt / rsq (about 1 ulp) are ample: c^2 + s^2 = 1 to a few ulp
         const float theta = (aqq - app) * __builtin_amdgcn_rcpf(2.0f * apq);
-        const float at = fabsf(theta);
-        float t = (at > 1e15f) ? 0.5f * __builtin_amdgcn_rcpf(at)
-                               : __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(1.0f + at * at));
+        // |theta| clamped so theta^2 cannot overflow (t is then ~1/(2|theta|),
+        // a rotation that is the identity to working precision)
+        const float at = fminf(fabsf(theta), 1e18f);
+        float t = __builtin_amdgcn_rcpf(at + __builtin_amdgcn_sqrtf(fmaf(at, at, 1.0f)));
         t = theta < 0.f ? -t : t;
         const float c = __builtin_amdgcn_rsqf(1.0f + t * t);
         const float s = t * c;
@@ -130,7 +135,7 @@ __device__ __forceinline__ bool jacobi_sweep(float (&A)[Sym<N>::NP]) {
 template <int N>
 __global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
-  const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= ncell) return;
   const int n = g.nbeam;
   const int64_t cnt = g.count[cell / g.nchan];
@@ -138,7 +143,7 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
     g.stat[cell] = 1.0;
     g.status[cell] = RFI_CELL_BAD_COUNT | RFI_CELL_DEGENERATE;
     if (g.eigvals)
-      for (int i = 0; i < n; ++i) g.eigvals[i * ncell + cell] = 0.f;
+      for (int i = 0; i < n; ++i) g.eigvals[i * g.out_stride + cell] = 0.f;
     return;
   }
   uint8_t st = 0;
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
     }
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (i < n) g.eigvals[i * ncell + cell] = ev[i];
+      if (i < n) g.eigvals[i * g.out_stride + cell] = ev[i];
   }
 }
 
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
 template <int N>
 __global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
-  const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= ncell) return;
   const int n = g.nbeam;
   const int64_t cnt = g.count[cell / g.nchan];
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
   if (st & RFI_CELL_BAD_COUNT) {
     g.stat[cell] = 0.0;
     if (g.v1)
-      for (int i = 0; i < n; ++i) g.v1[i * ncell + cell] = 0.f;
+      for (int i = 0; i < n; ++i) g.v1[i * g.out_stride + cell] = 0.f;
     return;
   }
   const float lam1 = (float)g.stat[cell];
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
       const float f = 0.5f + 0.7548776662466927f * (float)i;
       v[i] = i < n ? 0.5f + (f - floorf(f)) : 0.0f;
     }
-    for (int it = 0; it < 4; ++it) {
+    for (int it = 0; it < 3; ++it) {
       // R y = v (forward), then R^T w = y (backward), in place
       static_for<0, N>([&](auto I) {
         constexpr int i = RFI_CI(I);
@@ -327,31 +332,32 @@ __global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
     const float sgn = (sum < 0.f || (sum == 0.f && first < 0.f)) ? -1.0f : 1.0f;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-      if (i < n) g.v1[i * ncell + cell] = have_v ? sgn * v[i] : 0.f;
+      if (i < n) g.v1[i * g.out_stride + cell] = have_v ? sgn * v[i] : 0.f;
   }
 }
 
 template <int N>
-hipError_t launch_n(const EigArgs& a, hipStream_t s) {
+hipError_t launch_n(const EigArgs& a, int wg, hipStream_t s) {
   const int64_t ncell = (int64_t)a.nsub * a.nchan;
-  const dim3 grid((unsigned)((ncell + 255) / 256));
-  hipLaunchKernelGGL(eig_lane_jacobi<N>, grid, dim3(256), 0, s, a);
+  const dim3 grid((unsigned)((ncell + wg - 1) / wg));
+  hipLaunchKernelGGL(eig_lane_jacobi<N>, grid, dim3(wg), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(eig_lane_refine<N>, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(eig_lane_refine<N>, grid, dim3(wg), 0, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s) {
+hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg) {
   const int n = a.nbeam;
-  if (n <= 4) return launch_n<4>(a, s);
-  if (n <= 8) return launch_n<8>(a, s);
-  if (n <= 12) return launch_n<12>(a, s);
-  if (n <= 16) return launch_n<16>(a, s);
-  if (n == 19) return launch_n<19>(a, s);
-  if (n <= 20) return launch_n<20>(a, s);
+  if (wg != 64 && wg != 128 && wg != 256) return hipErrorInvalidValue;
+  if (n <= 4) return launch_n<4>(a, wg, s);
+  if (n <= 8) return launch_n<8>(a, wg, s);
+  if (n <= 12) return launch_n<12>(a, wg, s);
+  if (n <= 16) return launch_n<16>(a, wg, s);
+  if (n == 19) return launch_n<19>(a, wg, s);
+  if (n <= 20) return launch_n<20>(a, wg, s);
   return hipErrorInvalidValue;
 }
 

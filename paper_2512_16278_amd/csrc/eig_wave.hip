@@ -68,8 +68,8 @@ __global__ __launch_bounds__(64) void eig_wave_kernel(EigArgs g) {
   const int64_t cnt = g.count[cell / g.nchan];
   if (cnt < 2 || cnt > RFI_MAX_COUNT) {
     for (int i = lane; i < n; i += 64) {
-      if (g.eigvals) g.eigvals[i * ncell + cell] = 0.f;
-      if (g.v1) g.v1[i * ncell + cell] = 0.f;
+      if (g.eigvals) g.eigvals[i * g.out_stride + cell] = 0.f;
+      if (g.v1) g.v1[i * g.out_stride + cell] = 0.f;
     }
     if (lane == 0) {
       g.stat[cell] = 0.0;
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(64) void eig_wave_kernel(EigArgs g) {
         const T lj = fabs(A[j * n + j]);
         rank += (lj > li) || (lj == li && j < i);
       }
-      g.eigvals[rank * ncell + cell] = (float)A[i * n + i];
+      g.eigvals[rank * g.out_stride + cell] = (float)A[i * n + i];
     }
   }
 
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(64) void eig_wave_kernel(EigArgs g) {
   __syncthreads();
   if (g.v1) {
     const double sgn = red[0];   // columns of V are unit vectors
-    for (int a = lane; a < n; a += 64) g.v1[a * ncell + cell] = (float)(sgn * (double)V[a * n + i1]);
+    for (int a = lane; a < n; a += 64) g.v1[a * g.out_stride + cell] = (float)(sgn * (double)V[a * n + i1]);
   }
 }
 

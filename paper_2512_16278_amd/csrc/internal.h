@@ -18,7 +18,7 @@ inline int npair_of(int n) { return n * (n + 1) / 2; }
 // Kernel launchers (return a HIP error code; arguments already validated).
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
-                           int32_t* count, int accumulate, hipStream_t s);
+                           int32_t* count, int accumulate, int shared_cu, hipStream_t s);
 hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, hipStream_t s);
@@ -33,8 +33,10 @@ struct EigArgs {
   double* stat;
   float* v1;
   uint8_t* status;
+  int64_t out_stride;  // cell stride of the eigvals / v1 rows (>= nsub * nchan)
 };
-hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s);       // FP32, nbeam <= 20
+// FP32, nbeam <= 20; wg = lanes (cells) per workgroup: 64, 128 or 256
+hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg = 256);
 hipError_t launch_eig_wave(const EigArgs& a, int precision, hipStream_t s);  // any nbeam
 
 size_t flag_workspace_size(int nsub, int nchan);
@@ -47,5 +49,15 @@ hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float* v1,
                               const uint8_t* protect_chan, double kappa_v,
                               uint8_t* beam_mask, double* beam_mu, double* beam_sigma,
                               hipStream_t s);
+
+// Error reporting shared by the entry points (thread-local message).
+void clear_error();
+rfi_status fail(rfi_status code, const char* fmt, ...);
+rfi_status check_hip(hipError_t e, const char* what);
+// Argument checks shared by the entry points; fill bp on success.
+rfi_status validate_block(const rfi_block* blk, int64_t t0, int32_t L, int32_t nsub,
+                          const char* who, BeamPtrs* bp);
+// Eigen parameters with defaults applied and the solver resolved.
+rfi_status resolve_eig(int nbeam, const rfi_eig_params* p, rfi_eig_params* out, const char* who);
 
 }  // namespace rfi

@@ -58,6 +58,12 @@ class rfi_stream_state(C.Structure):
                 ("nblocks", C.c_int64), ("hist", rfi_hist_entry * RFI_HIST_CAP)]
 
 
+class rfi_process_params(C.Structure):
+    _fields_ = [("t0", C.c_int64), ("L", C.c_int32), ("nsub", C.c_int32), ("group", C.c_int32),
+                ("eig_precision", C.c_int32), ("max_sweeps", C.c_int32), ("max_iter", C.c_int32),
+                ("kappa", C.c_double)]
+
+
 class rfi_synth_spec(C.Structure):
     _fields_ = [("nbeam", C.c_int32), ("nchan", C.c_int32), ("nsamp", C.c_int64),
                 ("row_stride", C.c_int64), ("key0", C.c_uint32), ("key1", C.c_uint32),
@@ -96,7 +102,12 @@ def lib():
         L.rfi_flag_workspace_size.argtypes = [i32, i32]
         L.rfi_flag_workspace_size.restype = C.c_size_t
         L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
-        for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_eigvec_flag"):
+        L.rfi_process_workspace_size.argtypes = [i32, i32, C.POINTER(rfi_process_params)]
+        L.rfi_process_workspace_size.restype = C.c_size_t
+        L.rfi_process_block.argtypes = [C.POINTER(rfi_block), C.POINTER(rfi_process_params),
+                                        vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_eigvec_flag",
+                  "rfi_process_block"):
             getattr(L, f).restype = i32
         L.rfi_last_error.restype = C.c_char_p
         L.rfi_version.restype = C.c_char_p
@@ -171,6 +182,24 @@ def rfi_flag(nsub, nchan, stat, status, mask, protect_chan=None, kappa=3.0, max_
     _check(lib().rfi_flag(int(nsub), int(nchan), _ptr(stat), _ptr(status), _ptr(protect_chan),
                           float(kappa), int(max_iter), _ptr(state), _ptr(mask), _ptr(out),
                           _ptr(workspace), _stream(stream)))
+
+
+def process_params(L, nsub, t0=0, group=0, eig_precision=32, max_sweeps=12, max_iter=50,
+                   kappa=3.0) -> rfi_process_params:
+    return rfi_process_params(int(t0), int(L), int(nsub), int(group), int(eig_precision),
+                              int(max_sweeps), int(max_iter), float(kappa))
+
+
+def rfi_process_workspace_size(nbeam, nchan, p: rfi_process_params):
+    return int(lib().rfi_process_workspace_size(int(nbeam), int(nchan), C.byref(p)))
+
+
+def rfi_process_block(blk: rfi_block, p: rfi_process_params, stat, status, mask, workspace,
+                      protect_chan=None, state=None, eigvals=None, v1=None, out=None,
+                      stream=None):
+    _check(lib().rfi_process_block(C.byref(blk), C.byref(p), _ptr(protect_chan), _ptr(state),
+                                   _ptr(stat), _ptr(status), _ptr(mask), _ptr(eigvals), _ptr(v1),
+                                   _ptr(out), _ptr(workspace), _stream(stream)))
 
 
 def rfi_eigvec_flag(nbeam, nsub, nchan, v1, mask, status, beam_mask, protect_chan=None,

@@ -84,3 +84,34 @@ def test_struct_layouts_match_header():
     assert f"#define RFI_MAX_BEAMS {rfi.RFI_MAX_BEAMS}" in hdr
     assert f"#define RFI_HIST_CAP {rfi.RFI_HIST_CAP}" in hdr
     assert f"#define RFI_MAX_COUNT {rfi.RFI_MAX_COUNT}" in hdr
+
+
+def test_process_block_argument_errors():
+    from paper_2512_16278_amd import rfi
+    L = rfi.lib()
+    p = rfi.process_params(256, 4)
+    assert rfi.rfi_process_workspace_size(19, 4096, p) > 0
+    bad = rfi.process_params(256, 4, group=-1)
+    assert rfi.rfi_process_workspace_size(19, 4096, bad) == 0
+    assert rfi.rfi_process_workspace_size(1, 4096, p) == 0
+    assert L.rfi_process_block(None, C.byref(p), None, None, None, None, None, None, None,
+                               None, None, None) == rfi.RFI_E_INVALID
+    blk = rfi.rfi_block()
+    blk.nbeam, blk.nchan, blk.nsamp, blk.row_stride = 19, 64, 1024, 64
+    for b in range(19):
+        blk.beam[b] = 16 * (b + 1)          # never dereferenced: validation fails first
+    args = [C.c_void_p(256)] * 3
+    assert L.rfi_process_block(C.byref(blk), None, None, None, *args, None, None, None,
+                               C.c_void_p(256), None) == rfi.RFI_E_INVALID
+    # workspace missing / misaligned
+    assert L.rfi_process_block(C.byref(blk), C.byref(p), None, None, *args, None, None, None,
+                               None, None) == rfi.RFI_E_INVALID
+    assert L.rfi_process_block(C.byref(blk), C.byref(p), None, None, *args, None, None, None,
+                               C.c_void_p(272), None) == rfi.RFI_E_INVALID
+    # samples outside the block; kappa < 0
+    assert L.rfi_process_block(C.byref(blk), C.byref(rfi.process_params(256, 5)), None, None,
+                               *args, None, None, None, C.c_void_p(256), None) == rfi.RFI_E_INVALID
+    assert L.rfi_process_block(C.byref(blk), C.byref(rfi.process_params(256, 4, kappa=-1)),
+                               None, None, *args, None, None, None, C.c_void_p(256),
+                               None) == rfi.RFI_E_INVALID
+    assert b"kappa" in L.rfi_last_error()
