@@ -16,7 +16,7 @@ namespace {
 thread_local std::string g_err;
 }
 
-void clear_error() { rfi::clear_error(); }
+void clear_error() { g_err.clear(); }
 
 rfi_status fail(rfi_status code, const char* fmt, ...) {
   char buf[512];
