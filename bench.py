@@ -82,6 +82,11 @@ def main():
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--path", default="fused", choices=["fused", "stages"])
     ap.add_argument("--group", type=int, default=0, help="sub-intervals per pipeline group")
+    ap.add_argument("--quick", action="store_true",
+                    help="time the steps only (no latency, stage split or CPU baseline)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for counter collection: one copy, one streaming read, one three-call "
+                         "step and one whole-block step, then the JSON line of those")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -113,6 +118,21 @@ def main():
     calib = data.view(-1)[: 1 << 30].clone()
     del calib
     torch.cuda.synchronize()
+
+    # measured streaming-read peak: the whole input read once by a plain
+    # 16-byte-load kernel (median of 5, HIP events on the launch stream)
+    sink = torch.empty(rfi.stream_read_sink_words(), dtype=torch.int32, device=dev)
+    rd = []
+    for _ in range(1 if args.profile_run else 6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        rfi.stream_read(data, sink)
+        b.record()
+        torch.cuda.synchronize()
+        rd.append(a.elapsed_time(b))
+    rd = rd[1:] if len(rd) > 1 else rd
+    read_gbs = data.numel() / (float(np.median(rd)) / 1e3) / 1e9
+    log(f"streaming read of {data.numel() / 1e9:.2f} GB: {read_gbs:.0f} GB/s")
 
     blk = rfi.make_block(data, nc)
     sx = torch.empty((nb, ncell), dtype=torch.int32, device=dev)
@@ -149,6 +169,12 @@ def main():
         rfi.rfi_process_block(blk, pp, stat, status, mask, pws, out=fstats)
 
     step = step_fused if args.path == "fused" else step_stages
+    if args.profile_run:
+        step_stages()
+        step_fused()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "stream_read_gbs": round(read_gbs, 1)}), flush=True)
+        return
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -166,6 +192,13 @@ def main():
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
     log(f"timed {args.steps} steps ({args.path}): {ms_step:.3f} ms/step")
+    if args.quick:
+        nbytes_q = nb * nc * nsub * L
+        print(json.dumps({"quick": True, "ms_per_step": round(ms_step, 4),
+                          "value": round(nbytes_q / (ms_step / 1e3) / 1e9, 2),
+                          "stream_read_gbs": round(read_gbs, 1), "group": args.group,
+                          "path": args.path}), flush=True)
+        return
 
     # block latency: each step alone, from an event before it to one after it
     lat = []
@@ -233,6 +266,8 @@ def main():
         "stages_ms": {"path": "three calls", "ccm": round(float(ms_ccm), 4),
                       "eig": round(float(ms_eig), 4), "flag": round(float(ms_flag), 4)},
         "hbm_frac_whole_path": round(value / HBM_PEAK_GBS, 4),
+        "stream_read_gbs": round(read_gbs, 1),
+        "frac_of_measured_read": round(value / read_gbs, 4),
         "flagged_cells": int(flags["nflag"]), "clip_iterations": int(flags["iterations"]),
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -43,6 +43,16 @@ typedef struct {
 int32_t rfi_synth_fill(const rfi_synth_spec* spec, int32_t beam, int64_t t_lo, int64_t t_hi,
                        uint8_t* dst, void* stream);
 
+/* Streaming-read reference for the HBM roofline (measurement infrastructure,
+ * not part of the method): reads nbytes of device memory at src once, in
+ * 16-byte loads spread over the whole chip, and writes one 32-bit XOR of the
+ * data per thread into sink (device, at least rfi_stream_read_sink_words()
+ * words) so that the loads cannot be dropped. src 16-byte aligned; nbytes a
+ * multiple of 16. Returns 0, -1 for bad arguments, -5 for a launch error.
+ * Asynchronous on stream (a hipStream_t). */
+int32_t rfi_stream_read_sink_words(void);
+int32_t rfi_stream_read(const void* src, int64_t nbytes, uint32_t* sink, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

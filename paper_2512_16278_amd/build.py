@@ -2,7 +2,8 @@
 
 librfi.so       -- the method (csrc/api.cpp, pipeline.cpp, ccm.hip, eig_lane.hip, eig_wave.hip,
                    flag.hip, serve.cpp)
-librfi_synth.so -- the GPU input generator (csrc/synth.hip)
+librfi_synth.so -- the GPU input generator (csrc/synth.hip) and the streaming-read
+                   reference of the HBM roofline (csrc/stream_read.hip)
 
 Every call recompiles (objects go to _build/, the libraries next to this file).
 """
@@ -31,7 +32,7 @@ COMMON = [
 LIBS = {
     "librfi.so": ["api.cpp", "pipeline.cpp", "ccm.hip", "eig_lane.hip", "eig_wave.hip", "flag.hip",
                   "serve.cpp"],
-    "librfi_synth.so": ["synth.hip"],
+    "librfi_synth.so": ["synth.hip", "stream_read.hip"],
 }
 
 

@@ -31,6 +31,8 @@
 // pair accumulators in registers, four samples per v_dot4_u32_u8.
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace rfi {
@@ -70,6 +72,20 @@ struct MfmaCfg {
   static constexpr int UPB = TC * SEGS;                // units per beam per chunk
   static constexpr int STAGE = IPW * NWAVE * 1024;     // bytes per chunk buffer
   static constexpr int NGRP = CPW >= 4 ? CPW / 4 : 1;  // dword groups of 4 channels
+  // LDS: the ring of NST chunk buffers. After the last chunk the same space
+  // holds the epilogue's offset sums [MAXB][CW], its row table [MAXROW]
+  // (uint16) and its staging rows.
+  static constexpr int MAXB = 16 * NB - 1;             // beams (plus the ones row)
+  static constexpr int MAXROW = MAXB + MAXB * (MAXB + 1) / 2;
+  static constexpr int LDS_MAX = 160 * 1024;
+  static constexpr int RING = NST * STAGE;
+  static constexpr int SXL_OFF = 0;
+  static constexpr int TAB_OFF = SXL_OFF + MAXB * CW * 4;
+  static constexpr int STG_OFF = (TAB_OFF + MAXROW * 2 + 15) / 16 * 16;
+  static constexpr int STG_BYTES = LDS_MAX - STG_OFF;
+  // worst case: one wave's channels per pass at the largest beam count
+  static constexpr bool FITS = RING <= LDS_MAX && STG_BYTES >= MAXROW * (CPW + 1) * 4;
+  static constexpr int LDS = LDS_MAX;
 };
 
 // LDS unit (16 bytes) of (beam, row, segment) inside a chunk buffer
@@ -88,13 +104,15 @@ __device__ __forceinline__ void vm_wait_barrier() {
 
 template <int IPW, int NST>
 __device__ __forceinline__ void wait_chunk(int ahead) {
-  // 'ahead' chunks were requested after the one about to be consumed
+  // 'ahead' chunks (IPW loads each) were requested after the one about to be
+  // consumed; at most NST - 1
   if constexpr (NST >= 4) {
-    if (ahead >= 2) { vm_wait_barrier<2 * IPW>(); return; }
+    if (ahead >= 3) { vm_wait_barrier<3 * IPW>(); return; }
   }
   if constexpr (NST >= 3) {
-    if (ahead >= 1) { vm_wait_barrier<IPW>(); return; }
+    if (ahead >= 2) { vm_wait_barrier<2 * IPW>(); return; }
   }
+  if (ahead >= 1) { vm_wait_barrier<IPW>(); return; }
   vm_wait_barrier<0>();
 }
 
@@ -102,43 +120,44 @@ template <int NB, int CW, int CPW, int IPW, int NST>
 __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm_mfma_kernel(
     BeamPtrs bp, int nbeam, int nchan, int64_t row_stride, int64_t t0, int L, int nsub,
     int nct, int32_t* __restrict__ sum_x, int32_t* __restrict__ sum_xy,
-    int32_t* __restrict__ count, int accumulate, int remap) {
+    int32_t* __restrict__ count, int accumulate, int G, int nh, int prio) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
+  // optional issue priority over waves of other kernels on the same SIMD
+  if (prio) __builtin_amdgcn_s_setprio(2);
   extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+  // epilogue areas, over the drained ring
+  int32_t* sxl = (int32_t*)(lds + C::SXL_OFF);       // [nbeam][CW] offset sums S'_a
+  uint16_t* rowab = (uint16_t*)(lds + C::TAB_OFF);   // [nrow] (a, b) of each output row
+  int32_t* stg = (int32_t*)(lds + C::STG_OFF);       // [nrow][CW / nh + 1] output staging
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
+  const int ntiles = nsub * nct;
+  const int nchunk = (L + TC - 1) / TC;
+  const int64_t ncell = (int64_t)nsub * nchan;
+  const int nrow = nbeam + nbeam * (nbeam + 1) / 2;
 
   // workgroup -> tile: G consecutive channel tiles of a sub-interval (G CW
   // contiguous bytes of every row) go to G workgroups that are dispatched
-  // back to back on the same XCD (workgroup ids w, w + 8, w + 16, ...), so
-  // each row is fetched as one long run per XCD (DRAM page locality, shared L2)
-  const int ntiles = nsub * nct;
+  // back to back on the same XCD (workgroup ids w, w + 8, w + 16, ...): the
+  // hardware dispatcher then keeps adjacent tiles in step, and each row is
+  // fetched in long runs through one L2
   const int w = blockIdx.x;
-  const int G = remap;
   const int full = G > 1 ? (ntiles / (8 * G)) * (8 * G) : 0;
   int tile = w;
   if (w < full) {
     const int u = w / (8 * G), rem = w % (8 * G);
     tile = G * (8 * u + rem % 8) + rem / 8;
   }
-  const int k = tile / nct;
-  const int c0 = (tile % nct) * CW;
-  const int64_t ncell = (int64_t)nsub * nchan;
-  const int64_t row0 = t0 + (int64_t)k * L;
-  const int nchunk = (L + TC - 1) / TC;
-
-  // the beam pointer table is the first kernel argument: index it in place
-  const uint8_t* const* beam_tab = (const uint8_t* const*)__builtin_amdgcn_kernarg_segment_ptr();
 
   // Per chunk this thread's lane fills unit (64 q + lane) of the buffer for
   // q = wave + NWAVE i, i < IPW; decode which (beam, row, seg) lands there.
   // Units past the beams, rows past the sub-interval and segments past the
   // row read a valid dummy address (never consumed), so every wave issues
   // exactly IPW loads per chunk and vmcnt counts stay uniform.
-  int64_t src_off[IPW];
+  const uint8_t* const* beam_tab = (const uint8_t* const*)__builtin_amdgcn_kernarg_segment_ptr();
   const uint8_t* src_base[IPW];
-  int src_row[IPW];
+  int src_row[IPW], src_col[IPW];
 #pragma unroll
   for (int i = 0; i < IPW; ++i) {
     const int s = 64 * (wave + C::NWAVE * i) + lane;
@@ -146,19 +165,23 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
     const int bh = hi / C::UPB, rh = (hi % C::UPB) / C::SEGS;
     const int lin = s ^ ((bh + 2 * (rh >> 3)) & 7);
     const int b = lin / C::UPB, r = (lin % C::UPB) / C::SEGS, g = lin % C::SEGS;
-    const int64_t col = c0 + 16 * g;
-    const bool ok = b < nbeam && col < row_stride;
-    src_base[i] = beam_tab[ok ? b : 0];
-    src_off[i] = ok ? col : 0;
-    src_row[i] = ok ? r : -1;
+    src_base[i] = beam_tab[b < nbeam ? b : 0];
+    src_row[i] = b < nbeam ? r : -1;
+    src_col[i] = 16 * g;
   }
-  auto issue = [&](int chunk) {
-    uint8_t* buf = lds + (chunk % NST) * C::STAGE;
+  // DMA of chunk `chunk` of tile T into ring buffer `slot`
+  auto issue = [&](int T, int chunk, int slot) {
+    const int k = T / nct;
+    const int c0 = (T % nct) * CW;
+    uint8_t* buf = lds + slot * C::STAGE;
     const int rows = min(TC, L - chunk * TC);
+    const int64_t row = t0 + (int64_t)k * L + (int64_t)chunk * TC;
 #pragma unroll
     for (int i = 0; i < IPW; ++i) {
-      const int r = (src_row[i] >= 0 && src_row[i] < rows) ? src_row[i] : 0;
-      const uint8_t* src = src_base[i] + (row0 + (int64_t)chunk * TC + r) * row_stride + src_off[i];
+      const int64_t col = c0 + src_col[i];
+      const bool ok = src_row[i] >= 0 && col < row_stride;
+      const int r = (ok && src_row[i] < rows) ? src_row[i] : 0;
+      const uint8_t* src = src_base[i] + (row + r) * row_stride + (ok ? col : 0);
       __builtin_amdgcn_global_load_lds(
           (const __attribute__((address_space(1))) void*)src,
           (__attribute__((address_space(3))) void*)(buf + 1024 * (wave + C::NWAVE * i)), 16, 0, 0);
@@ -166,18 +189,20 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
   };
 
   v4i acc[CPW][C::NBP];
+  auto zero_acc = [&]() {
 #pragma unroll
-  for (int c = 0; c < CPW; ++c)
+    for (int c = 0; c < CPW; ++c)
 #pragma unroll
-    for (int p = 0; p < C::NBP; ++p) acc[c][p] = v4i{0, 0, 0, 0};
+      for (int p = 0; p < C::NBP; ++p) acc[c][p] = v4i{0, 0, 0, 0};
+  };
+  zero_acc();
 
   const int li = lane & 15;     // row (beam) within a 16-row block
   const int kg = lane >> 4;     // which 8 of the chunk's 32 rows this lane supplies
   const int cb = wave * CPW;    // first channel of this wave within the tile
 
-  auto compute_chunk = [&](int chunk) {
-    const uint8_t* src = lds + (chunk % NST) * C::STAGE;
-    const int rows = min(TC, L - chunk * TC);
+  auto compute_chunk = [&](int slot) {
+    const uint8_t* src = lds + slot * C::STAGE;
 #pragma unroll
     for (int grp = 0; grp < C::NGRP; ++grp) {
       const int ch4 = (CPW >= 4) ? (cb + 4 * grp) : (cb & ~3);
@@ -203,11 +228,6 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
           const uint32_t v = (beam == nbeam) ? 0x01010101u : 0u;
 #pragma unroll
           for (int j = 0; j < 8; ++j) r[j] = v;
-        }
-        if (rows < TC) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j)
-            if (8 * kg + j >= rows) r[j] = 0;
         }
         uint32_t o[8];
         transpose4x4(r[0], r[1], r[2], r[3], o[0], o[1], o[2], o[3]);
@@ -252,70 +272,125 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
     }
   };
 
-  // ring of NST buffers: chunks c+1 .. c+NST-2 (and c+NST-1 once issued) are
-  // in flight while chunk c is consumed
-  for (int c = 0; c < NST - 1 && c < nchunk; ++c) issue(c);
-  for (int c = 0; c < nchunk; ++c) {
-    const int last_issued = min(c + NST - 2, nchunk - 1);
-    wait_chunk<IPW, NST>(last_issued - c);           // chunk c complete in LDS
-    if (c + NST - 1 < nchunk) issue(c + NST - 1);     // reuses the buffer of chunk c - 1
-    compute_chunk(c);
-  }
-  __syncthreads();
-
-  // Epilogue: offset sums S'_a sit in the ones column; share them through LDS,
-  // then every lane converts its entries to raw sums and stores them.
-  int32_t* sxl = (int32_t*)lds;                      // [nbeam][CW]
-  const int jn = nbeam & 15, bn = nbeam >> 4;
-  if (li == jn) {
+  // Epilogue of one tile. Output rows: r < nbeam is sum_x of beam r, r =
+  // nbeam + pair(a, b) is sum_xy of (a, b); rowab[r] = a | b << 8 (b = 255
+  // for sum_x rows). The offset sums S'_a (ones column) go to LDS first.
+  // Then, in nh passes over the tile's channels (whole waves per pass), the
+  // waves of the pass write their raw offset sums to the staging rows
+  // [row][CW / nh + 1] (the pad keeps the scattered writes of one
+  // instruction in distinct banks), and the whole workgroup converts them to
+  // raw sums
+  //     S_a = S'_a + 128 L,   S_ab = S'_ab + 128 (S'_a + S'_b) + 16384 L
+  // and stores each row as CW / nh consecutive cells: coalesced runs. The
+  // epilogue runs over the drained ring; its barriers wait for LDS only.
+  auto lds_barrier = []() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
+  const int cwp = CW / nh;
+  const int ch_st = tid % cwp, row_st = tid / cwp, rstep = C::NTHR / cwp;
+  auto epilogue = [&](int T) {
+    const int k = T / nct;
+    const int c0 = (T % nct) * CW;
+    for (int r = tid; r < nrow; r += C::NTHR) {
+      int a = r, b = 255;
+      if (r >= nbeam) {
+        int q = r - nbeam;
+        a = 0;
+        while (q >= nbeam - a) { q -= nbeam - a; ++a; }
+        b = a + q;
+      }
+      rowab[r] = (uint16_t)(a | (b << 8));
+    }
+    const int jn = nbeam & 15, bn = nbeam >> 4;
+    if (li == jn) {
 #pragma unroll
-    for (int c = 0; c < CPW; ++c)
+      for (int c = 0; c < CPW; ++c)
 #pragma unroll
-      for (int b1 = 0; b1 < NB; ++b1)
+        for (int b1 = 0; b1 < NB; ++b1)
 #pragma unroll
-        for (int b2 = b1; b2 < NB; ++b2) {
-          if (b2 != bn) continue;
-          const int p = block_pair(b1, b2, NB);
+          for (int b2 = b1; b2 < NB; ++b2) {
+            if (b2 != bn) continue;
+            const int p = block_pair(b1, b2, NB);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int a = 16 * b1 + 4 * kg + r;
-            if (a < nbeam) sxl[a * CW + cb + c] = acc[c][p][r];
+            for (int r = 0; r < 4; ++r) {
+              const int a = 16 * b1 + 4 * kg + r;
+              if (a < nbeam) sxl[a * CW + cb + c] = acc[c][p][r];
+            }
           }
-        }
-  }
-  __syncthreads();
-  const uint32_t cnt = (uint32_t)L;
+    }
+    const uint32_t cnt = (uint32_t)L;
+    const int mypass = cb / cwp;
+    for (int h = 0; h < nh; ++h) {
+      if (mypass == h) {
 #pragma unroll
-  for (int c = 0; c < CPW; ++c) {
-    const int chl = cb + c;
-    const int chan = c0 + chl;
-    if (chan >= nchan) continue;
-    const int64_t cell = (int64_t)k * nchan + chan;
+        for (int b1 = 0; b1 < NB; ++b1)
 #pragma unroll
-    for (int b1 = 0; b1 < NB; ++b1)
+          for (int b2 = b1; b2 < NB; ++b2) {
+            const int p = block_pair(b1, b2, NB);
+            const int b = 16 * b2 + li;
 #pragma unroll
-      for (int b2 = b1; b2 < NB; ++b2) {
-        const int p = block_pair(b1, b2, NB);
-        const int b = 16 * b2 + li;
+            for (int r = 0; r < 4; ++r) {
+              const int a = 16 * b1 + 4 * kg + r;
+              int row = -1;
+              if (a <= b && b < nbeam) row = nbeam + a * nbeam - a * (a - 1) / 2 + (b - a);
+              else if (b == nbeam && a < nbeam) row = a;
+              if (row >= 0) {
+                int32_t* dst = stg + row * (cwp + 1) + (cb - h * cwp);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int a = 16 * b1 + 4 * kg + r;
-          const uint32_t v = (uint32_t)acc[c][p][r];
-          if (a <= b && b < nbeam) {
-            const uint32_t raw = v + 128u * ((uint32_t)sxl[a * CW + chl] + (uint32_t)sxl[b * CW + chl]) +
-                                 16384u * cnt;
-            const int64_t idx = (int64_t)a * nbeam - (int64_t)a * (a - 1) / 2 + (b - a);
-            int32_t* dst = sum_xy + idx * ncell + cell;
-            *dst = accumulate ? (int32_t)((uint32_t)*dst + raw) : (int32_t)raw;
-          } else if (b == nbeam && a < nbeam) {
-            const uint32_t raw = v + 128u * cnt;
-            int32_t* dst = sum_x + (int64_t)a * ncell + cell;
-            *dst = accumulate ? (int32_t)((uint32_t)*dst + raw) : (int32_t)raw;
+                for (int c = 0; c < CPW; ++c) dst[c] = acc[c][p][r];
+              }
+            }
           }
+      }
+      lds_barrier();
+      // thread t stores channel t mod cwp of rows t / cwp, t / cwp + rstep, ...
+      const int chl = h * cwp + ch_st;
+      const int chan = c0 + chl;
+      if (chan < nchan) {
+        const int64_t cell = (int64_t)k * nchan + chan;
+        for (int row = row_st; row < nrow; row += rstep) {
+          const uint32_t v = (uint32_t)stg[row * (cwp + 1) + ch_st];
+          const int ab = rowab[row];
+          const int a = ab & 255, b = ab >> 8;
+          const uint32_t raw = b == 255 ? v + 128u * cnt
+                                        : v + 128u * ((uint32_t)sxl[a * CW + chl] +
+                                                      (uint32_t)sxl[b * CW + chl]) + 16384u * cnt;
+          int32_t* dst = (row < nbeam ? sum_x + (int64_t)row * ncell
+                                      : sum_xy + (int64_t)(row - nbeam) * ncell) + cell;
+          *dst = accumulate ? (int32_t)((uint32_t)*dst + raw) : (int32_t)raw;
         }
       }
+      lds_barrier();
+    }
+    if (c0 == 0 && tid == 0) count[k] = accumulate ? count[k] + L : L;
+  };
+
+  // ring of NST buffers: chunks c+1 .. c+NST-2 (and c+NST-1 once issued) are
+  // in flight while chunk c is consumed
+  for (int c = 0; c < NST - 1 && c < nchunk; ++c) issue(tile, c, c);
+  for (int c = 0; c < nchunk; ++c) {
+    const int last_issued = min(c + NST - 2, nchunk - 1);
+    const int slot = c % NST;
+    wait_chunk<IPW, NST>(last_issued - c);          // chunk c complete in LDS
+    if (c + NST - 1 < nchunk) issue(tile, c + NST - 1, (c + NST - 1) % NST);  // buffer of c - 1
+    if (c == nchunk - 1 && L % TC != 0) {
+      // short last chunk: its rows past L hold dummy data; overwrite them
+      // with 0x80 bytes (0 after the offset XOR)
+      const int rows = L - c * TC;
+      uint8_t* buf = lds + slot * C::STAGE;
+      const int nu = nbeam * (TC - rows) * C::SEGS;
+      for (int u = tid; u < nu; u += C::NTHR) {
+        const int b = u / ((TC - rows) * C::SEGS);
+        const int rr = rows + (u / C::SEGS) % (TC - rows);
+        const int sg = u % C::SEGS;
+        *(uint4*)(buf + 16 * unit_of<C::UPB, C::SEGS>(b, rr, sg)) =
+            make_uint4(OFFSET_XOR, OFFSET_XOR, OFFSET_XOR, OFFSET_XOR);
+      }
+      lds_barrier();
+    }
+    compute_chunk(slot);
   }
-  if (c0 == 0 && tid == 0) count[k] = accumulate ? count[k] + L : L;
+  // every wave is past its last read of the ring before the epilogue reuses it
+  lds_barrier();
+  epilogue(tile);
 }
 
 template <int NB, int CW, int CPW, int IPW, int NST>
@@ -324,25 +399,34 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
                            int32_t* count, int accumulate, hipStream_t s) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   if ((int64_t)nbeam * C::UPB > (int64_t)64 * IPW * C::NWAVE) return hipErrorInvalidValue;
+  if (nbeam > C::MAXB) return hipErrorInvalidValue;
+  // epilogue passes: the fewest (power of two, whole waves each) whose
+  // staging rows fit
+  const int nrow = nbeam + nbeam * (nbeam + 1) / 2;
+  int nh = 1;
+  while (nh < C::NWAVE && nrow * (CW / nh + 1) * 4 > C::STG_BYTES) nh *= 2;
+  if (nrow * (CW / nh + 1) * 4 > C::STG_BYTES) return hipErrorInvalidValue;
   const int nct = (nchan + CW - 1) / CW;
-  const size_t ring = (size_t)NST * C::STAGE;
-  const size_t epi = (size_t)nbeam * CW * 4;
-  const size_t shm = ring > epi ? ring : epi;
   const auto kern = ccm_mfma_kernel<NB, CW, CPW, IPW, NST>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
   if (e != hipSuccess) return e;
   const int64_t ntiles = (int64_t)nsub * nct;
   // tiles per XCD group: 1 KB of contiguous row bytes by default (measured
   // best for the 4 KB-row FAST layout); RFI_CCM_GROUP_BYTES overrides
   static const int group_bytes = [] {
-    const char* e = getenv("RFI_CCM_GROUP_BYTES");
-    const int v = e ? atoi(e) : 1024;
-    return v < 16 ? 16 : v;
+    const char* v = getenv("RFI_CCM_GROUP_BYTES");
+    const int g = v ? atoi(v) : 1024;
+    return g < 16 ? 16 : g;
   }();
-  const int remap = group_bytes / CW > 1 ? group_bytes / CW : 1;
-  hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), shm, s, bp, nbeam, nchan,
-                     row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate, remap);
+  const int G = group_bytes / CW > 1 ? group_bytes / CW : 1;
+  // tuning knob: RFI_CCM_PRIO=1 raises the streaming waves' issue priority
+  static const int prio = [] {
+    const char* v = getenv("RFI_CCM_PRIO");
+    return v && atoi(v) == 1 ? 1 : 0;
+  }();
+  hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), C::LDS, s, bp, nbeam, nchan,
+                     row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate, G, nh, prio);
   return hipGetLastError();
 }
 
@@ -351,18 +435,20 @@ template <int NB, int CW, int CPW, int IPW>
 hipError_t launch_ipw(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride, int64_t t0,
                       int L, int nsub, int32_t* sum_x, int32_t* sum_xy, int32_t* count,
                       int accumulate, int max_stages, hipStream_t s) {
-  constexpr int stage_kb = IPW * (CW / CPW);
-  constexpr int NST = (4 * stage_kb <= 160) ? 4 : (3 * stage_kb <= 160) ? 3 : 2;
-  if (NST >= 4 && max_stages >= 4)
-    return launch_mfma_cfg<NB, CW, CPW, IPW, (NST >= 4 ? 4 : 2)>(bp, nbeam, nchan, row_stride, t0,
-                                                                  L, nsub, sum_x, sum_xy, count,
-                                                                  accumulate, s);
-  if (NST >= 3 && max_stages >= 3)
-    return launch_mfma_cfg<NB, CW, CPW, IPW, (NST >= 3 ? 3 : 2)>(bp, nbeam, nchan, row_stride, t0,
-                                                                  L, nsub, sum_x, sum_xy, count,
-                                                                  accumulate, s);
-  return launch_mfma_cfg<NB, CW, CPW, IPW, 2>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
-                                              sum_xy, count, accumulate, s);
+  if constexpr (MfmaCfg<NB, CW, CPW, IPW, 4>::FITS) {
+    if (max_stages >= 4)
+      return launch_mfma_cfg<NB, CW, CPW, IPW, 4>(bp, nbeam, nchan, row_stride, t0, L, nsub,
+                                                  sum_x, sum_xy, count, accumulate, s);
+  }
+  if constexpr (MfmaCfg<NB, CW, CPW, IPW, 3>::FITS) {
+    if (max_stages >= 3)
+      return launch_mfma_cfg<NB, CW, CPW, IPW, 3>(bp, nbeam, nchan, row_stride, t0, L, nsub,
+                                                  sum_x, sum_xy, count, accumulate, s);
+  }
+  if constexpr (MfmaCfg<NB, CW, CPW, IPW, 2>::FITS)
+    return launch_mfma_cfg<NB, CW, CPW, IPW, 2>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
+                                                sum_xy, count, accumulate, s);
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

@@ -122,6 +122,9 @@ def synth_lib():
         S.rfi_synth_fill.argtypes = [C.POINTER(rfi_synth_spec), C.c_int32, C.c_int64, C.c_int64,
                                      C.c_void_p, C.c_void_p]
         S.rfi_synth_fill.restype = C.c_int32
+        S.rfi_stream_read_sink_words.restype = C.c_int32
+        S.rfi_stream_read.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        S.rfi_stream_read.restype = C.c_int32
         _SYN = S
     return _SYN
 
@@ -219,7 +222,19 @@ def stream_state_from_bytes(raw: bytes) -> rfi_stream_state:
     return rfi_stream_state.from_buffer_copy(raw)
 
 
-# --- GPU input generator -----------------------------------------------------
+# --- measurement and input infrastructure ----------------------------------------
+
+def stream_read_sink_words() -> int:
+    return int(synth_lib().rfi_stream_read_sink_words())
+
+
+def stream_read(t, sink, nbytes=None, stream=None):
+    """Read nbytes (default: all) of device tensor t once (HBM roofline reference)."""
+    n = t.numel() * t.element_size() if nbytes is None else int(nbytes)
+    r = synth_lib().rfi_stream_read(C.c_void_p(t.data_ptr()), n, _ptr(sink), _stream(stream))
+    if r != 0:
+        raise RuntimeError(f"rfi_stream_read failed ({r})")
+
 
 class DeviceSynth:
     """Device copies of a SynthSpec's integer tables and rfi_synth_fill calls."""

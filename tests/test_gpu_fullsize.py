@@ -1,0 +1,160 @@
+"""Parity at the full FAST-shaped size (19 beams x 4096 channels, L = 2048,
+99 sub-intervals, 15.78 GB), in the launch configuration the benchmark times.
+
+The oracle cannot process all 405,504 cells in a test, so:
+
+* sampled cells (two whole sub-intervals over 512 channels each, and eight
+  channels over all 99 sub-intervals, including channels with injected
+  sinusoids and the burst sub-interval) are recomputed by the FP64 oracle
+  from bytes regenerated on the CPU: sums bit-exact, statistic <= 1e-9,
+  status bits equal, and the mask equal to the oracle statistic against the
+  GPU's final threshold;
+* over every cell, properties that hold at any size: the statistic lies in
+  [1/n, 1]; the mask is exactly {eligible cells with q > thr} for the
+  reported fit; the reported fit is the exact moment fit of the unmasked
+  eligible cells (recomputed here with Python integers); the clip reached
+  its fixed point.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ccm, pipeline
+from gpu_util import packed_oracle_sums, say
+
+pytestmark = pytest.mark.gpu
+
+TWO40 = float(1 << 40)
+
+
+@pytest.fixture(scope="module")
+def fast(request):
+    import torch
+    from paper_2512_16278_amd import rfi, synth
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    dev = torch.device("cuda:0")
+    spec = synth.fast_spec(seconds=10.0)
+    nb, nc, ns, L = spec.nbeam, spec.nchan, spec.nsamp, spec.L
+    stride = (nc + 15) // 16 * 16
+    say(f"full size: generating {nb} x {ns} x {nc} on the GPU")
+    data = torch.empty((nb, ns, stride), dtype=torch.uint8, device=dev)
+    ds = rfi.DeviceSynth(spec, dev)
+    for b in range(nb):
+        ds.fill(data[b], b)
+    torch.cuda.synchronize()
+    yield spec, data, dev
+    del data
+    torch.cuda.empty_cache()
+
+
+def _sample_windows(spec):
+    nsub = spec.nsamp // spec.L
+    burst_k = [bu.t_lo // spec.L for bu in spec.bursts]
+    sin_ch = sorted(s.chan for s in spec.sinusoids)
+    subs = sorted({0, burst_k[0] if burst_k else nsub - 1})
+    chans = sorted(set(sin_ch[:4]) | {1, 777, 2048, 4095})
+    return subs, chans
+
+
+def test_fullsize_process_block(fast):
+    import torch
+    from paper_2512_16278_amd import rfi, synth
+    spec, data, dev = fast
+    nb, nc, L = spec.nbeam, spec.nchan, spec.L
+    nsub = spec.nsamp // L
+    ncell = nsub * nc
+    blk = rfi.make_block(data, nc)
+    p = rfi.process_params(L, nsub)                    # the benchmark's configuration
+    ws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, p), dtype=torch.uint8, device=dev)
+    stat = torch.empty(ncell, dtype=torch.float64, device=dev)
+    status = torch.empty(ncell, dtype=torch.uint8, device=dev)
+    mask = torch.empty(ncell, dtype=torch.uint8, device=dev)
+    out = torch.zeros(48, dtype=torch.uint8, device=dev)
+    say("full size: rfi_process_block")
+    rfi.rfi_process_block(blk, p, stat, status, mask, ws, out=out)
+    torch.cuda.synchronize()
+    s = stat.cpu().numpy().reshape(nsub, nc)
+    st = status.cpu().numpy().reshape(nsub, nc)
+    m = mask.cpu().numpy().reshape(nsub, nc).astype(bool)
+    fs = rfi.flag_stats_from_bytes(out.cpu().numpy().tobytes())
+    say(f"full size: fit mu={fs['mu']:.6f} sigma={fs['sigma']:.6f} thr={fs['thr']:.6f} "
+        f"iters={fs['iterations']} nflag={fs['nflag']}")
+
+    # --- properties over every cell -------------------------------------------------
+    elig = (st & (rfi.RFI_CELL_DEGENERATE | rfi.RFI_CELL_BAD_COUNT)) == 0
+    assert elig.all()                                   # no degenerate cells in this data
+    assert (s >= 1.0 / nb - 1e-12).all() and (s <= 1.0 + 1e-12).all()
+    q = np.rint(s * TWO40).astype(np.int64)
+    assert fs["converged"] == 1 and 1 <= fs["iterations"] <= 50
+    T = math.floor(fs["thr"] * TWO40)
+    assert np.array_equal(m, elig & (q > T))
+    assert fs["nflag"] == int(m.sum())
+    live = [int(v) for v in q[elig & ~m]]
+    N, Q1, Q2 = len(live), sum(live), sum(v * v for v in live)
+    assert fs["nfit"] == N
+    mu = Q1 / (N << 40)
+    var = (N * Q2 - Q1 * Q1) / ((N * N) << 80)
+    assert abs(fs["mu"] - mu) <= 1e-13 * mu
+    assert abs(fs["sigma"] - math.sqrt(var)) <= 1e-12 * math.sqrt(var)
+    assert abs(fs["thr"] - (mu + 3.0 * math.sqrt(var))) <= 1e-12 * fs["thr"]
+    # fixed point: the last fit masks nothing new
+    assert (q[elig & ~m] * 2.0 ** -40 <= fs["thr"]).all()
+    # every injected common-mode channel is masked in most sub-intervals
+    for sn in spec.sinusoids:
+        assert m[:, sn.chan].mean() > 0.9, sn.chan
+
+    # --- sampled cells against the oracle -------------------------------------------
+    subs, chans = _sample_windows(spec)
+    thr = fs["thr"]
+    for k in subs:
+        say(f"full size: oracle on sub-interval {k}, channels 0..511")
+        x = synth.generate(spec, k * L, (k + 1) * L, 0, 512)
+        cr, _, _ = pipeline.block(x, L, 1)
+        so = cr.stat.ravel()
+        assert np.abs(s[k, :512] - so).max() <= 1e-9, k
+        qo = np.rint(so * TWO40) * 2.0 ** -40
+        clear = np.abs(qo - thr) > 1e-9
+        assert np.array_equal(m[k, :512][clear], (qo > thr)[clear]), k
+    for c in chans:
+        say(f"full size: oracle on channel {c}, all sub-intervals")
+        x = synth.generate(spec, 0, nsub * L, c, c + 1)
+        cr, _, _ = pipeline.block(x, L, nsub)
+        so = cr.stat.ravel()
+        assert np.abs(s[:, c] - so).max() <= 1e-9, c
+        qo = np.rint(so * TWO40) * 2.0 ** -40
+        clear = np.abs(qo - thr) > 1e-9
+        assert np.array_equal(m[:, c][clear], (qo > thr)[clear]), c
+
+
+def test_fullsize_sums_sampled(fast):
+    import torch
+    from paper_2512_16278_amd import rfi, synth
+    spec, data, dev = fast
+    nb, nc, L = spec.nbeam, spec.nchan, spec.L
+    nsub = spec.nsamp // L
+    ncell = nsub * nc
+    npair = nb * (nb + 1) // 2
+    blk = rfi.make_block(data, nc)
+    sx = torch.empty((nb, ncell), dtype=torch.int32, device=dev)
+    sxy = torch.empty((npair, ncell), dtype=torch.int32, device=dev)
+    cnt = torch.empty(nsub, dtype=torch.int32, device=dev)
+    say("full size: rfi_ccm_accumulate (MFMA)")
+    rfi.rfi_ccm_accumulate(blk, 0, L, nsub, sx, sxy, cnt, variant=rfi.RFI_CCM_MFMA)
+    torch.cuda.synchronize()
+    assert (cnt.cpu().numpy() == L).all()
+    gx = sx.cpu().numpy().reshape(nb, nsub, nc)
+    gxy = sxy.cpu().numpy().reshape(npair, nsub, nc)
+    subs, chans = _sample_windows(spec)
+    for k in subs:
+        x = synth.generate(spec, k * L, (k + 1) * L, 0, 512)
+        S, S2 = ccm.sums_fp64(x, L, 1)
+        rx, rxy = packed_oracle_sums(S, S2)
+        assert np.array_equal(gx[:, k, :512], rx), k
+        assert np.array_equal(gxy[:, k, :512], rxy), k
+    for c in chans[:3]:
+        x = synth.generate(spec, 0, nsub * L, c, c + 1)
+        S, S2 = ccm.sums_fp64(x, L, nsub)
+        rx, rxy = packed_oracle_sums(S, S2)
+        assert np.array_equal(gx[:, :, c], rx), c
+        assert np.array_equal(gxy[:, :, c], rxy), c
