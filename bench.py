@@ -69,6 +69,95 @@ def cpu_baseline(spec, nsub_sample: int, nchan_sample: int):
     }
 
 
+MIX_NBEAM = (7, 19, 36, 72)
+MIX_NCHAN = (1024, 4096, 8192)
+MIX_L = (512, 1024, 4096)
+
+
+def serve_bench(dev, rates, nblocks, nstreams=8, seed=7, slots=8, budget=64 << 30):
+    """Serving loop: Poisson arrivals of uneven blocks from nstreams streams.
+
+    Each stream has one shape class (nbeam, nchan, L) drawn from the uneven
+    mix; its blocks last U(0.1, 2) s (49.152 us samples) and are windows into
+    a device-resident pool of synthetic data (pre-generated on the GPU: host
+    generation at TB/s is impossible). For every arrival rate the same trace
+    runs through a session with `slots` execution slots (continuous batching)
+    and through a one-slot session (one block at a time). Throughput counts
+    every ingested beam-sample; latency is submit -> results ready.
+    """
+    import torch
+    from paper_2512_16278_amd import rfi, synth
+    rng = np.random.default_rng(seed)
+    pool_s = 2.2
+    pools = {}
+    for F in MIX_NCHAN:
+        spec = synth.mixed_spec(seed + F, max(MIX_NBEAM), F, 512, pool_s)
+        t = torch.empty((spec.nbeam, spec.nsamp, F), dtype=torch.uint8, device=dev)
+        ds = rfi.DeviceSynth(spec, dev)
+        for b in range(spec.nbeam):
+            ds.fill(t[b], b)
+        pools[F] = t
+    torch.cuda.synchronize()
+    shapes = [(int(rng.choice(MIX_NBEAM)), int(rng.choice(MIX_NCHAN)), int(rng.choice(MIX_L)))
+              for _ in range(nstreams)]
+    log(f"serving: {nstreams} streams {shapes}; pools {sum(p.numel() for p in pools.values()) / 1e9:.1f} GB")
+
+    def trace(rate):
+        r = np.random.default_rng(seed + int(rate))
+        t = np.cumsum(r.exponential(1.0 / rate, size=nblocks))
+        out = []
+        for ta in t:
+            si = int(r.integers(nstreams))
+            nb, F, L = shapes[si]
+            nsamp = int(r.uniform(0.1, 2.0) / synth.TSAMP)
+            start = int(r.integers(0, pools[F].shape[1] - nsamp))
+            out.append((float(ta), si, start, nsamp))
+        return out
+
+    def run(tr, nslot):
+        with rfi.Session(max_inflight=nslot, hbm_budget=budget) as S:
+            sids = [S.open_stream(nb, F, L) for nb, F, L in shapes]
+            blks = []
+            for ta, si, start, nsamp in tr:
+                nb, F, L = shapes[si]
+                pool = pools[F]
+                blks.append(rfi.make_block([pool[b, start:start + nsamp] for b in range(nb)], F))
+            tickets = []
+            t0 = time.perf_counter()
+            for (ta, si, start, nsamp), blk in zip(tr, blks):
+                while time.perf_counter() - t0 < ta:
+                    pass
+                tickets.append(S.submit(sids[si], blk))
+            lat, byts, t_first, t_last = [], 0, None, 0.0
+            for (ta, si, start, nsamp), tk in zip(tr, tickets):
+                r = S.wait(tk)
+                if r.status != rfi.RFI_OK:
+                    raise RuntimeError(f"serving block failed ({r.status})")
+                lat.append((r.t_done_us - r.t_submit_us) / 1e3)
+                t_first = r.t_submit_us if t_first is None else min(t_first, r.t_submit_us)
+                t_last = max(t_last, r.t_done_us)
+                nb, F, L = shapes[si]
+                byts += nb * F * nsamp
+                S.release(tk)
+        lat = np.array(lat)
+        span = (t_last - t_first) / 1e6
+        return {"gbs": round(byts / span / 1e9, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3), "span_s": round(span, 3)}
+
+    out = {"streams": [list(s) for s in shapes], "blocks_per_rate": nblocks, "slots": slots,
+           "budget_gb": budget / 2**30, "rates": []}
+    run(trace(rates[0])[:4], slots)                    # warm-up (code objects, pools)
+    for rate in rates:
+        tr = trace(rate)
+        a = run(tr, slots)
+        b = run(tr, 1)
+        log(f"serving rate {rate}/s: batched {a}  one-at-a-time {b}")
+        out["rates"].append({"rate_per_s": rate, "batched": a, "one_at_a_time": b})
+    del pools
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +171,9 @@ def main():
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--path", default="fused", choices=["fused", "stages"])
     ap.add_argument("--group", type=int, default=0, help="sub-intervals per pipeline group")
+    ap.add_argument("--serve-rates", default="200,2000",
+                    help="arrival rates (blocks/s) of the serving run; empty = skip it")
+    ap.add_argument("--serve-blocks", type=int, default=40, help="blocks per serving rate")
     ap.add_argument("--quick", action="store_true",
                     help="time the steps only (no latency, stage split or CPU baseline)")
     ap.add_argument("--profile-run", action="store_true",
@@ -244,6 +336,13 @@ def main():
                 "frac": round(ach / FP32_VALU_PEAK, 4), "traffic": None,
                 "ms": round(float(ms_eig), 4)}
 
+    serving = None
+    if args.serve_rates:
+        del data
+        torch.cuda.empty_cache()
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        serving = serve_bench(dev, rates, args.serve_blocks)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -270,6 +369,7 @@ def main():
         "frac_of_measured_read": round(value / read_gbs, 4),
         "flagged_cells": int(flags["nflag"]), "clip_iterations": int(flags["iterations"]),
         "roofline": roof,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -231,6 +231,100 @@ rfi_status rfi_process_block(const rfi_block* blk /* host */,
                              float* v1, rfi_flag_stats* out, void* workspace,
                              rfi_stream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of observation blocks from many streams.
+ *
+ * A session owns one device, a set of execution slots (each a HIP stream with
+ * its own workspace) and a scheduler thread. rfi_submit queues a block of a
+ * stream and returns at once with a ticket. The scheduler admits queued
+ * blocks in submission order while a slot is free and the session's HBM
+ * budget (block input + result buffers + workspace, charged from admission to
+ * rfi_result_release) allows, so blocks that arrive while others run are
+ * taken as soon as slots and memory free up, and blocks of different streams
+ * run concurrently on the device. Blocks of one stream run in submission
+ * order, since each updates that stream's state:
+ *  - the pooled clip state and fit history (rfi_stream_state, the streaming
+ *    reading of the Sec. 3.3 clip: each fit pools the exact moment sums of
+ *    the stream's earlier unmasked cells);
+ *  - the partial sub-interval: samples after a block's last full
+ *    sub-interval are summed into the stream's carry and completed by the
+ *    next block, so sub-intervals span block boundaries.
+ * A block's cells are: the completed carry sub-interval (if any) followed by
+ * its full sub-intervals, nsub x nchan in all. The result of every block is
+ * the same whether it runs alone or among other streams' blocks.
+ *
+ * Threading: every call is thread-safe. Block input buffers are zero-copy
+ * and must stay valid and unchanged until the ticket is done. Result device
+ * buffers belong to the session until rfi_result_release. */
+typedef struct rfi_session rfi_session;
+
+typedef struct {
+  int32_t device;        /* HIP device ordinal */
+  int32_t max_inflight;  /* execution slots, 1..64 (0 = 8); 1 = one block at a time */
+  int64_t hbm_budget;    /* bytes admitted at once (0 = 64 GiB) */
+} rfi_session_config;
+
+typedef struct {
+  int32_t nbeam, nchan;  /* block shape of this stream */
+  int32_t L;             /* samples per sub-interval, 1..RFI_MAX_COUNT */
+  int32_t eig_precision; /* 32 (0 = 32) or 64 */
+  int32_t max_sweeps;    /* 0 = 12 */
+  int32_t max_iter;      /* clip fits, 0 = 50 */
+  double kappa;          /* clip multiple (Sec. 4.5), >= 0 */
+  const uint8_t* protect_chan; /* HOST [nchan] (1 = preserved channel) or NULL; copied */
+} rfi_stream_config;
+
+typedef struct {
+  uint64_t ticket, user_tag;
+  int32_t stream_id;
+  rfi_status status;     /* RFI_OK, or the error that ended this block */
+  int32_t nsub, nchan;   /* cells of this block: nsub x nchan */
+  int32_t carried;       /* 1 if row 0 is the sub-interval completed from the carry */
+  int64_t carry_samples; /* samples of the stream's partial sub-interval after this block */
+  const double* stat;    /* DEVICE [nsub * nchan] statistic, session-owned */
+  const uint8_t* cell_status; /* DEVICE [nsub * nchan] RFI_CELL_* bits */
+  const uint8_t* mask;   /* DEVICE [nsub * nchan] 1 = masked */
+  rfi_flag_stats flag;   /* host copy of the block's clip summary */
+  double t_submit_us, t_admit_us, t_done_us; /* host clock, microseconds since session start */
+} rfi_result;
+
+rfi_status rfi_session_create(const rfi_session_config* cfg /* host, nullable */,
+                              rfi_session** s);
+/* Waits for all admitted work, cancels queued blocks (RFI_E_CANCELLED) and
+ * frees everything, including unreleased results. */
+void rfi_session_destroy(rfi_session* s);
+rfi_status rfi_stream_open(rfi_session* s, const rfi_stream_config* c /* host */,
+                           int32_t* stream_id);
+/* Waits for the stream's blocks, then frees its state. */
+rfi_status rfi_stream_close(rfi_session* s, int32_t stream_id);
+/* Queue one block (beam pointers and shape as for rfi_ccm_accumulate; nbeam
+ * and nchan must match the stream). Errors (synchronous): RFI_E_INVALID,
+ * RFI_E_BUDGET if the block alone exceeds the budget. */
+rfi_status rfi_submit(rfi_session* s, int32_t stream_id, const rfi_block* blk /* host */,
+                      uint64_t user_tag, uint64_t* ticket);
+/* RFI_OK and *r filled when the ticket is done (r->status tells how it
+ * ended); RFI_E_NOT_READY while queued or running; RFI_E_INVALID for an
+ * unknown or released ticket. */
+rfi_status rfi_poll(rfi_session* s, uint64_t ticket, rfi_result* r);
+/* As rfi_poll, blocking up to timeout_us (< 0: no limit); RFI_E_TIMEOUT. */
+rfi_status rfi_wait(rfi_session* s, uint64_t ticket, int64_t timeout_us, rfi_result* r);
+/* Cancel a block that has not been admitted yet (RFI_E_NOT_READY if it is
+ * already running or done). Later blocks of the stream still run. */
+rfi_status rfi_cancel(rfi_session* s, uint64_t ticket);
+/* Copy a done ticket's per-cell results into HOST buffers of nsub * nchan
+ * elements (each pointer nullable). Synchronous. */
+rfi_status rfi_result_copy(rfi_session* s, uint64_t ticket, double* stat, uint8_t* cell_status,
+                           uint8_t* mask);
+/* Free a done ticket's result buffers and budget. */
+rfi_status rfi_result_release(rfi_session* s, uint64_t ticket);
+/* Checkpoint / resume of a stream (clip state, fit history, partial
+ * sub-interval). Export waits for the stream's blocks; *nbytes is in/out
+ * (host_buf NULL: query the size). Import needs an open stream of the same
+ * nbeam, nchan and L with no block in flight. */
+rfi_status rfi_stream_export(rfi_session* s, int32_t stream_id, void* host_buf, size_t* nbytes);
+rfi_status rfi_stream_import(rfi_session* s, int32_t stream_id, const void* host_buf,
+                             size_t nbytes);
+
 /* Message for the last error returned on the calling thread ("" if none). */
 const char* rfi_last_error(void);
 

@@ -1,0 +1,772 @@
+// Serving runtime: continuous batching of observation blocks from many
+// streams on one device (the session API of rfi.h).
+//
+// A scheduler thread owns the device work. Queued blocks are admitted in
+// submission order whenever an execution slot is free and the HBM budget
+// allows; a block of a stream never overtakes an earlier queued block of the
+// same stream, but blocks of other streams may pass a block that does not
+// fit yet (no head-of-line blocking). Each slot is a non-blocking HIP stream
+// with its own helper stream, workspace and clip summary buffers, so admitted
+// blocks of different streams run concurrently. Blocks of one stream are
+// chained by a per-stream event, because each reads and writes that stream's
+// device state: the pooled clip state and fit history, and the carry of the
+// partial sub-interval. Completion is observed by polling per-block events.
+//
+// Per block (all on the slot's stream, after the stream's previous block):
+//   1. if the stream carries c samples of a sub-interval, the first L - c
+//      samples are added into the carry sums and, when that completes it,
+//      the eigen stage runs on that one row of cells (row 0 of the block);
+//   2. the full sub-intervals that follow run through the grouped sums ->
+//      eigen pipeline of the whole-block call;
+//   3. the remaining samples start a new carry;
+//   4. the clip over all of the block's cells, pooled with the stream state.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+#include "pipeline.h"
+#include "rfi.h"
+
+namespace rfi {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+constexpr int kMaxSlots = 64;
+constexpr int64_t kDefaultBudget = (int64_t)64 << 30;
+constexpr size_t kAlign = 256;
+inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct StreamCtx {
+  int id = 0;
+  rfi_stream_config cfg{};
+  uint8_t* protect = nullptr;        // device copy of the preserved-channel flags
+  rfi_stream_state* state = nullptr; // device
+  int32_t* carry = nullptr;          // device: sum_x [nbeam][nchan], sum_xy [npair][nchan], count
+  int64_t carry_samples = 0;         // samples in the carry after the last admitted block
+  hipEvent_t last = nullptr;         // completion of the stream's last admitted block
+  bool has_last = false;
+  int queued = 0, inflight = 0;
+  int32_t* carry_sx() const { return carry; }
+  int32_t* carry_sxy() const { return carry + (size_t)cfg.nbeam * cfg.nchan; }
+  int32_t* carry_cnt() const {
+    return carry + (size_t)(cfg.nbeam + npair_of(cfg.nbeam)) * cfg.nchan;
+  }
+  size_t carry_bytes() const {
+    return ((size_t)(cfg.nbeam + npair_of(cfg.nbeam)) * cfg.nchan + 1) * sizeof(int32_t);
+  }
+};
+
+enum class RState { Queued, Running, Done };
+
+struct Request {
+  uint64_t ticket = 0, tag = 0;
+  int stream_id = 0;
+  rfi_block blk{};
+  RState st = RState::Queued;
+  rfi_status status = RFI_OK;
+  int nsub = 0, carried = 0;
+  int64_t carry_after = 0;
+  int64_t charge_run = 0, charge_res = 0;
+  void* res = nullptr;               // stat | cell status | mask, one allocation
+  double* stat = nullptr;
+  uint8_t* cstat = nullptr;
+  uint8_t* mask = nullptr;
+  rfi_flag_stats flag{};
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int slot = -1;
+  hipEvent_t done = nullptr;
+};
+
+struct Slot {
+  hipStream_t s = nullptr;
+  PipeEvents ev;
+  void* ws = nullptr;
+  size_t ws_size = 0;
+  rfi_flag_stats* dstats = nullptr;  // device
+  rfi_flag_stats* hstats = nullptr;  // pinned host
+  Request* req = nullptr;
+};
+
+// The device stays current for the calling thread only inside the guard.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+}  // namespace rfi
+
+struct rfi_session {
+  int device = 0;
+  int max_slots = 8;
+  int64_t budget = rfi::kDefaultBudget;
+  std::mutex mu;
+  std::condition_variable cv_work;   // new work / stop, for the scheduler
+  std::condition_variable cv_done;   // a block finished, for waiters
+  std::thread sched;
+  bool stop = false;
+  std::deque<rfi::Request*> queue;
+  std::map<uint64_t, std::unique_ptr<rfi::Request>> reqs;
+  std::map<int, std::unique_ptr<rfi::StreamCtx>> streams;
+  std::vector<rfi::Slot> slots;
+  int running = 0;
+  int64_t charged = 0;
+  uint64_t next_ticket = 1;
+  int next_stream = 1;
+  rfi::Clock::time_point t0;
+  hipStream_t free_stream = nullptr;  // stream-ordered frees of released memory
+  // The clip kernel is grid-wide (all its workgroups co-resident, meeting at
+  // a grid barrier): two of them running at once could each hold part of the
+  // device and wait for the other. Clip launches of all slots are therefore
+  // chained through this event, in admission order.
+  hipEvent_t flag_chain = nullptr;
+  bool flag_chain_used = false;
+
+  double now_us() const {
+    return std::chrono::duration<double, std::micro>(rfi::Clock::now() - t0).count();
+  }
+  void scheduler();
+  bool admit(rfi::Request* r);        // false: does not fit now
+  rfi_status enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& st);
+  void finish(rfi::Slot& sl, bool ok);
+};
+
+namespace rfi {
+namespace {
+
+// Cells, carry and buffer sizes of a block given the stream's carry.
+struct BlockPlan {
+  int64_t t_full = 0;   // first sample of the full sub-intervals
+  int carried = 0;      // the carry sub-interval completes in this block
+  int64_t carry_add = 0;  // samples added to the carry before t_full
+  int nfull = 0;
+  int64_t rem = 0;      // samples after the full sub-intervals
+  int64_t carry_after = 0;
+  int nsub = 0;
+  ProcessPlan pl;       // for max(nfull, 1) sub-intervals
+  size_t ws = 0, res = 0;
+};
+
+rfi_status plan_block(const StreamCtx& st, int64_t nsamp, BlockPlan* b, const char* who) {
+  const int64_t L = st.cfg.L, c = st.carry_samples;
+  int64_t t = 0;
+  if (c > 0) {
+    const int64_t need = L - c;
+    if (nsamp >= need) {
+      b->carried = 1;
+      b->carry_add = need;
+      t = need;
+    } else {
+      b->carry_add = nsamp;
+      t = nsamp;
+    }
+  }
+  b->t_full = t;
+  const bool open_carry = c > 0 && !b->carried;
+  b->nfull = open_carry ? 0 : (int)((nsamp - t) / L);
+  b->rem = open_carry ? 0 : nsamp - t - (int64_t)b->nfull * L;
+  b->carry_after = open_carry ? c + nsamp : b->rem;
+  b->nsub = b->carried + b->nfull;
+  if ((int64_t)b->nsub * st.cfg.nchan > ((int64_t)1 << 30))
+    return fail(RFI_E_INVALID, "%s: block has more than 2^30 cells", who);
+  rfi_process_params p{};
+  p.L = (int32_t)L;
+  p.nsub = b->nfull > 0 ? b->nfull : 1;
+  p.eig_precision = st.cfg.eig_precision;
+  p.max_sweeps = st.cfg.max_sweeps;
+  p.max_iter = st.cfg.max_iter;
+  p.kappa = st.cfg.kappa;
+  // the clip covers nsub rows; its workspace does not depend on the size
+  rfi_status s = resolve_process(st.cfg.nbeam, st.cfg.nchan, &p, &b->pl, who);
+  if (s != RFI_OK) return s;
+  b->ws = b->pl.ws_bytes;
+  const size_t ncell = (size_t)b->nsub * st.cfg.nchan;
+  b->res = ncell ? up(ncell * 8) + up(ncell) + up(ncell) : 0;
+  return RFI_OK;
+}
+
+int64_t input_bytes(const rfi_block& blk) {
+  return (int64_t)blk.nbeam * blk.nsamp * blk.row_stride;
+}
+
+}  // namespace
+}  // namespace rfi
+
+using rfi::fail;
+
+rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& st) {
+  using namespace rfi;
+  hipError_t e;
+  BlockPlan b;
+  rfi_status rs = plan_block(st, r->blk.nsamp, &b, "rfi_submit");
+  if (rs != RFI_OK) return rs;
+  BeamPtrs bp;
+  std::memset(&bp, 0, sizeof(bp));
+  for (int i = 0; i < r->blk.nbeam; ++i) bp.p[i] = r->blk.beam[i];
+  const int n = st.cfg.nbeam, F = st.cfg.nchan, L = st.cfg.L;
+  const int64_t stride = r->blk.row_stride;
+  hipStream_t s = sl.s;
+  auto dev = [&](hipError_t err, const char* what) {
+    return err == hipSuccess ? RFI_OK : check_hip(err, what);
+  };
+  if (st.has_last && (e = hipStreamWaitEvent(s, st.last, 0)) != hipSuccess)
+    return dev(e, "rfi_submit: stream order");
+  if (sl.ws_size < b.ws) {
+    if (sl.ws) (void)hipFreeAsync(sl.ws, s);
+    sl.ws = nullptr;
+    sl.ws_size = 0;
+    if ((e = hipMallocAsync(&sl.ws, b.ws, s)) != hipSuccess) return dev(e, "rfi_submit: workspace");
+    sl.ws_size = b.ws;
+  }
+  if (b.res) {
+    if ((e = hipMallocAsync(&r->res, b.res, s)) != hipSuccess) return dev(e, "rfi_submit: results");
+    const size_t ncell = (size_t)b.nsub * F;
+    r->stat = (double*)r->res;
+    r->cstat = (uint8_t*)r->res + up(ncell * 8);
+    r->mask = r->cstat + up(ncell);
+  }
+  // 1. complete (or extend) the carried sub-interval
+  if (b.carry_add > 0) {
+    e = launch_ccm_mfma(bp, n, F, stride, 0, (int)b.carry_add, 1, st.carry_sx(), st.carry_sxy(),
+                        st.carry_cnt(), 1, 0, s);
+    if (e != hipSuccess) return dev(e, "rfi_submit: carry sums");
+  }
+  if (b.carried) {
+    EigArgs a{n, 1, F, st.carry_sx(), st.carry_sxy(), st.carry_cnt(), b.pl.eig.max_sweeps, 1,
+              nullptr, r->stat, nullptr, r->cstat, (int64_t)b.nsub * F};
+    e = b.pl.eig.solver == RFI_EIG_LANE ? launch_eig_lane(a, s)
+                                        : launch_eig_wave(a, b.pl.eig.precision, s);
+    if (e != hipSuccess) return dev(e, "rfi_submit: carry eigen stage");
+  }
+  // 2. full sub-intervals
+  if (b.nfull > 0) {
+    ProcessPlan pl = b.pl;
+    char* ws = (char*)sl.ws;
+    e = enqueue_eig_groups(bp, stride, b.t_full, L, pl, r->stat + (size_t)b.carried * F,
+                           r->cstat + (size_t)b.carried * F, nullptr, nullptr,
+                           (int64_t)b.nsub * F, ws + pl.flag_ws, sl.ev, s);
+    if (e != hipSuccess) return dev(e, "rfi_submit: sums / eigen stage");
+  }
+  // 3. new carry
+  if (b.rem > 0) {
+    e = launch_ccm_mfma(bp, n, F, stride, b.t_full + (int64_t)b.nfull * L, (int)b.rem, 1,
+                        st.carry_sx(), st.carry_sxy(), st.carry_cnt(), 0, 0, s);
+    if (e != hipSuccess) return dev(e, "rfi_submit: new carry");
+  }
+  // 4. clip, pooled with the stream state (after the previous clip of any slot)
+  if (b.nsub > 0) {
+    if (flag_chain_used && (e = hipStreamWaitEvent(s, flag_chain, 0)) != hipSuccess)
+      return dev(e, "rfi_submit: clip order");
+    e = launch_flag(b.nsub, F, r->stat, r->cstat, st.protect, st.cfg.kappa, b.pl.max_iter,
+                    st.state, r->mask, sl.dstats, sl.ws, s);
+    if (e != hipSuccess) return dev(e, "rfi_submit: clip");
+    if ((e = hipEventRecord(flag_chain, s)) != hipSuccess) return dev(e, "rfi_submit: clip order");
+    flag_chain_used = true;
+    if ((e = hipMemcpyAsync(sl.hstats, sl.dstats, sizeof(rfi_flag_stats), hipMemcpyDeviceToHost,
+                            s)) != hipSuccess)
+      return dev(e, "rfi_submit: clip summary");
+  }
+  if ((e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming)) != hipSuccess)
+    return dev(e, "rfi_submit: event");
+  if ((e = hipEventRecord(r->done, s)) != hipSuccess) return dev(e, "rfi_submit: event");
+  if ((e = hipEventRecord(st.last, s)) != hipSuccess) return dev(e, "rfi_submit: event");
+  st.has_last = true;
+  r->nsub = b.nsub;
+  r->carried = b.carried;
+  r->carry_after = b.carry_after;
+  st.carry_samples = b.carry_after;
+  return RFI_OK;
+}
+
+bool rfi_session::admit(rfi::Request* r) {
+  using namespace rfi;
+  StreamCtx& st = *streams.at(r->stream_id);
+  BlockPlan b;
+  if (plan_block(st, r->blk.nsamp, &b, "rfi_submit") != RFI_OK) {
+    r->status = RFI_E_INVALID;
+    r->st = RState::Done;
+    r->t_admit = r->t_done = now_us();
+    st.queued--;
+    cv_done.notify_all();
+    return true;
+  }
+  const int64_t run = input_bytes(r->blk) + (int64_t)b.ws;
+  const int64_t res = (int64_t)b.res;
+  if (charged + run + res > budget && running > 0) return false;
+  int si = -1;
+  for (int i = 0; i < (int)slots.size(); ++i)
+    if (!slots[i].req) { si = i; break; }
+  if (si < 0) return false;
+  Slot& sl = slots[si];
+  r->t_admit = now_us();
+  st.queued--;
+  const rfi_status rs = enqueue(r, sl, st);
+  r->charge_run = run;
+  r->charge_res = res;
+  charged += run + res;
+  if (rs != RFI_OK) {
+    // nothing more of this block is queued; the work already enqueued runs out
+    // before the slot is reused (the slot's stream is in order)
+    r->status = rs;
+    r->st = RState::Done;
+    r->t_done = now_us();
+    charged -= r->charge_run;
+    r->charge_run = 0;
+    cv_done.notify_all();
+    return true;
+  }
+  r->st = RState::Running;
+  r->slot = si;
+  sl.req = r;
+  st.inflight++;
+  running++;
+  return true;
+}
+
+void rfi_session::finish(rfi::Slot& sl, bool ok) {
+  using namespace rfi;
+  Request* r = sl.req;
+  StreamCtx& st = *streams.at(r->stream_id);
+  if (ok) {
+    if (r->nsub > 0) r->flag = *sl.hstats;
+  } else {
+    r->status = RFI_E_DEVICE;
+  }
+  r->st = RState::Done;
+  r->t_done = now_us();
+  r->slot = -1;
+  sl.req = nullptr;
+  charged -= r->charge_run;
+  r->charge_run = 0;
+  st.inflight--;
+  running--;
+  cv_done.notify_all();
+}
+
+void rfi_session::scheduler() {
+  using namespace rfi;
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // completions
+    for (Slot& sl : slots) {
+      if (!sl.req) continue;
+      const hipError_t q = hipEventQuery(sl.req->done);
+      if (q == hipSuccess) finish(sl, true);
+      else if (q != hipErrorNotReady) finish(sl, false);
+    }
+    // admissions: submission order; a stream's later block waits behind its
+    // earlier queued one, other streams may pass
+    std::vector<int> blocked;
+    for (auto it = queue.begin(); it != queue.end();) {
+      Request* r = *it;
+      if (std::find(blocked.begin(), blocked.end(), r->stream_id) != blocked.end()) {
+        ++it;
+        continue;
+      }
+      if (admit(r)) {
+        it = queue.erase(it);
+      } else {
+        blocked.push_back(r->stream_id);
+        ++it;
+      }
+    }
+    if (stop && queue.empty() && running == 0) break;
+    if (running > 0)
+      cv_work.wait_for(lk, std::chrono::microseconds(20));
+    else
+      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+  }
+}
+
+extern "C" {
+
+rfi_status rfi_session_create(const rfi_session_config* cfg, rfi_session** out) {
+  rfi::clear_error();
+  const char* who = "rfi_session_create";
+  if (!out) return fail(RFI_E_INVALID, "%s: out is NULL", who);
+  *out = nullptr;
+  rfi_session_config c{0, 8, rfi::kDefaultBudget};
+  if (cfg) c = *cfg;
+  if (c.max_inflight == 0) c.max_inflight = 8;
+  if (c.hbm_budget == 0) c.hbm_budget = rfi::kDefaultBudget;
+  if (c.max_inflight < 1 || c.max_inflight > rfi::kMaxSlots)
+    return fail(RFI_E_INVALID, "%s: max_inflight %d outside 1..%d", who, c.max_inflight,
+                rfi::kMaxSlots);
+  if (c.hbm_budget < 0) return fail(RFI_E_INVALID, "%s: negative budget", who);
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) return fail(RFI_E_DEVICE, "%s: no HIP device", who);
+  if (c.device < 0 || c.device >= ndev)
+    return fail(RFI_E_INVALID, "%s: device %d outside 0..%d", who, c.device, ndev - 1);
+  std::unique_ptr<rfi_session> s(new rfi_session);
+  s->device = c.device;
+  s->max_slots = c.max_inflight;
+  s->budget = c.hbm_budget;
+  s->t0 = rfi::Clock::now();
+  rfi::DeviceGuard g(s->device);
+  s->slots.resize(s->max_slots);
+  for (rfi::Slot& sl : s->slots) {
+    if ((e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking)) != hipSuccess ||
+        (e = sl.ev.init()) != hipSuccess ||
+        (e = hipMalloc((void**)&sl.dstats, sizeof(rfi_flag_stats))) != hipSuccess ||
+        (e = hipHostMalloc((void**)&sl.hstats, sizeof(rfi_flag_stats), 0)) != hipSuccess) {
+      rfi_session_destroy(s.release());
+      return rfi::check_hip(e, "rfi_session_create: slot");
+    }
+  }
+  if ((e = hipStreamCreateWithFlags(&s->free_stream, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&s->flag_chain, hipEventDisableTiming)) != hipSuccess) {
+    rfi_session_destroy(s.release());
+    return rfi::check_hip(e, "rfi_session_create: stream");
+  }
+  rfi_session* raw = s.release();
+  raw->sched = std::thread([raw] { raw->scheduler(); });
+  *out = raw;
+  return RFI_OK;
+}
+
+void rfi_session_destroy(rfi_session* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (rfi::Request* r : s->queue) {
+      r->status = RFI_E_CANCELLED;
+      r->st = rfi::RState::Done;
+      s->streams.at(r->stream_id)->queued--;
+    }
+    s->queue.clear();
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->sched.joinable()) s->sched.join();
+  rfi::DeviceGuard g(s->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : s->reqs) {
+    if (kv.second->res) (void)hipFree(kv.second->res);
+    if (kv.second->done) (void)hipEventDestroy(kv.second->done);
+  }
+  for (auto& kv : s->streams) {
+    rfi::StreamCtx& st = *kv.second;
+    if (st.protect) (void)hipFree(st.protect);
+    if (st.state) (void)hipFree(st.state);
+    if (st.carry) (void)hipFree(st.carry);
+    if (st.last) (void)hipEventDestroy(st.last);
+  }
+  for (rfi::Slot& sl : s->slots) {
+    if (sl.ws) (void)hipFree(sl.ws);
+    if (sl.dstats) (void)hipFree(sl.dstats);
+    if (sl.hstats) (void)hipHostFree(sl.hstats);
+    sl.ev.destroy();
+    if (sl.s) (void)hipStreamDestroy(sl.s);
+  }
+  if (s->free_stream) (void)hipStreamDestroy(s->free_stream);
+  if (s->flag_chain) (void)hipEventDestroy(s->flag_chain);
+  delete s;
+}
+
+rfi_status rfi_stream_open(rfi_session* s, const rfi_stream_config* c, int32_t* stream_id) {
+  rfi::clear_error();
+  const char* who = "rfi_stream_open";
+  if (!s || !c || !stream_id) return fail(RFI_E_INVALID, "%s: NULL argument", who);
+  rfi_stream_config cfg = *c;
+  if (cfg.eig_precision == 0) cfg.eig_precision = 32;
+  if (cfg.max_sweeps == 0) cfg.max_sweeps = 12;
+  if (cfg.max_iter == 0) cfg.max_iter = 50;
+  if (cfg.L < 1 || cfg.L > RFI_MAX_COUNT)
+    return fail(RFI_E_INVALID, "%s: L %d outside 1..%d", who, cfg.L, RFI_MAX_COUNT);
+  if (!(cfg.kappa >= 0.0)) return fail(RFI_E_INVALID, "%s: kappa must be >= 0", who);
+  if (cfg.max_iter < 1) return fail(RFI_E_INVALID, "%s: max_iter %d < 1", who, cfg.max_iter);
+  rfi::ProcessPlan pl;
+  rfi_process_params p{};
+  p.L = cfg.L;
+  p.nsub = 1;
+  p.eig_precision = cfg.eig_precision;
+  p.max_sweeps = cfg.max_sweeps;
+  p.max_iter = cfg.max_iter;
+  p.kappa = cfg.kappa;
+  rfi_status rs = rfi::resolve_process(cfg.nbeam, cfg.nchan, &p, &pl, who);
+  if (rs != RFI_OK) return rs;
+  std::unique_ptr<rfi::StreamCtx> st(new rfi::StreamCtx);
+  st->cfg = cfg;
+  st->cfg.protect_chan = nullptr;
+  rfi::DeviceGuard g(s->device);
+  hipError_t e;
+  auto bad = [&](hipError_t err) {
+    if (st->protect) (void)hipFree(st->protect);
+    if (st->state) (void)hipFree(st->state);
+    if (st->carry) (void)hipFree(st->carry);
+    if (st->last) (void)hipEventDestroy(st->last);
+    return rfi::check_hip(err, "rfi_stream_open");
+  };
+  if ((e = hipMalloc((void**)&st->state, sizeof(rfi_stream_state))) != hipSuccess ||
+      (e = hipMemset(st->state, 0, sizeof(rfi_stream_state))) != hipSuccess ||
+      (e = hipMalloc((void**)&st->carry, st->carry_bytes())) != hipSuccess ||
+      (e = hipMemset(st->carry, 0, st->carry_bytes())) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&st->last, hipEventDisableTiming)) != hipSuccess)
+    return bad(e);
+  if (c->protect_chan) {
+    if ((e = hipMalloc((void**)&st->protect, cfg.nchan)) != hipSuccess ||
+        (e = hipMemcpy(st->protect, c->protect_chan, cfg.nchan, hipMemcpyHostToDevice)) !=
+            hipSuccess)
+      return bad(e);
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  st->id = s->next_stream++;
+  *stream_id = st->id;
+  s->streams[st->id] = std::move(st);
+  return RFI_OK;
+}
+
+rfi_status rfi_submit(rfi_session* s, int32_t stream_id, const rfi_block* blk, uint64_t user_tag,
+                      uint64_t* ticket) {
+  rfi::clear_error();
+  const char* who = "rfi_submit";
+  if (!s || !blk || !ticket) return fail(RFI_E_INVALID, "%s: NULL argument", who);
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->streams.find(stream_id);
+  if (it == s->streams.end()) return fail(RFI_E_INVALID, "%s: unknown stream %d", who, stream_id);
+  rfi::StreamCtx& st = *it->second;
+  if (blk->nbeam != st.cfg.nbeam || blk->nchan != st.cfg.nchan)
+    return fail(RFI_E_INVALID, "%s: block shape %d x %d differs from the stream's %d x %d", who,
+                blk->nbeam, blk->nchan, st.cfg.nbeam, st.cfg.nchan);
+  if (blk->nsamp < 0) return fail(RFI_E_INVALID, "%s: nsamp < 0", who);
+  rfi::BeamPtrs bp;
+  rfi_status rs = rfi::validate_block(blk, 0, st.cfg.L, 0, who, &bp);
+  if (rs != RFI_OK) return rs;
+  if (rfi::input_bytes(*blk) > s->budget)
+    return fail(RFI_E_BUDGET, "%s: block of %lld bytes exceeds the budget of %lld", who,
+                (long long)rfi::input_bytes(*blk), (long long)s->budget);
+  std::unique_ptr<rfi::Request> r(new rfi::Request);
+  r->ticket = s->next_ticket++;
+  r->tag = user_tag;
+  r->stream_id = stream_id;
+  r->blk = *blk;
+  r->t_submit = s->now_us();
+  *ticket = r->ticket;
+  st.queued++;
+  s->queue.push_back(r.get());
+  s->reqs[r->ticket] = std::move(r);
+  lk.unlock();
+  s->cv_work.notify_one();
+  return RFI_OK;
+}
+
+static void fill_result(const rfi::Request& r, rfi_result* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->ticket = r.ticket;
+  out->user_tag = r.tag;
+  out->stream_id = r.stream_id;
+  out->status = r.status;
+  out->nsub = r.nsub;
+  out->nchan = r.blk.nchan;
+  out->carried = r.carried;
+  out->carry_samples = r.carry_after;
+  out->stat = r.stat;
+  out->cell_status = r.cstat;
+  out->mask = r.mask;
+  out->flag = r.flag;
+  out->t_submit_us = r.t_submit;
+  out->t_admit_us = r.t_admit;
+  out->t_done_us = r.t_done;
+}
+
+rfi_status rfi_poll(rfi_session* s, uint64_t ticket, rfi_result* r) {
+  rfi::clear_error();
+  if (!s || !r) return fail(RFI_E_INVALID, "rfi_poll: NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(RFI_E_INVALID, "rfi_poll: unknown ticket %llu",
+                                       (unsigned long long)ticket);
+  if (it->second->st != rfi::RState::Done) return RFI_E_NOT_READY;
+  fill_result(*it->second, r);
+  return RFI_OK;
+}
+
+rfi_status rfi_wait(rfi_session* s, uint64_t ticket, int64_t timeout_us, rfi_result* r) {
+  rfi::clear_error();
+  if (!s || !r) return fail(RFI_E_INVALID, "rfi_wait: NULL argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(RFI_E_INVALID, "rfi_wait: unknown ticket %llu",
+                                       (unsigned long long)ticket);
+  rfi::Request* q = it->second.get();
+  auto ready = [&] { return q->st == rfi::RState::Done; };
+  if (timeout_us < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    return fail(RFI_E_TIMEOUT, "rfi_wait: ticket %llu not done after %lld us",
+                (unsigned long long)ticket, (long long)timeout_us);
+  }
+  fill_result(*q, r);
+  return RFI_OK;
+}
+
+rfi_status rfi_cancel(rfi_session* s, uint64_t ticket) {
+  rfi::clear_error();
+  if (!s) return fail(RFI_E_INVALID, "rfi_cancel: NULL session");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(RFI_E_INVALID, "rfi_cancel: unknown ticket");
+  rfi::Request* r = it->second.get();
+  if (r->st != rfi::RState::Queued) return RFI_E_NOT_READY;
+  s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+  s->streams.at(r->stream_id)->queued--;
+  r->status = RFI_E_CANCELLED;
+  r->st = rfi::RState::Done;
+  r->t_admit = r->t_done = s->now_us();
+  s->cv_done.notify_all();
+  return RFI_OK;
+}
+
+rfi_status rfi_result_copy(rfi_session* s, uint64_t ticket, double* stat, uint8_t* cell_status,
+                           uint8_t* mask) {
+  rfi::clear_error();
+  if (!s) return fail(RFI_E_INVALID, "rfi_result_copy: NULL session");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(RFI_E_INVALID, "rfi_result_copy: unknown ticket");
+  rfi::Request* r = it->second.get();
+  if (r->st != rfi::RState::Done)
+    return fail(RFI_E_NOT_READY, "rfi_result_copy: ticket still queued or running");
+  const size_t n = (size_t)r->nsub * r->blk.nchan;
+  if (n == 0 || !r->res) return RFI_OK;
+  rfi::DeviceGuard g(s->device);
+  hipError_t e = hipSuccess;
+  if (stat) e = hipMemcpy(stat, r->stat, n * sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && cell_status)
+    e = hipMemcpy(cell_status, r->cstat, n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && mask) e = hipMemcpy(mask, r->mask, n, hipMemcpyDeviceToHost);
+  return rfi::check_hip(e, "rfi_result_copy");
+}
+
+rfi_status rfi_result_release(rfi_session* s, uint64_t ticket) {
+  rfi::clear_error();
+  if (!s) return fail(RFI_E_INVALID, "rfi_result_release: NULL session");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(RFI_E_INVALID, "rfi_result_release: unknown ticket");
+  rfi::Request* r = it->second.get();
+  if (r->st != rfi::RState::Done)
+    return fail(RFI_E_NOT_READY, "rfi_result_release: ticket still queued or running");
+  rfi::DeviceGuard g(s->device);
+  if (r->res) (void)hipFreeAsync(r->res, s->free_stream);
+  if (r->done) (void)hipEventDestroy(r->done);
+  s->charged -= r->charge_res;
+  s->reqs.erase(it);
+  s->cv_work.notify_one();   // budget freed
+  return RFI_OK;
+}
+
+// Wait (holding lk) until the stream has nothing queued or running.
+static rfi::StreamCtx* idle_stream(rfi_session* s, std::unique_lock<std::mutex>& lk, int id,
+                                   const char* who) {
+  auto it = s->streams.find(id);
+  if (it == s->streams.end()) {
+    fail(RFI_E_INVALID, "%s: unknown stream %d", who, id);
+    return nullptr;
+  }
+  rfi::StreamCtx* st = it->second.get();
+  s->cv_done.wait(lk, [&] { return st->queued == 0 && st->inflight == 0; });
+  return st;
+}
+
+rfi_status rfi_stream_close(rfi_session* s, int32_t stream_id) {
+  rfi::clear_error();
+  if (!s) return fail(RFI_E_INVALID, "rfi_stream_close: NULL session");
+  std::unique_lock<std::mutex> lk(s->mu);
+  rfi::StreamCtx* st = idle_stream(s, lk, stream_id, "rfi_stream_close");
+  if (!st) return RFI_E_INVALID;
+  rfi::DeviceGuard g(s->device);
+  (void)hipEventSynchronize(st->last);
+  if (st->protect) (void)hipFree(st->protect);
+  (void)hipFree(st->state);
+  (void)hipFree(st->carry);
+  (void)hipEventDestroy(st->last);
+  s->streams.erase(stream_id);
+  return RFI_OK;
+}
+
+namespace {
+struct ExportHeader {
+  uint32_t magic, version;
+  int32_t nbeam, nchan, L, pad;
+  int64_t carry_samples;
+};
+constexpr uint32_t kMagic = 0x52464953u;   // "RFIS"
+}  // namespace
+
+rfi_status rfi_stream_export(rfi_session* s, int32_t stream_id, void* host_buf, size_t* nbytes) {
+  rfi::clear_error();
+  const char* who = "rfi_stream_export";
+  if (!s || !nbytes) return fail(RFI_E_INVALID, "%s: NULL argument", who);
+  std::unique_lock<std::mutex> lk(s->mu);
+  rfi::StreamCtx* st = idle_stream(s, lk, stream_id, who);
+  if (!st) return RFI_E_INVALID;
+  const size_t need = sizeof(ExportHeader) + sizeof(rfi_stream_state) + st->carry_bytes();
+  if (!host_buf) {
+    *nbytes = need;
+    return RFI_OK;
+  }
+  if (*nbytes < need) return fail(RFI_E_INVALID, "%s: buffer of %zu bytes < %zu", who, *nbytes, need);
+  rfi::DeviceGuard g(s->device);
+  hipError_t e = hipEventSynchronize(st->last);
+  ExportHeader h{kMagic, 1, st->cfg.nbeam, st->cfg.nchan, st->cfg.L, 0, st->carry_samples};
+  char* p = (char*)host_buf;
+  std::memcpy(p, &h, sizeof(h));
+  if (e == hipSuccess)
+    e = hipMemcpy(p + sizeof(h), st->state, sizeof(rfi_stream_state), hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(p + sizeof(h) + sizeof(rfi_stream_state), st->carry, st->carry_bytes(),
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return rfi::check_hip(e, who);
+  *nbytes = need;
+  return RFI_OK;
+}
+
+rfi_status rfi_stream_import(rfi_session* s, int32_t stream_id, const void* host_buf,
+                             size_t nbytes) {
+  rfi::clear_error();
+  const char* who = "rfi_stream_import";
+  if (!s || !host_buf) return fail(RFI_E_INVALID, "%s: NULL argument", who);
+  std::unique_lock<std::mutex> lk(s->mu);
+  rfi::StreamCtx* st = idle_stream(s, lk, stream_id, who);
+  if (!st) return RFI_E_INVALID;
+  const size_t need = sizeof(ExportHeader) + sizeof(rfi_stream_state) + st->carry_bytes();
+  ExportHeader h;
+  if (nbytes < sizeof(h)) return fail(RFI_E_INVALID, "%s: buffer too small", who);
+  std::memcpy(&h, host_buf, sizeof(h));
+  if (h.magic != kMagic || h.version != 1 || h.nbeam != st->cfg.nbeam ||
+      h.nchan != st->cfg.nchan || h.L != st->cfg.L || nbytes != need || h.carry_samples < 0 ||
+      h.carry_samples >= st->cfg.L)
+    return fail(RFI_E_INVALID, "%s: checkpoint does not match the stream", who);
+  rfi::DeviceGuard g(s->device);
+  const char* p = (const char*)host_buf;
+  hipError_t e = hipEventSynchronize(st->last);
+  if (e == hipSuccess)
+    e = hipMemcpy(st->state, p + sizeof(h), sizeof(rfi_stream_state), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(st->carry, p + sizeof(h) + sizeof(rfi_stream_state), st->carry_bytes(),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return rfi::check_hip(e, who);
+  st->carry_samples = h.carry_samples;
+  return RFI_OK;
+}
+
+}  // extern "C"

@@ -64,6 +64,25 @@ class rfi_process_params(C.Structure):
                 ("kappa", C.c_double)]
 
 
+class rfi_session_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32), ("hbm_budget", C.c_int64)]
+
+
+class rfi_stream_config(C.Structure):
+    _fields_ = [("nbeam", C.c_int32), ("nchan", C.c_int32), ("L", C.c_int32),
+                ("eig_precision", C.c_int32), ("max_sweeps", C.c_int32), ("max_iter", C.c_int32),
+                ("kappa", C.c_double), ("protect_chan", C.c_void_p)]
+
+
+class rfi_result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("user_tag", C.c_uint64), ("stream_id", C.c_int32),
+                ("status", C.c_int32), ("nsub", C.c_int32), ("nchan", C.c_int32),
+                ("carried", C.c_int32), ("carry_samples", C.c_int64), ("stat", C.c_void_p),
+                ("cell_status", C.c_void_p), ("mask", C.c_void_p), ("flag", rfi_flag_stats),
+                ("t_submit_us", C.c_double), ("t_admit_us", C.c_double),
+                ("t_done_us", C.c_double)]
+
+
 class rfi_synth_spec(C.Structure):
     _fields_ = [("nbeam", C.c_int32), ("nchan", C.c_int32), ("nsamp", C.c_int64),
                 ("row_stride", C.c_int64), ("key0", C.c_uint32), ("key1", C.c_uint32),
@@ -106,8 +125,25 @@ def lib():
         L.rfi_process_workspace_size.restype = C.c_size_t
         L.rfi_process_block.argtypes = [C.POINTER(rfi_block), C.POINTER(rfi_process_params),
                                         vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        u64 = C.c_uint64
+        L.rfi_session_create.argtypes = [C.POINTER(rfi_session_config), C.POINTER(vp)]
+        L.rfi_session_destroy.argtypes = [vp]
+        L.rfi_session_destroy.restype = None
+        L.rfi_stream_open.argtypes = [vp, C.POINTER(rfi_stream_config), C.POINTER(i32)]
+        L.rfi_stream_close.argtypes = [vp, i32]
+        L.rfi_submit.argtypes = [vp, i32, C.POINTER(rfi_block), u64, C.POINTER(u64)]
+        L.rfi_poll.argtypes = [vp, u64, C.POINTER(rfi_result)]
+        L.rfi_wait.argtypes = [vp, u64, i64, C.POINTER(rfi_result)]
+        L.rfi_cancel.argtypes = [vp, u64]
+        L.rfi_result_release.argtypes = [vp, u64]
+        L.rfi_result_copy.argtypes = [vp, u64, vp, vp, vp]
+        L.rfi_stream_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
+        L.rfi_stream_import.argtypes = [vp, i32, vp, C.c_size_t]
         for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_eigvec_flag",
-                  "rfi_process_block"):
+                  "rfi_process_block", "rfi_session_create", "rfi_stream_open",
+                  "rfi_stream_close", "rfi_submit", "rfi_poll", "rfi_wait", "rfi_cancel",
+                  "rfi_result_release", "rfi_stream_export", "rfi_stream_import",
+                  "rfi_result_copy"):
             getattr(L, f).restype = i32
         L.rfi_last_error.restype = C.c_char_p
         L.rfi_version.restype = C.c_char_p
@@ -210,6 +246,90 @@ def rfi_eigvec_flag(nbeam, nsub, nchan, v1, mask, status, beam_mask, protect_cha
     _check(lib().rfi_eigvec_flag(int(nbeam), int(nsub), int(nchan), _ptr(v1), _ptr(mask),
                                  _ptr(status), _ptr(protect_chan), float(kappa_v), _ptr(beam_mask),
                                  _ptr(beam_mu), _ptr(beam_sigma), _stream(stream)))
+
+
+# --- serving session ------------------------------------------------------------
+
+class Session:
+    """Thin wrapper of an rfi_session (continuous batching of blocks)."""
+
+    def __init__(self, device=0, max_inflight=8, hbm_budget=0):
+        self.h = C.c_void_p()
+        cfg = rfi_session_config(int(device), int(max_inflight), int(hbm_budget))
+        _check(lib().rfi_session_create(C.byref(cfg), C.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().rfi_session_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def open_stream(self, nbeam, nchan, L, kappa=3.0, max_iter=50, eig_precision=32,
+                    max_sweeps=12, protect_chan=None) -> int:
+        keep = None
+        pp = None
+        if protect_chan is not None:
+            keep = np.ascontiguousarray(np.asarray(protect_chan, dtype=np.uint8))
+            pp = keep.ctypes.data
+        cfg = rfi_stream_config(int(nbeam), int(nchan), int(L), int(eig_precision),
+                                int(max_sweeps), int(max_iter), float(kappa), pp)
+        sid = C.c_int32()
+        _check(lib().rfi_stream_open(self.h, C.byref(cfg), C.byref(sid)))
+        return sid.value
+
+    def close_stream(self, sid):
+        _check(lib().rfi_stream_close(self.h, int(sid)))
+
+    def submit(self, sid, blk: rfi_block, tag=0) -> int:
+        t = C.c_uint64()
+        _check(lib().rfi_submit(self.h, int(sid), C.byref(blk), int(tag), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket):
+        r = rfi_result()
+        code = lib().rfi_poll(self.h, int(ticket), C.byref(r))
+        if code == RFI_E_NOT_READY:
+            return None
+        _check(code)
+        return r
+
+    def wait(self, ticket, timeout_us=-1) -> rfi_result:
+        r = rfi_result()
+        _check(lib().rfi_wait(self.h, int(ticket), int(timeout_us), C.byref(r)))
+        return r
+
+    def cancel(self, ticket) -> int:
+        return int(lib().rfi_cancel(self.h, int(ticket)))
+
+    def release(self, ticket):
+        _check(lib().rfi_result_release(self.h, int(ticket)))
+
+    def export_stream(self, sid) -> bytes:
+        n = C.c_size_t(0)
+        _check(lib().rfi_stream_export(self.h, int(sid), None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().rfi_stream_export(self.h, int(sid), buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def import_stream(self, sid, raw: bytes):
+        buf = C.create_string_buffer(raw, len(raw))
+        _check(lib().rfi_stream_import(self.h, int(sid), buf, len(raw)))
+
+
+def result_arrays(sess: "Session", r: rfi_result):
+    """Host copies (stat, cell status, mask) of a done ticket's results."""
+    n = r.nsub * r.nchan
+    stat = np.zeros(n, dtype=np.float64)
+    cst = np.zeros(n, dtype=np.uint8)
+    mask = np.zeros(n, dtype=np.uint8)
+    _check(lib().rfi_result_copy(sess.h, r.ticket, stat.ctypes.data, cst.ctypes.data,
+                                 mask.ctypes.data))
+    return stat, cst, mask
 
 
 def flag_stats_from_bytes(raw: bytes) -> dict:

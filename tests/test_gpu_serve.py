@@ -1,0 +1,196 @@
+"""GPU: the serving session (continuous batching of blocks from many streams).
+
+* Each block's result is the same alone and in the mix: every stream is run
+  once through a one-slot session on its own, and once interleaved with the
+  other streams through a multi-slot session. Statistic, cell status and mask
+  must be bit-identical, and so must the clip summaries.
+* Against the oracle: the blocks of a stream are cut at arbitrary sample
+  counts, so sub-intervals span block boundaries (the carry). The oracle
+  forms the sub-intervals of the concatenated samples, and the cells of block
+  i are the sub-intervals that end inside it; the clip is the pooled stream
+  clip, block by block. Statistic within 1e-9, masks identical.
+* Export / import: a stream split across two sessions through a checkpoint
+  gives the same results as the uninterrupted stream.
+* Errors, cancellation, budget.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import say, upload
+from oracle import clip, pipeline
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2512_16278_amd import rfi
+    rfi.lib()
+    return torch.device("cuda:0")
+
+
+def _data(nbeam, nchan, nsamp, seed):
+    rng = np.random.default_rng(seed)
+    x = 128 + 20 * rng.standard_normal((nbeam, nsamp, nchan))
+    t = np.arange(nsamp)
+    for j in rng.choice(nchan, size=max(1, nchan // 30), replace=False):
+        g = rng.uniform(0.5, 1.5, nbeam)
+        x[:, :, j] += 12 * g[:, None] * np.sin(2 * np.pi * t / 29.0 + j)[None, :]
+    return np.clip(np.rint(x), 0, 255).astype(np.uint8)
+
+
+# (nbeam, nchan, L, block lengths in samples): lengths that are not multiples
+# of L, one shorter than L, so that carries open, extend and complete
+STREAMS = [
+    (19, 100, 256, [700, 300, 100, 900]),
+    (7, 64, 128, [128, 500, 77, 333]),
+    (36, 40, 300, [1000, 250, 650]),
+]
+
+
+def _blocks(dev, spec, seed):
+    nb, nc, L, lens = spec
+    x = _data(nb, nc, sum(lens), seed)
+    bufs, t = [], 0
+    for n in lens:
+        bufs.append(upload(x[:, t:t + n, :], dev))
+        t += n
+    return x, bufs
+
+
+def _run(sess, sid, bufs, nc):
+    from paper_2512_16278_amd import rfi
+    tickets = [sess.submit(sid, rfi.make_block(b, nc), tag=i) for i, b in enumerate(bufs)]
+    return tickets
+
+
+def _collect(sess, tickets):
+    from paper_2512_16278_amd import rfi
+    out = []
+    for t in tickets:
+        r = sess.wait(t, timeout_us=60_000_000)
+        assert r.status == rfi.RFI_OK, r.status
+        arrs = rfi.result_arrays(sess, r)
+        out.append((r.nsub, r.carried, r.carry_samples, arrs,
+                    (r.flag.mu, r.flag.sigma, r.flag.thr, r.flag.iterations, r.flag.nflag)))
+        sess.release(t)
+    return out
+
+
+def test_serve_alone_equals_mix_and_oracle(dev):
+    from paper_2512_16278_amd import rfi
+    data = [_blocks(dev, spec, 50 + i) for i, spec in enumerate(STREAMS)]
+    # alone: one stream at a time, one block at a time
+    alone = []
+    for (nb, nc, L, lens), (x, bufs) in zip(STREAMS, data):
+        say("serve: alone", nb, nc, L, lens)
+        with rfi.Session(max_inflight=1) as s:
+            sid = s.open_stream(nb, nc, L)
+            alone.append(_collect(s, _run(s, sid, bufs, nc)))
+    # mix: all streams interleaved block by block, several slots
+    say("serve: mix")
+    with rfi.Session(max_inflight=6) as s:
+        sids = [s.open_stream(nb, nc, L) for nb, nc, L, _ in STREAMS]
+        tickets = [[] for _ in STREAMS]
+        for i in range(max(len(sp[3]) for sp in STREAMS)):
+            for j, (spec, (x, bufs)) in enumerate(zip(STREAMS, data)):
+                if i < len(bufs):
+                    tickets[j].append(s.submit(sids[j], rfi.make_block(bufs[i], spec[1]), tag=i))
+        mixed = [_collect(s, tk) for tk in tickets]
+    for j in range(len(STREAMS)):
+        for a, m in zip(alone[j], mixed[j]):
+            assert a[:3] == m[:3], j
+            for u, v in zip(a[3], m[3]):
+                assert np.array_equal(u, v), j
+            assert a[4] == m[4] or (np.isnan(a[4][0]) and np.isnan(m[4][0])), j
+    # oracle: sub-intervals of the concatenated samples, pooled clip per block
+    for (nb, nc, L, lens), (x, _), res in zip(STREAMS, data, alone):
+        ksub = x.shape[1] // L
+        cr = pipeline.cells(x, L, ksub)
+        st = clip.StreamState()
+        ends = np.cumsum(lens)
+        done = 0
+        for i, (nsub, carried, carry, (stat, cst, mask), fl) in enumerate(res):
+            kend = ends[i] // L                     # sub-intervals complete after block i
+            rows = slice(done, kend)
+            assert nsub == kend - done, (nb, i)
+            assert carry == ends[i] - kend * L, (nb, i)
+            if nsub:
+                so = cr.stat[rows].ravel()
+                assert np.abs(stat - so).max() <= 1e-9, (nb, i)
+                ref = clip.clip_stream(st, so, ~cr.degenerate[rows].ravel())
+                assert np.array_equal(mask.astype(bool), ref.mask), (nb, i)
+                assert fl[3] == ref.iterations and fl[4] == ref.nflag, (nb, i)
+            done = kend
+
+
+def test_serve_export_import(dev):
+    from paper_2512_16278_amd import rfi
+    nb, nc, L, lens = STREAMS[0]
+    x, bufs = _blocks(dev, STREAMS[0], 77)
+    say("serve: uninterrupted")
+    with rfi.Session(max_inflight=2) as s:
+        sid = s.open_stream(nb, nc, L)
+        whole = _collect(s, _run(s, sid, bufs, nc))
+    say("serve: split at a checkpoint")
+    with rfi.Session(max_inflight=2) as s:
+        sid = s.open_stream(nb, nc, L)
+        first = _collect(s, _run(s, sid, bufs[:2], nc))
+        ckpt = s.export_stream(sid)
+    with rfi.Session(max_inflight=3) as s:
+        sid = s.open_stream(nb, nc, L)
+        s.import_stream(sid, ckpt)
+        second = _collect(s, _run(s, sid, bufs[2:], nc))
+    for a, b in zip(whole, first + second):
+        assert a[:3] == b[:3]
+        for u, v in zip(a[3], b[3]):
+            assert np.array_equal(u, v)
+
+
+def test_serve_errors_cancel_budget(dev):
+    import torch
+    from paper_2512_16278_amd import rfi
+    nb, nc, L = 19, 64, 128
+    x = _data(nb, nc, 40 * L, 5)
+    buf = upload(x, dev)
+    with rfi.Session(max_inflight=1, hbm_budget=1 << 20) as s:
+        sid = s.open_stream(nb, nc, L)
+        with pytest.raises(rfi.RfiError) as e:          # the block alone exceeds the budget
+            s.submit(sid, rfi.make_block(buf, nc))
+        assert e.value.code == rfi.RFI_E_BUDGET
+        with pytest.raises(rfi.RfiError):               # shape differs from the stream
+            s.submit(sid, rfi.make_block(buf[:7], nc))
+        with pytest.raises(rfi.RfiError):
+            s.submit(sid + 99, rfi.make_block(buf[:, :L], nc))
+        with pytest.raises(rfi.RfiError):
+            s.open_stream(nb, nc, 0)
+    with rfi.Session(max_inflight=1) as s:
+        sid = s.open_stream(nb, nc, L)
+        big = s.submit(sid, rfi.make_block(buf, nc))
+        small = [s.submit(sid, rfi.make_block(buf[:, :L], nc)) for _ in range(4)]
+        code = s.cancel(small[-1])
+        r_big = s.wait(big)
+        assert r_big.status == rfi.RFI_OK and r_big.nsub == 40
+        rs = [s.wait(t) for t in small]
+        if code == rfi.RFI_OK:
+            assert rs[-1].status == rfi.RFI_E_CANCELLED
+        else:
+            assert code == rfi.RFI_E_NOT_READY
+        for r in rs[:-1]:
+            assert r.status == rfi.RFI_OK and r.nsub == 1
+        assert s.poll(big) is not None
+        s.release(big)
+        with pytest.raises(rfi.RfiError):
+            s.release(big)                               # already released
+        with pytest.raises(rfi.RfiError):
+            s.wait(big)
+        # a block shorter than L only extends the carry: no cells
+        sid2 = s.open_stream(nb, nc, L)
+        r = s.wait(s.submit(sid2, rfi.make_block(buf[:, :L // 2], nc)))
+        assert r.status == rfi.RFI_OK and r.nsub == 0 and r.carry_samples == L // 2
+        r = s.wait(s.submit(sid2, rfi.make_block(buf[:, :L // 2], nc)))
+        assert r.nsub == 1 and r.carried == 1 and r.carry_samples == 0
+        s.close_stream(sid2)
+        torch.cuda.synchronize()

@@ -115,3 +115,26 @@ def test_process_block_argument_errors():
                                None, None, *args, None, None, None, C.c_void_p(256),
                                None) == rfi.RFI_E_INVALID
     assert b"kappa" in L.rfi_last_error()
+
+
+def test_session_without_device_or_with_bad_arguments():
+    """Session calls validate their arguments before touching a device; with
+    no device the session cannot be created."""
+    from paper_2512_16278_amd import rfi
+    L = rfi.lib()
+    h = C.c_void_p()
+    cfg = rfi.rfi_session_config(0, 65, 0)                      # too many slots
+    assert L.rfi_session_create(C.byref(cfg), C.byref(h)) == rfi.RFI_E_INVALID
+    assert L.rfi_session_create(None, None) == rfi.RFI_E_INVALID
+    t = C.c_uint64()
+    r = rfi.rfi_result()
+    assert L.rfi_submit(None, 1, None, 0, C.byref(t)) == rfi.RFI_E_INVALID
+    assert L.rfi_poll(None, 1, C.byref(r)) == rfi.RFI_E_INVALID
+    assert L.rfi_wait(None, 1, 0, C.byref(r)) == rfi.RFI_E_INVALID
+    assert L.rfi_cancel(None, 1) == rfi.RFI_E_INVALID
+    assert L.rfi_result_release(None, 1) == rfi.RFI_E_INVALID
+    L.rfi_session_destroy(None)
+    import torch
+    if not torch.cuda.is_available():
+        cfg = rfi.rfi_session_config(0, 4, 0)
+        assert L.rfi_session_create(C.byref(cfg), C.byref(h)) == rfi.RFI_E_DEVICE
