@@ -74,6 +74,76 @@ MIX_NCHAN = (1024, 4096, 8192)
 MIX_L = (512, 1024, 4096)
 
 
+def precision_split(dev, spec, data, blk, nsub, ev_time):
+    """Precision split on the FAST-shaped block: exact int32 sums by the int8
+    MFMA engine vs the dot4 VALU engine (bit-exact, timed); FP32 Jacobi vs
+    FP64 Jacobi on the GPU (timed), each against the FP64 oracle on sampled
+    cells (per-cell eigenvalue error, residual of the dominant pair), and the
+    mask disagreement of the two precisions over every cell."""
+    import torch
+    from oracle import pipeline
+    from paper_2512_16278_amd import rfi, synth
+    nb, nc, L = spec.nbeam, spec.nchan, spec.L
+    ncell = nsub * nc
+    npair = nb * (nb + 1) // 2
+    sums = {}
+    times = {}
+    for name, var in (("mfma", rfi.RFI_CCM_MFMA), ("valu", rfi.RFI_CCM_VALU)):
+        sx = torch.empty((nb, ncell), dtype=torch.int32, device=dev)
+        sxy = torch.empty((npair, ncell), dtype=torch.int32, device=dev)
+        cnt = torch.empty(nsub, dtype=torch.int32, device=dev)
+        times[f"ccm_{name}_ms"] = ev_time(lambda: rfi.rfi_ccm_accumulate(
+            blk, 0, L, nsub, sx, sxy, cnt, variant=var))
+        sums[name] = (sx, sxy, cnt)
+    exact = bool(torch.equal(sums["mfma"][0], sums["valu"][0]) and
+                 torch.equal(sums["mfma"][1], sums["valu"][1]))
+    del sums["valu"]
+    sx, sxy, cnt = sums["mfma"]
+    res = {}
+    for prec in (32, 64):
+        stat = torch.empty(ncell, dtype=torch.float64, device=dev)
+        status = torch.empty(ncell, dtype=torch.uint8, device=dev)
+        ev = torch.empty((nb, ncell), dtype=torch.float32, device=dev)
+        v1 = torch.empty((nb, ncell), dtype=torch.float32, device=dev)
+        mask = torch.empty(ncell, dtype=torch.uint8, device=dev)
+        times[f"eig_fp{prec}_ms"] = ev_time(lambda: rfi.rfi_eig_batched(
+            nb, nsub, nc, sx, sxy, cnt, stat, status, eigvals=ev, v1=v1, precision=prec))
+        times[f"eig_fp{prec}_stat_only_ms"] = ev_time(lambda: rfi.rfi_eig_batched(
+            nb, nsub, nc, sx, sxy, cnt, stat, status, precision=prec))
+        rfi.rfi_eig_batched(nb, nsub, nc, sx, sxy, cnt, stat, status, eigvals=ev, v1=v1,
+                            precision=prec)
+        rfi.rfi_flag(nsub, nc, stat, status, mask)
+        torch.cuda.synchronize()
+        res[prec] = dict(stat=stat.cpu().numpy().reshape(nsub, nc),
+                         ev=ev.cpu().numpy().reshape(nb, nsub, nc),
+                         v1=v1.cpu().numpy().reshape(nb, nsub, nc),
+                         status=status.cpu().numpy(), mask=mask.cpu().numpy())
+    mask_diff = int(np.count_nonzero(res[32]["mask"] != res[64]["mask"]))
+    # sampled cells against the oracle
+    k, c_hi = 0, 256
+    x = synth.generate(spec, k * L, (k + 1) * L, 0, c_hi)
+    cr = pipeline.cells(x, L, 1)
+    w_ref = cr.w[0]                                  # [c, n], |lambda| descending
+    r_ref = cr.r[0]                                  # [c, n, n]
+    out = {"sums_bit_exact_mfma_vs_valu": exact, "mask_disagreements_fp32_vs_fp64": mask_diff,
+           "cells": ncell, "sample": f"sub-interval {k}, channels 0..{c_hi - 1} ({c_hi} cells)"}
+    for prec in (32, 64):
+        ev = res[prec]["ev"][:, k, :c_hi].T.astype(np.float64)       # [c, n]
+        v = res[prec]["v1"][:, k, :c_hi].T.astype(np.float64)
+        lam1 = w_ref[:, :1]
+        nrel = np.abs(ev - w_ref) / np.abs(lam1)
+        erel = np.abs(ev - w_ref) / np.abs(w_ref)
+        s_err = np.abs(res[prec]["stat"][k, :c_hi] - cr.stat[0])
+        resid = np.linalg.norm(np.einsum("cab,cb->ca", r_ref, v) - ev[:, :1] * v, axis=1)
+        out[f"fp{prec}"] = {
+            "eig_norm_rel_max": float(nrel.max()), "eig_elem_rel_max": float(erel.max()),
+            "stat_abs_max": float(s_err.max()), "resid_max": float(resid.max()),
+            "not_converged": int(np.count_nonzero(res[prec]["status"] & rfi.RFI_CELL_NOT_CONVERGED)),
+        }
+    out.update({k2: round(v2, 4) for k2, v2 in times.items()})
+    return out
+
+
 def serve_bench(dev, rates, nblocks, nstreams=8, seed=7, slots=8, budget=64 << 30):
     """Serving loop: Poisson arrivals of uneven blocks from nstreams streams.
 
@@ -174,6 +244,7 @@ def main():
     ap.add_argument("--serve-rates", default="200,2000",
                     help="arrival rates (blocks/s) of the serving run; empty = skip it")
     ap.add_argument("--serve-blocks", type=int, default=40, help="blocks per serving rate")
+    ap.add_argument("--no-precision-split", action="store_true")
     ap.add_argument("--quick", action="store_true",
                     help="time the steps only (no latency, stage split or CPU baseline)")
     ap.add_argument("--profile-run", action="store_true",
@@ -336,6 +407,24 @@ def main():
                 "frac": round(ach / FP32_VALU_PEAK, 4), "traffic": None,
                 "ms": round(float(ms_eig), 4)}
 
+    def ev_time(fn, reps=3):
+        ts = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts[1:]))
+
+    psplit = None
+    if not args.no_precision_split:
+        del sx, sxy
+        torch.cuda.empty_cache()
+        psplit = precision_split(dev, spec, data, blk, nsub, ev_time)
+        log(f"precision split: {psplit}")
+
     serving = None
     if args.serve_rates:
         del data
@@ -369,6 +458,7 @@ def main():
         "frac_of_measured_read": round(value / read_gbs, 4),
         "flagged_cells": int(flags["nflag"]), "clip_iterations": int(flags["iterations"]),
         "roofline": roof,
+        "precision_split": psplit,
         "serving": serving,
         "cpu_baseline": cpu,
     }

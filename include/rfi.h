@@ -232,6 +232,61 @@ rfi_status rfi_process_block(const rfi_block* blk /* host */,
                              rfi_stream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched uneven blocks: many blocks of different beam counts, channel counts
+ * and sub-interval lengths through the whole path (as rfi_process_block for
+ * each) with one launch per kernel class instead of one per block:
+ *  - one sums launch per instance class of the sums engine (beam-count
+ *    range), whose workgroups cover the tiles of all blocks of the class;
+ *  - one eigen launch (or two: Jacobi, then refinement) per solver class
+ *    (beam-count template of the per-lane solver, or the per-wavefront
+ *    solver) over all cells of its blocks;
+ *  - one clip launch, one workgroup per block.
+ * The sums of every block live in the workspace at once. Outputs per block as
+ * rfi_process_block (stat, status, mask; out and state nullable), every one
+ * equal to what rfi_process_block computes for that block alone, bit for bit.
+ * The clip of a batch runs one workgroup per block: it suits blocks of up to
+ * a few hundred thousand cells; larger blocks are better served by
+ * rfi_process_block. rfi_batch_graph_* capture the same launches once into a
+ * HIP graph that is replayed with one call (the descriptors and pointers are
+ * fixed at capture: replays reprocess the same buffers). */
+typedef struct {
+  const rfi_block* blk;          /* host pointer to the block description */
+  int64_t t0;                    /* first sample of the first sub-interval */
+  int32_t L;                     /* samples per sub-interval, 1..RFI_MAX_COUNT */
+  int32_t nsub;                  /* full sub-intervals (0: the block is skipped) */
+  const uint8_t* protect_chan;   /* device [nchan] or NULL */
+  rfi_stream_state* state;       /* device or NULL: pooled clip state */
+  double* stat;                  /* device [nsub * nchan] */
+  uint8_t* status;               /* device [nsub * nchan] */
+  uint8_t* mask;                 /* device [nsub * nchan] */
+  rfi_flag_stats* out;           /* device or NULL */
+} rfi_batch_item;
+
+typedef struct {
+  int32_t eig_precision;         /* 32 (0 = 32) or 64 */
+  int32_t max_sweeps;            /* 0 = 12 */
+  int32_t max_iter;              /* clip fits, 0 = 50 */
+  int32_t pad;
+  double kappa;                  /* clip multiple, >= 0 */
+} rfi_batch_params;
+
+/* Workspace bytes for the batch (0 on invalid arguments; rfi_last_error). */
+size_t rfi_batch_workspace_size(int32_t nitem, const rfi_batch_item* items /* host */,
+                                const rfi_batch_params* p /* host */);
+/* Asynchronous on stream. workspace: device, 256-byte aligned, caller-owned,
+ * used by one call (or graph) at a time. */
+rfi_status rfi_process_batch(int32_t nitem, const rfi_batch_item* items /* host */,
+                             const rfi_batch_params* p /* host */, void* workspace,
+                             rfi_stream_t stream);
+
+typedef struct rfi_batch_graph rfi_batch_graph;
+rfi_status rfi_batch_graph_create(int32_t nitem, const rfi_batch_item* items /* host */,
+                                  const rfi_batch_params* p /* host */, void* workspace,
+                                  rfi_batch_graph** g);
+rfi_status rfi_batch_graph_launch(rfi_batch_graph* g, rfi_stream_t stream);
+void rfi_batch_graph_destroy(rfi_batch_graph* g);
+
+/* ---------------------------------------------------------------------------
  * Serving: continuous batching of observation blocks from many streams.
  *
  * A session owns one device, a set of execution slots (each a HIP stream with

@@ -1,0 +1,331 @@
+// Batched uneven blocks: the whole path for many blocks with one launch per
+// kernel class (rfi_process_batch) and its capture into a HIP graph.
+//
+// Workspace layout: one descriptor area, uploaded by one host-to-device copy,
+// then the sums of every block (sum_x, sum_xy, count; 256-byte aligned):
+//   [beam pointer tables][CcmItem x nitem][EigArgs x nitem][cell0 x (nitem +
+//   nclass)][FlagItem x nitem] | sums of item 0 | sums of item 1 | ...
+// Items are ordered by sums class for the sums launches (each class a
+// contiguous run of CcmItem sorted by first workgroup) and by solver class
+// for the eigen launches (each a contiguous run of EigArgs with ascending
+// first cells).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "internal.h"
+#include "rfi.h"
+
+namespace rfi {
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct ItemPlan {
+  int idx;                 // position in the caller's array
+  BeamPtrs bp;
+  int nbeam, nchan;
+  int64_t ncell;
+  CcmClass cc;
+  int solver, precision;   // eigen class
+  int lane_cls;
+  size_t sums_off;         // byte offset of the item's sums in the workspace
+};
+
+struct EigClass {
+  int lane_cls, precision, max_nbeam;
+  std::vector<int> items;  // indices into plans
+};
+
+struct BatchPlan {
+  std::vector<ItemPlan> plans;
+  rfi_eig_params eig;      // sweeps, precision (solver per item)
+  int max_iter = 50;
+  double kappa = 3.0;
+  // descriptor area
+  size_t tab_off = 0, ccm_off = 0, eig_off = 0, cell0_off = 0, flag_off = 0, desc_bytes = 0;
+  size_t ws_bytes = 0;
+  std::vector<std::pair<int, std::vector<int>>> ccm_classes;  // (nbeam of class, plans)
+  std::vector<EigClass> eig_classes;
+  std::vector<char> host;  // descriptor bytes (device addresses resolved for ws)
+};
+
+rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_params* p,
+                      BatchPlan* bpn, const char* who) {
+  if (nitem < 0) return fail(RFI_E_INVALID, "%s: nitem < 0", who);
+  if (nitem > 0 && !items) return fail(RFI_E_INVALID, "%s: items is NULL", who);
+  rfi_batch_params prm{32, 12, 50, 0, 3.0};
+  if (p) prm = *p;
+  if (prm.eig_precision == 0) prm.eig_precision = 32;
+  if (prm.max_sweeps == 0) prm.max_sweeps = 12;
+  if (prm.max_iter == 0) prm.max_iter = 50;
+  if (!(prm.kappa >= 0.0)) return fail(RFI_E_INVALID, "%s: kappa must be >= 0", who);
+  if (prm.max_iter < 1) return fail(RFI_E_INVALID, "%s: max_iter < 1", who);
+  bpn->max_iter = prm.max_iter;
+  bpn->kappa = prm.kappa;
+  size_t tab_bytes = 0;
+  for (int i = 0; i < nitem; ++i) {
+    const rfi_batch_item& it = items[i];
+    if (!it.blk) return fail(RFI_E_INVALID, "%s: item %d has no block", who, i);
+    ItemPlan ip{};
+    ip.idx = i;
+    rfi_status st = validate_block(it.blk, it.t0, it.L, it.nsub, who, &ip.bp);
+    if (st != RFI_OK) return st;
+    if (it.nsub == 0) continue;
+    if (!it.stat || !it.status || !it.mask)
+      return fail(RFI_E_INVALID, "%s: item %d has a NULL output", who, i);
+    rfi_eig_params ep{prm.eig_precision, prm.max_sweeps, 1, RFI_EIG_AUTO};
+    rfi_eig_params res;
+    if ((st = resolve_eig(it.blk->nbeam, &ep, &res, who)) != RFI_OK) return st;
+    bpn->eig = res;
+    ip.nbeam = it.blk->nbeam;
+    ip.nchan = it.blk->nchan;
+    ip.ncell = (int64_t)it.nsub * it.blk->nchan;
+    if (ccm_class(ip.nbeam, &ip.cc) != hipSuccess)
+      return fail(RFI_E_INVALID, "%s: item %d: no sums instance for %d beams", who, i, ip.nbeam);
+    ip.solver = res.solver;
+    ip.precision = res.precision;
+    ip.lane_cls = res.solver == RFI_EIG_LANE ? eig_lane_class(ip.nbeam) : 0;
+    tab_bytes += (size_t)ip.nbeam * sizeof(void*);
+    bpn->plans.push_back(ip);
+  }
+  const int n = (int)bpn->plans.size();
+  // classes
+  std::map<int, std::vector<int>> ccm;
+  std::map<std::pair<int, int>, std::vector<int>> eig;   // (lane class or 0, precision)
+  for (int k = 0; k < n; ++k) {
+    ccm[bpn->plans[k].cc.key].push_back(k);
+    eig[{bpn->plans[k].lane_cls, bpn->plans[k].precision}].push_back(k);
+  }
+  for (auto& kv : ccm) bpn->ccm_classes.push_back({bpn->plans[kv.second[0]].nbeam, kv.second});
+  for (auto& kv : eig) {
+    EigClass ec{kv.first.first, kv.first.second, 0, kv.second};
+    for (int k : kv.second) ec.max_nbeam = std::max(ec.max_nbeam, bpn->plans[k].nbeam);
+    bpn->eig_classes.push_back(ec);
+  }
+  // layout
+  size_t o = 0;
+  bpn->tab_off = o;
+  o = up(o + tab_bytes);
+  bpn->ccm_off = o;
+  o = up(o + (size_t)n * sizeof(CcmItem));
+  bpn->eig_off = o;
+  o = up(o + (size_t)n * sizeof(EigArgs));
+  bpn->cell0_off = o;
+  o = up(o + (size_t)(n + bpn->eig_classes.size()) * sizeof(int64_t));
+  bpn->flag_off = o;
+  o = up(o + (size_t)n * sizeof(FlagItem));
+  bpn->desc_bytes = o;
+  for (ItemPlan& ip : bpn->plans) {
+    ip.sums_off = o;
+    o += up((size_t)ip.nbeam * ip.ncell * 4) + up((size_t)npair_of(ip.nbeam) * ip.ncell * 4) +
+         up((size_t)items[ip.idx].nsub * 4);
+  }
+  bpn->ws_bytes = std::max<size_t>(o, kAlign);
+  return RFI_OK;
+}
+
+// Fill the descriptor bytes for a workspace at device address ws.
+void fill_descriptors(const rfi_batch_item* items, BatchPlan* bpn, char* ws) {
+  std::vector<char>& h = bpn->host;
+  h.assign(bpn->desc_bytes, 0);
+  auto dptr = [&](size_t off) { return ws + off; };
+  size_t tab = bpn->tab_off;
+  std::vector<const uint8_t* const*> tabs(bpn->plans.size());
+  for (size_t k = 0; k < bpn->plans.size(); ++k) {
+    const ItemPlan& ip = bpn->plans[k];
+    std::memcpy(h.data() + tab, ip.bp.p, (size_t)ip.nbeam * sizeof(void*));
+    tabs[k] = (const uint8_t* const*)dptr(tab);
+    tab += (size_t)ip.nbeam * sizeof(void*);
+  }
+  auto sums = [&](const ItemPlan& ip, int32_t** sx, int32_t** sxy, int32_t** cnt) {
+    char* b = dptr(ip.sums_off);
+    *sx = (int32_t*)b;
+    *sxy = (int32_t*)(b + up((size_t)ip.nbeam * ip.ncell * 4));
+    *cnt = (int32_t*)(b + up((size_t)ip.nbeam * ip.ncell * 4) +
+                      up((size_t)npair_of(ip.nbeam) * ip.ncell * 4));
+  };
+  // sums descriptors, class by class
+  CcmItem* ci = (CcmItem*)(h.data() + bpn->ccm_off);
+  int pos = 0;
+  for (auto& cls : bpn->ccm_classes) {
+    int wg = 0;
+    for (int k : cls.second) {
+      const ItemPlan& ip = bpn->plans[k];
+      const rfi_batch_item& it = items[ip.idx];
+      CcmItem& c = ci[pos++];
+      c.beams = tabs[k];
+      c.row_stride = it.blk->row_stride;
+      c.t0 = it.t0;
+      sums(ip, &c.sum_x, &c.sum_xy, &c.count);
+      c.nbeam = ip.nbeam;
+      c.nchan = ip.nchan;
+      c.L = it.L;
+      c.nsub = it.nsub;
+      c.nct = (ip.nchan + ip.cc.cw - 1) / ip.cc.cw;
+      c.nh = ip.cc.nh;
+      c.wg0 = wg;
+      wg += (c.nsub * c.nct + 7) / 8 * 8;
+    }
+  }
+  // eigen descriptors, class by class, with the first global cell of each
+  EigArgs* ea = (EigArgs*)(h.data() + bpn->eig_off);
+  int64_t* c0 = (int64_t*)(h.data() + bpn->cell0_off);
+  pos = 0;
+  int cpos = 0;
+  for (EigClass& ec : bpn->eig_classes) {
+    int64_t cell = 0;
+    for (int k : ec.items) {
+      const ItemPlan& ip = bpn->plans[k];
+      const rfi_batch_item& it = items[ip.idx];
+      EigArgs& a = ea[pos++];
+      int32_t *sx, *sxy, *cnt;
+      sums(ip, &sx, &sxy, &cnt);
+      a = EigArgs{ip.nbeam, it.nsub, ip.nchan, sx, sxy, cnt, bpn->eig.max_sweeps, 1,
+                  nullptr, it.stat, nullptr, it.status, ip.ncell};
+      c0[cpos++] = cell;
+      cell += ip.ncell;
+    }
+    c0[cpos++] = cell;      // total of the class
+  }
+  FlagItem* fi = (FlagItem*)(h.data() + bpn->flag_off);
+  for (size_t k = 0; k < bpn->plans.size(); ++k) {
+    const ItemPlan& ip = bpn->plans[k];
+    const rfi_batch_item& it = items[ip.idx];
+    fi[k] = FlagItem{it.nsub, ip.nchan, bpn->max_iter, 0, bpn->kappa, it.stat, it.status,
+                     it.protect_chan, it.state, it.mask, it.out};
+  }
+}
+
+// Enqueue the batch on s; desc is the host copy of the descriptors (pinned
+// for graph capture, where the copy node reads it at every replay).
+hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipStream_t s) {
+  const int n = (int)bpn.plans.size();
+  if (n == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(ws, desc, bpn.desc_bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  const CcmItem* ci = (const CcmItem*)(ws + bpn.ccm_off);
+  const CcmItem* hci = (const CcmItem*)((const char*)desc + bpn.ccm_off);
+  int pos = 0;
+  for (auto& cls : bpn.ccm_classes) {
+    const int m = (int)cls.second.size();
+    const CcmItem& last = hci[pos + m - 1];
+    const int total = last.wg0 + (last.nsub * last.nct + 7) / 8 * 8;
+    if ((e = launch_ccm_batch(cls.first, ci + pos, m, total, s)) != hipSuccess) return e;
+    pos += m;
+  }
+  const EigArgs* ea = (const EigArgs*)(ws + bpn.eig_off);
+  const int64_t* c0 = (const int64_t*)(ws + bpn.cell0_off);
+  const int64_t* hc0 = (const int64_t*)((const char*)desc + bpn.cell0_off);
+  pos = 0;
+  int cpos = 0;
+  for (const EigClass& ec : bpn.eig_classes) {
+    const int m = (int)ec.items.size();
+    const int64_t total = hc0[cpos + m];
+    e = ec.lane_cls ? launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s)
+                    : launch_eig_wave_batch(ec.precision, ec.max_nbeam, ea + pos, c0 + cpos, m,
+                                            total, s);
+    if (e != hipSuccess) return e;
+    pos += m;
+    cpos += m + 1;
+  }
+  return launch_flag_batch((const FlagItem*)(ws + bpn.flag_off), n, s);
+}
+
+}  // namespace
+}  // namespace rfi
+
+struct rfi_batch_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* desc = nullptr;      // pinned host copy of the descriptors
+};
+
+using rfi::fail;
+
+extern "C" {
+
+size_t rfi_batch_workspace_size(int32_t nitem, const rfi_batch_item* items,
+                                const rfi_batch_params* p) {
+  rfi::clear_error();
+  rfi::BatchPlan bpn;
+  if (rfi::plan_batch(nitem, items, p, &bpn, "rfi_batch_workspace_size") != RFI_OK) return 0;
+  return bpn.ws_bytes;
+}
+
+rfi_status rfi_process_batch(int32_t nitem, const rfi_batch_item* items,
+                             const rfi_batch_params* p, void* workspace, rfi_stream_t stream) {
+  rfi::clear_error();
+  const char* who = "rfi_process_batch";
+  rfi::BatchPlan bpn;
+  rfi_status st = rfi::plan_batch(nitem, items, p, &bpn, who);
+  if (st != RFI_OK) return st;
+  if (bpn.plans.empty()) return RFI_OK;
+  if (!workspace || (uintptr_t)workspace % 256 != 0)
+    return fail(RFI_E_INVALID, "%s: workspace NULL or not 256-byte aligned", who);
+  rfi::fill_descriptors(items, &bpn, (char*)workspace);
+  // pageable source: the runtime stages it before the call returns
+  return rfi::check_hip(rfi::enqueue_batch(bpn, bpn.host.data(), (char*)workspace,
+                                           (hipStream_t)stream),
+                        who);
+}
+
+rfi_status rfi_batch_graph_create(int32_t nitem, const rfi_batch_item* items,
+                                  const rfi_batch_params* p, void* workspace,
+                                  rfi_batch_graph** out) {
+  rfi::clear_error();
+  const char* who = "rfi_batch_graph_create";
+  if (!out) return fail(RFI_E_INVALID, "%s: out is NULL", who);
+  *out = nullptr;
+  rfi::BatchPlan bpn;
+  rfi_status st = rfi::plan_batch(nitem, items, p, &bpn, who);
+  if (st != RFI_OK) return st;
+  if (!workspace || (uintptr_t)workspace % 256 != 0)
+    return fail(RFI_E_INVALID, "%s: workspace NULL or not 256-byte aligned", who);
+  rfi::fill_descriptors(items, &bpn, (char*)workspace);
+  std::unique_ptr<rfi_batch_graph> g(new rfi_batch_graph);
+  hipError_t e = hipHostMalloc(&g->desc, std::max<size_t>(bpn.desc_bytes, 1), 0);
+  if (e != hipSuccess) return rfi::check_hip(e, who);
+  std::memcpy(g->desc, bpn.host.data(), bpn.desc_bytes);
+  hipStream_t cs = nullptr;
+  if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
+    (void)hipHostFree(g->desc);
+    return rfi::check_hip(e, who);
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t ee = rfi::enqueue_batch(bpn, g->desc, (char*)workspace, cs);
+    e = hipStreamEndCapture(cs, &g->graph);
+    if (ee != hipSuccess) e = ee;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    (void)hipHostFree(g->desc);
+    return rfi::check_hip(e, who);
+  }
+  *out = g.release();
+  return RFI_OK;
+}
+
+rfi_status rfi_batch_graph_launch(rfi_batch_graph* g, rfi_stream_t stream) {
+  rfi::clear_error();
+  if (!g) return fail(RFI_E_INVALID, "rfi_batch_graph_launch: NULL graph");
+  return rfi::check_hip(hipGraphLaunch(g->exec, (hipStream_t)stream), "rfi_batch_graph_launch");
+}
+
+void rfi_batch_graph_destroy(rfi_batch_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->desc) (void)hipHostFree(g->desc);
+  delete g;
+}
+
+}  // extern "C"

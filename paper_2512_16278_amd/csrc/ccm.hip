@@ -30,6 +30,7 @@
 // Comparison engine (ccm_valu_kernel, nbeam <= 20): one lane per channel, all
 // pair accumulators in registers, four samples per v_dot4_u32_u8.
 #include <stdlib.h>
+#include <string.h>
 
 #include <type_traits>
 
@@ -116,12 +117,51 @@ __device__ __forceinline__ void wait_chunk(int ahead) {
   vm_wait_barrier<0>();
 }
 
+// Tiles per XCD group: 1 KB of contiguous row bytes by default (measured best
+// for the 4 KB-row FAST layout); RFI_CCM_GROUP_BYTES overrides.
+int group_tiles(int cw) {
+  static const int group_bytes = [] {
+    const char* v = getenv("RFI_CCM_GROUP_BYTES");
+    const int g = v ? atoi(v) : 1024;
+    return g < 16 ? 16 : g;
+  }();
+  return group_bytes / cw > 1 ? group_bytes / cw : 1;
+}
+
 template <int NB, int CW, int CPW, int IPW, int NST>
 __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm_mfma_kernel(
     BeamPtrs bp, int nbeam, int nchan, int64_t row_stride, int64_t t0, int L, int nsub,
     int nct, int32_t* __restrict__ sum_x, int32_t* __restrict__ sum_xy,
-    int32_t* __restrict__ count, int accumulate, int G, int nh, int prio) {
+    int32_t* __restrict__ count, int accumulate, int G, int nh, int prio,
+    const CcmItem* __restrict__ items, int nitem) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
+  // the beam pointer table is the first kernel argument: index it in place
+  const uint8_t* const* beam_tab = (const uint8_t* const*)__builtin_amdgcn_kernarg_segment_ptr();
+  int w = blockIdx.x;
+  if (items) {
+    // batched launch: workgroups [wg0, wg0 + 8 ceil(tiles / 8)) belong to one
+    // block (its own shape, beams, sub-intervals and sum buffers); find it
+    int lo = 0, hi = nitem - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].wg0 <= w) lo = mid; else hi = mid - 1;
+    }
+    const CcmItem& it = items[lo];
+    beam_tab = it.beams;
+    nbeam = it.nbeam;
+    nchan = it.nchan;
+    row_stride = it.row_stride;
+    t0 = it.t0;
+    L = it.L;
+    nsub = it.nsub;
+    nct = it.nct;
+    nh = it.nh;
+    sum_x = it.sum_x;
+    sum_xy = it.sum_xy;
+    count = it.count;
+    w -= it.wg0;
+    if (w >= nsub * nct) return;      // padding to a multiple of 8 workgroups
+  }
   // optional issue priority over waves of other kernels on the same SIMD
   if (prio) __builtin_amdgcn_s_setprio(2);
   extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
@@ -142,7 +182,6 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
   // back to back on the same XCD (workgroup ids w, w + 8, w + 16, ...): the
   // hardware dispatcher then keeps adjacent tiles in step, and each row is
   // fetched in long runs through one L2
-  const int w = blockIdx.x;
   const int full = G > 1 ? (ntiles / (8 * G)) * (8 * G) : 0;
   int tile = w;
   if (w < full) {
@@ -155,7 +194,6 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
   // Units past the beams, rows past the sub-interval and segments past the
   // row read a valid dummy address (never consumed), so every wave issues
   // exactly IPW loads per chunk and vmcnt counts stay uniform.
-  const uint8_t* const* beam_tab = (const uint8_t* const*)__builtin_amdgcn_kernarg_segment_ptr();
   const uint8_t* src_base[IPW];
   int src_row[IPW], src_col[IPW];
 #pragma unroll
@@ -393,6 +431,17 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
   epilogue(tile);
 }
 
+// Epilogue passes: the fewest (power of two, whole waves each) whose staging
+// rows fit; 0 if none does.
+template <int NB, int CW, int CPW, int IPW, int NST>
+int epilogue_passes(int nbeam) {
+  using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
+  const int nrow = nbeam + nbeam * (nbeam + 1) / 2;
+  int nh = 1;
+  while (nh < C::NWAVE && nrow * (CW / nh + 1) * 4 > C::STG_BYTES) nh *= 2;
+  return nrow * (CW / nh + 1) * 4 > C::STG_BYTES ? 0 : nh;
+}
+
 template <int NB, int CW, int CPW, int IPW, int NST>
 hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
@@ -400,56 +449,138 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   if ((int64_t)nbeam * C::UPB > (int64_t)64 * IPW * C::NWAVE) return hipErrorInvalidValue;
   if (nbeam > C::MAXB) return hipErrorInvalidValue;
-  // epilogue passes: the fewest (power of two, whole waves each) whose
-  // staging rows fit
-  const int nrow = nbeam + nbeam * (nbeam + 1) / 2;
-  int nh = 1;
-  while (nh < C::NWAVE && nrow * (CW / nh + 1) * 4 > C::STG_BYTES) nh *= 2;
-  if (nrow * (CW / nh + 1) * 4 > C::STG_BYTES) return hipErrorInvalidValue;
+  const int nh = epilogue_passes<NB, CW, CPW, IPW, NST>(nbeam);
+  if (nh == 0) return hipErrorInvalidValue;
   const int nct = (nchan + CW - 1) / CW;
   const auto kern = ccm_mfma_kernel<NB, CW, CPW, IPW, NST>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
   if (e != hipSuccess) return e;
   const int64_t ntiles = (int64_t)nsub * nct;
-  // tiles per XCD group: 1 KB of contiguous row bytes by default (measured
-  // best for the 4 KB-row FAST layout); RFI_CCM_GROUP_BYTES overrides
-  static const int group_bytes = [] {
-    const char* v = getenv("RFI_CCM_GROUP_BYTES");
-    const int g = v ? atoi(v) : 1024;
-    return g < 16 ? 16 : g;
-  }();
-  const int G = group_bytes / CW > 1 ? group_bytes / CW : 1;
+  const int G = group_tiles(CW);
   // tuning knob: RFI_CCM_PRIO=1 raises the streaming waves' issue priority
   static const int prio = [] {
     const char* v = getenv("RFI_CCM_PRIO");
     return v && atoi(v) == 1 ? 1 : 0;
   }();
   hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), C::LDS, s, bp, nbeam, nchan,
-                     row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate, G, nh, prio);
+                     row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate, G, nh, prio,
+                     (const CcmItem*)nullptr, 0);
   return hipGetLastError();
 }
 
-// Largest ring (<= 4 buffers) of IPW KB-per-wave chunk buffers within 160 KB.
-template <int NB, int CW, int CPW, int IPW>
-hipError_t launch_ipw(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride, int64_t t0,
-                      int L, int nsub, int32_t* sum_x, int32_t* sum_xy, int32_t* count,
-                      int accumulate, int max_stages, hipStream_t s) {
+template <int NB, int CW, int CPW, int IPW, int NST>
+hipError_t launch_batch_cfg(const CcmItem* items, int nitem, int total_wg, hipStream_t s) {
+  using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
+  const auto kern = ccm_mfma_kernel<NB, CW, CPW, IPW, NST>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
+  if (e != hipSuccess) return e;
+  const int G = group_tiles(CW);
+  BeamPtrs none;
+  memset(&none, 0, sizeof(none));
+  hipLaunchKernelGGL(kern, dim3((unsigned)total_wg), dim3(C::NTHR), C::LDS, s, none, 0, 0,
+                     (int64_t)0, (int64_t)0, 0, 0, 0, (int32_t*)nullptr, (int32_t*)nullptr,
+                     (int32_t*)nullptr, 0, G, 1, 0, items, nitem);
+  return hipGetLastError();
+}
+
+// Largest ring (<= 4 buffers) of IPW KB-per-wave chunk buffers within 160 KB;
+// calls op.run<NB, CW, CPW, IPW, NST>().
+template <int NB, int CW, int CPW, int IPW, class Op>
+hipError_t dispatch_nst(int max_stages, Op& op) {
   if constexpr (MfmaCfg<NB, CW, CPW, IPW, 4>::FITS) {
-    if (max_stages >= 4)
-      return launch_mfma_cfg<NB, CW, CPW, IPW, 4>(bp, nbeam, nchan, row_stride, t0, L, nsub,
-                                                  sum_x, sum_xy, count, accumulate, s);
+    if (max_stages >= 4) return op.template run<NB, CW, CPW, IPW, 4>();
   }
   if constexpr (MfmaCfg<NB, CW, CPW, IPW, 3>::FITS) {
-    if (max_stages >= 3)
-      return launch_mfma_cfg<NB, CW, CPW, IPW, 3>(bp, nbeam, nchan, row_stride, t0, L, nsub,
-                                                  sum_x, sum_xy, count, accumulate, s);
+    if (max_stages >= 3) return op.template run<NB, CW, CPW, IPW, 3>();
   }
-  if constexpr (MfmaCfg<NB, CW, CPW, IPW, 2>::FITS)
-    return launch_mfma_cfg<NB, CW, CPW, IPW, 2>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
-                                                sum_xy, count, accumulate, s);
+  if constexpr (MfmaCfg<NB, CW, CPW, IPW, 2>::FITS) return op.template run<NB, CW, CPW, IPW, 2>();
   return hipErrorInvalidValue;
 }
+
+// The MFMA engine's instance for a beam count: 16-row blocks NB (including
+// the ones row), tile width CW channels, CPW channels per wave, IPW loads per
+// wave per chunk, ring depth NST.
+template <class Op>
+hipError_t ccm_dispatch(int nbeam, int shared_cu, Op& op) {
+  const int nb = (nbeam + 1 + 15) / 16;
+  // tile shape per block count: (CW channels, CPW channels per wave). With
+  // shared_cu the 19-beam tile is 32 channels on 8 waves of ~120 VGPRs.
+  int cw, cpw;
+  static const int cpw2 = [] {
+    const char* e = getenv("RFI_CCM_CPW");
+    return e && atoi(e) == 4 ? 4 : 8;
+  }();
+  switch (nb) {
+    case 1: cw = 64; cpw = 8; break;
+    case 2:
+      if (shared_cu) { cw = 32; cpw = 4; } else { cw = 64; cpw = cpw2; }
+      break;
+    case 3: cw = 32; cpw = 4; break;
+    case 4: case 5: cw = 16; cpw = 2; break;
+    default: return hipErrorInvalidValue;
+  }
+  // ring depth cap (tuning knob; default: the largest ring that fits)
+  static const int max_stages = [] {
+    const char* e = getenv("RFI_CCM_STAGES");
+    const int v = e ? atoi(e) : 4;
+    return v < 2 ? 2 : v;
+  }();
+  const int nwave = cw / cpw;
+  const int units = nbeam * 32 * (cw / 16);        // 16-byte units per chunk
+  const int ipw = (units + 64 * nwave - 1) / (64 * nwave);  // loads per wave per chunk
+#define RFI_CCM(NB, CW, CPW, IPW)                         \
+  if (nb == NB && cw == CW && cpw == CPW && ipw == IPW) \
+    return dispatch_nst<NB, CW, CPW, IPW>(max_stages, op);
+  RFI_CCM(1, 64, 8, 1) RFI_CCM(1, 64, 8, 2) RFI_CCM(1, 64, 8, 3) RFI_CCM(1, 64, 8, 4)
+  RFI_CCM(2, 64, 8, 4) RFI_CCM(2, 64, 8, 5) RFI_CCM(2, 64, 8, 6) RFI_CCM(2, 64, 8, 7)
+  RFI_CCM(2, 64, 8, 8)
+  RFI_CCM(2, 64, 4, 2) RFI_CCM(2, 64, 4, 3) RFI_CCM(2, 64, 4, 4)
+  RFI_CCM(2, 32, 4, 2) RFI_CCM(2, 32, 4, 3) RFI_CCM(2, 32, 4, 4)
+  RFI_CCM(3, 32, 4, 4) RFI_CCM(3, 32, 4, 5) RFI_CCM(3, 32, 4, 6)
+  RFI_CCM(4, 16, 2, 3) RFI_CCM(4, 16, 2, 4)
+  RFI_CCM(5, 16, 2, 4) RFI_CCM(5, 16, 2, 5)
+#undef RFI_CCM
+  return hipErrorInvalidValue;
+}
+
+struct LaunchOne {
+  const BeamPtrs& bp;
+  int nbeam, nchan;
+  int64_t row_stride, t0;
+  int L, nsub;
+  int32_t *sum_x, *sum_xy, *count;
+  int accumulate;
+  hipStream_t s;
+  template <int NB, int CW, int CPW, int IPW, int NST>
+  hipError_t run() {
+    return launch_mfma_cfg<NB, CW, CPW, IPW, NST>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
+                                                  sum_xy, count, accumulate, s);
+  }
+};
+
+struct Describe {
+  int nbeam;
+  CcmClass* out;
+  template <int NB, int CW, int CPW, int IPW, int NST>
+  hipError_t run() {
+    out->key = ((NB * 128 + CW) * 16 + CPW) * 16 * 8 + IPW * 8 + NST;
+    out->cw = CW;
+    out->nh = epilogue_passes<NB, CW, CPW, IPW, NST>(nbeam);
+    return out->nh > 0 ? hipSuccess : hipErrorInvalidValue;
+  }
+};
+
+struct LaunchBatch {
+  const CcmItem* items;
+  int nitem, total_wg;
+  hipStream_t s;
+  template <int NB, int CW, int CPW, int IPW, int NST>
+  hipError_t run() {
+    return launch_batch_cfg<NB, CW, CPW, IPW, NST>(items, nitem, total_wg, s);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // VALU comparison engine: one lane per channel, nbeam <= 20.
@@ -519,48 +650,19 @@ __global__ __launch_bounds__(256) void ccm_valu_kernel(BeamPtrs bp, int nbeam, i
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, int shared_cu, hipStream_t s) {
-  const int nb = (nbeam + 1 + 15) / 16;   // 16-row blocks incl. the ones row
-  // tile shape per block count: (CW channels, CPW channels per wave). With
-  // shared_cu the tile is 32 channels on 8 waves of ~120 VGPRs, which leaves
-  // every SIMD room for one wave of the register-resident eigensolver, so the
-  // two kernels run side by side on each CU.
-  int cw, cpw;
-  static const int cpw2 = [] {
-    const char* e = getenv("RFI_CCM_CPW");
-    return e && atoi(e) == 4 ? 4 : 8;
-  }();
-  switch (nb) {
-    case 1: cw = 64; cpw = 8; break;
-    case 2:
-      if (shared_cu) { cw = 32; cpw = 4; } else { cw = 64; cpw = cpw2; }
-      break;
-    case 3: cw = 32; cpw = 4; break;
-    case 4: case 5: cw = 16; cpw = 2; break;
-    default: return hipErrorInvalidValue;
-  }
-  // ring depth cap (tuning knob; default: the largest ring that fits)
-  static const int max_stages = [] {
-    const char* e = getenv("RFI_CCM_STAGES");
-    const int v = e ? atoi(e) : 4;
-    return v < 2 ? 2 : v;
-  }();
-  const int nwave = cw / cpw;
-  const int units = nbeam * 32 * (cw / 16);        // 16-byte units per chunk
-  const int ipw = (units + 64 * nwave - 1) / (64 * nwave);  // loads per wave per chunk
-#define RFI_CCM(NB, CW, CPW, IPW)                                                          \
-  if (nb == NB && cw == CW && cpw == CPW && ipw == IPW)                                \
-    return launch_ipw<NB, CW, CPW, IPW>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, \
-                                        sum_xy, count, accumulate, max_stages, s);
-  RFI_CCM(1, 64, 8, 1) RFI_CCM(1, 64, 8, 2) RFI_CCM(1, 64, 8, 3) RFI_CCM(1, 64, 8, 4)
-  RFI_CCM(2, 64, 8, 4) RFI_CCM(2, 64, 8, 5) RFI_CCM(2, 64, 8, 6) RFI_CCM(2, 64, 8, 7)
-  RFI_CCM(2, 64, 8, 8)
-  RFI_CCM(2, 64, 4, 2) RFI_CCM(2, 64, 4, 3) RFI_CCM(2, 64, 4, 4)
-  RFI_CCM(2, 32, 4, 2) RFI_CCM(2, 32, 4, 3) RFI_CCM(2, 32, 4, 4)
-  RFI_CCM(3, 32, 4, 4) RFI_CCM(3, 32, 4, 5) RFI_CCM(3, 32, 4, 6)
-  RFI_CCM(4, 16, 2, 3) RFI_CCM(4, 16, 2, 4)
-  RFI_CCM(5, 16, 2, 4) RFI_CCM(5, 16, 2, 5)
-#undef RFI_CCM
-  return hipErrorInvalidValue;
+  LaunchOne op{bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, sum_xy, count, accumulate, s};
+  return ccm_dispatch(nbeam, shared_cu, op);
+}
+
+hipError_t ccm_class(int nbeam, CcmClass* c) {
+  Describe op{nbeam, c};
+  return ccm_dispatch(nbeam, 0, op);
+}
+
+hipError_t launch_ccm_batch(int nbeam_of_class, const CcmItem* items, int nitem, int total_wg,
+                            hipStream_t s) {
+  LaunchBatch op{items, nitem, total_wg, s};
+  return ccm_dispatch(nbeam_of_class, 0, op);
 }
 
 hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,

@@ -133,10 +133,8 @@ __device__ __forceinline__ bool jacobi_sweep(float (&A)[Sym<N>::NP]) {
 // eigenvalue into stat[] (consumed by kernel 2), the optional sorted
 // eigenvalues, and the status bits of this stage.
 template <int N>
-__global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
+__device__ __forceinline__ void jacobi_cell(const EigArgs& g, int64_t cell) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
-  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= ncell) return;
   const int n = g.nbeam;
   const int64_t cnt = g.count[cell / g.nchan];
   if (cnt < 2 || cnt > RFI_MAX_COUNT) {
@@ -197,10 +195,8 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
 // Kernel 2: eigenvector by inverse iteration and FP64 Rayleigh quotient;
 // writes the statistic lambda_1^2 / ||C||_F^2, v1 and the remaining status bits.
 template <int N>
-__global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
+__device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
-  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= ncell) return;
   const int n = g.nbeam;
   const int64_t cnt = g.count[cell / g.nchan];
   uint8_t st = g.status[cell];
@@ -337,6 +333,62 @@ __global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
 }
 
 template <int N>
+__global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell < (int64_t)g.nsub * g.nchan) jacobi_cell<N>(g, cell);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell < (int64_t)g.nsub * g.nchan) refine_cell<N>(g, cell);
+}
+
+// Batched: the cells of several blocks (one EigArgs each, in device memory)
+// as one index space; cell0[i] = first global cell of item i (ascending).
+__device__ __forceinline__ int find_item(const int64_t* cell0, int nitem, int64_t c) {
+  int lo = 0, hi = nitem - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cell0[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void eig_lane_jacobi_batch(const EigArgs* items,
+                                                             const int64_t* cell0, int nitem,
+                                                             int64_t total) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total) return;
+  const int i = find_item(cell0, nitem, c);
+  const EigArgs g = items[i];
+  jacobi_cell<N>(g, c - cell0[i]);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void eig_lane_refine_batch(const EigArgs* items,
+                                                             const int64_t* cell0, int nitem,
+                                                             int64_t total) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total) return;
+  const int i = find_item(cell0, nitem, c);
+  const EigArgs g = items[i];
+  refine_cell<N>(g, c - cell0[i]);
+}
+
+template <int N>
+hipError_t launch_batch_n(const EigArgs* items, const int64_t* cell0, int nitem, int64_t total,
+                          hipStream_t s) {
+  const dim3 grid((unsigned)((total + 255) / 256));
+  hipLaunchKernelGGL(eig_lane_jacobi_batch<N>, grid, dim3(256), 0, s, items, cell0, nitem, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(eig_lane_refine_batch<N>, grid, dim3(256), 0, s, items, cell0, nitem, total);
+  return hipGetLastError();
+}
+
+template <int N>
 hipError_t launch_n(const EigArgs& a, int wg, hipStream_t s) {
   const int64_t ncell = (int64_t)a.nsub * a.nchan;
   const dim3 grid((unsigned)((ncell + wg - 1) / wg));
@@ -348,6 +400,29 @@ hipError_t launch_n(const EigArgs& a, int wg, hipStream_t s) {
 }
 
 }  // namespace
+
+int eig_lane_class(int n) {
+  if (n <= 4) return 4;
+  if (n <= 8) return 8;
+  if (n <= 12) return 12;
+  if (n <= 16) return 16;
+  if (n == 19) return 19;
+  if (n <= 20) return 20;
+  return 0;
+}
+
+hipError_t launch_eig_lane_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
+                                 int64_t total, hipStream_t s) {
+  switch (cls) {
+    case 4: return launch_batch_n<4>(items, cell0, nitem, total, s);
+    case 8: return launch_batch_n<8>(items, cell0, nitem, total, s);
+    case 12: return launch_batch_n<12>(items, cell0, nitem, total, s);
+    case 16: return launch_batch_n<16>(items, cell0, nitem, total, s);
+    case 19: return launch_batch_n<19>(items, cell0, nitem, total, s);
+    case 20: return launch_batch_n<20>(items, cell0, nitem, total, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg) {
   const int n = a.nbeam;

@@ -45,9 +45,27 @@ struct WaveLds {
   static __host__ __device__ size_t bytes(int n) { return red_off(n) + 2 * 64 * sizeof(double); }
 };
 
+__device__ __forceinline__ int find_item_w(const int64_t* cell0, int nitem, int64_t c) {
+  int lo = 0, hi = nitem - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cell0[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// items == nullptr: the cells of g; else the cells of several blocks as one
+// index space (cell0[i] = first global cell of items[i], ascending).
 template <typename T>
-__global__ __launch_bounds__(64) void eig_wave_kernel(EigArgs g) {
+__global__ __launch_bounds__(64) void eig_wave_kernel(EigArgs g, const EigArgs* items,
+                                                      const int64_t* cell0, int nitem) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  int64_t cell = blockIdx.x;
+  if (items) {
+    const int i = find_item_w(cell0, nitem, cell);
+    g = items[i];
+    cell -= cell0[i];
+  }
   using L = WaveLds<T>;
   const int n = g.nbeam;
   const int m = n + (n & 1);
@@ -63,7 +81,6 @@ __global__ __launch_bounds__(64) void eig_wave_kernel(EigArgs g) {
   double* red = (double*)(smem + L::red_off(n));
 
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
-  const int64_t cell = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t cnt = g.count[cell / g.nchan];
   if (cnt < 2 || cnt > RFI_MAX_COUNT) {
@@ -299,7 +316,21 @@ hipError_t launch_t(const EigArgs& a, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)shm);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3((unsigned)ncell), dim3(64), shm, s, a);
+  hipLaunchKernelGGL(kern, dim3((unsigned)ncell), dim3(64), shm, s, a, (const EigArgs*)nullptr,
+                     (const int64_t*)nullptr, 0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_t(int max_nbeam, const EigArgs* items, const int64_t* cell0, int nitem,
+                          int64_t total, hipStream_t s) {
+  const size_t shm = WaveLds<T>::bytes(max_nbeam);
+  const auto kern = eig_wave_kernel<T>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)shm);
+  if (e != hipSuccess) return e;
+  EigArgs none{};
+  hipLaunchKernelGGL(kern, dim3((unsigned)total), dim3(64), shm, s, none, items, cell0, nitem);
   return hipGetLastError();
 }
 
@@ -307,6 +338,12 @@ hipError_t launch_t(const EigArgs& a, hipStream_t s) {
 
 hipError_t launch_eig_wave(const EigArgs& a, int precision, hipStream_t s) {
   return precision == 64 ? launch_t<double>(a, s) : launch_t<float>(a, s);
+}
+
+hipError_t launch_eig_wave_batch(int precision, int max_nbeam, const EigArgs* items,
+                                 const int64_t* cell0, int nitem, int64_t total, hipStream_t s) {
+  return precision == 64 ? launch_batch_t<double>(max_nbeam, items, cell0, nitem, total, s)
+                         : launch_batch_t<float>(max_nbeam, items, cell0, nitem, total, s);
 }
 
 }  // namespace rfi

@@ -131,12 +131,11 @@ __device__ void pass_sums(const double* stat, const uint8_t* status, const uint8
   __syncthreads();
 }
 
-__global__ __launch_bounds__(FT) void flag_kernel(int nsub, int nchan, const double* __restrict__ stat,
-                                                  const uint8_t* __restrict__ status,
-                                                  const uint8_t* __restrict__ protect, double kappa,
-                                                  int max_iter, rfi_stream_state* state,
-                                                  uint8_t* __restrict__ mask,
-                                                  rfi_flag_stats* out) {
+__device__ __forceinline__ void flag_body(int nsub, int nchan, const double* __restrict__ stat,
+                                          const uint8_t* __restrict__ status,
+                                          const uint8_t* __restrict__ protect, double kappa,
+                                          int max_iter, rfi_stream_state* state,
+                                          uint8_t* __restrict__ mask, rfi_flag_stats* out) {
   __shared__ Shared sh;
   const int64_t ncell = (int64_t)nsub * nchan;
   // pooled history (thread 0 only uses it)
@@ -219,6 +218,22 @@ __global__ __launch_bounds__(FT) void flag_kernel(int nsub, int nchan, const dou
       state->nblocks += 1;
     }
   }
+}
+
+__global__ __launch_bounds__(FT) void flag_kernel(int nsub, int nchan, const double* __restrict__ stat,
+                                                  const uint8_t* __restrict__ status,
+                                                  const uint8_t* __restrict__ protect, double kappa,
+                                                  int max_iter, rfi_stream_state* state,
+                                                  uint8_t* __restrict__ mask,
+                                                  rfi_flag_stats* out) {
+  flag_body(nsub, nchan, stat, status, protect, kappa, max_iter, state, mask, out);
+}
+
+// Batched: one workgroup per block, each clipping its own cells.
+__global__ __launch_bounds__(FT) void flag_batch_kernel(const FlagItem* __restrict__ items) {
+  const FlagItem& it = items[blockIdx.x];
+  flag_body(it.nsub, it.nchan, it.stat, it.status, it.protect, it.kappa, it.max_iter, it.state,
+            it.mask, it.out);
 }
 
 // ---------------------------------------------------------------------------
@@ -514,6 +529,11 @@ hipError_t launch_flag(int nsub, int nchan, const double* stat, const uint8_t* s
   void* args[] = {&nsub, &nchan, &stat, &status, &protect_chan, &kappa, &max_iter,
                   &state, &mask, &out, &ws};
   return hipLaunchCooperativeKernel((const void*)flag_coop_kernel, dim3(nwg), dim3(CT), args, 0, s);
+}
+
+hipError_t launch_flag_batch(const FlagItem* items, int nitem, hipStream_t s) {
+  hipLaunchKernelGGL(flag_batch_kernel, dim3((unsigned)nitem), dim3(FT), 0, s, items);
+  return hipGetLastError();
 }
 
 hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float* v1,

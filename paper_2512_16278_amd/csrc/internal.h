@@ -15,6 +15,28 @@ struct BeamPtrs {
 
 inline int npair_of(int n) { return n * (n + 1) / 2; }
 
+// One block of a batched sums launch (device descriptor). The block's
+// workgroups are [wg0, wg0 + 8 ceil(nsub * nct / 8)); wg0 is a multiple of 8.
+struct CcmItem {
+  const uint8_t* const* beams;   // device table [nbeam] of beam pointers
+  int64_t row_stride, t0;
+  int32_t* sum_x;
+  int32_t* sum_xy;
+  int32_t* count;
+  int32_t nbeam, nchan, L, nsub;
+  int32_t nct, nh, wg0, pad;
+};
+// Instance class of the MFMA sums engine for a beam count: blocks of one
+// class share a batched launch; cw = channels per tile, nh = epilogue passes.
+struct CcmClass {
+  int key, cw, nh;
+};
+hipError_t ccm_class(int nbeam, CcmClass* c);
+// Batched sums launch over the items of one class (items in device memory,
+// sorted by wg0); nbeam_of_class is any member's beam count.
+hipError_t launch_ccm_batch(int nbeam_of_class, const CcmItem* items, int nitem, int total_wg,
+                            hipStream_t s);
+
 // Kernel launchers (return a HIP error code; arguments already validated).
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
@@ -38,8 +60,30 @@ struct EigArgs {
 // FP32, nbeam <= 20; wg = lanes (cells) per workgroup: 64, 128 or 256
 hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg = 256);
 hipError_t launch_eig_wave(const EigArgs& a, int precision, hipStream_t s);  // any nbeam
+// Batched eigen stage over the cells of several blocks, one index space:
+// items[i] (device) describes block i, cell0[i] (device, ascending) is its
+// first global cell, total the number of cells. The per-lane solver takes
+// one template class of beam counts (eig_lane_class(n), 0 = none); the
+// per-wave solver any beam counts up to max_nbeam.
+int eig_lane_class(int n);
+hipError_t launch_eig_lane_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
+                                 int64_t total, hipStream_t s);
+hipError_t launch_eig_wave_batch(int precision, int max_nbeam, const EigArgs* items,
+                                 const int64_t* cell0, int nitem, int64_t total, hipStream_t s);
 
 size_t flag_workspace_size(int nsub, int nchan);
+// One block of a batched clip (device descriptor); one workgroup per block.
+struct FlagItem {
+  int32_t nsub, nchan, max_iter, pad;
+  double kappa;
+  const double* stat;
+  const uint8_t* status;
+  const uint8_t* protect;
+  rfi_stream_state* state;
+  uint8_t* mask;
+  rfi_flag_stats* out;
+};
+hipError_t launch_flag_batch(const FlagItem* items, int nitem, hipStream_t s);
 hipError_t launch_flag(int nsub, int nchan, const double* stat, const uint8_t* status,
                        const uint8_t* protect_chan, double kappa, int max_iter,
                        rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,

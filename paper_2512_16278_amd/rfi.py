@@ -64,6 +64,18 @@ class rfi_process_params(C.Structure):
                 ("kappa", C.c_double)]
 
 
+class rfi_batch_item(C.Structure):
+    _fields_ = [("blk", C.POINTER(rfi_block)), ("t0", C.c_int64), ("L", C.c_int32),
+                ("nsub", C.c_int32), ("protect_chan", C.c_void_p), ("state", C.c_void_p),
+                ("stat", C.c_void_p), ("status", C.c_void_p), ("mask", C.c_void_p),
+                ("out", C.c_void_p)]
+
+
+class rfi_batch_params(C.Structure):
+    _fields_ = [("eig_precision", C.c_int32), ("max_sweeps", C.c_int32), ("max_iter", C.c_int32),
+                ("pad", C.c_int32), ("kappa", C.c_double)]
+
+
 class rfi_session_config(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32), ("hbm_budget", C.c_int64)]
 
@@ -137,13 +149,24 @@ def lib():
         L.rfi_cancel.argtypes = [vp, u64]
         L.rfi_result_release.argtypes = [vp, u64]
         L.rfi_result_copy.argtypes = [vp, u64, vp, vp, vp]
+        L.rfi_batch_workspace_size.argtypes = [i32, C.POINTER(rfi_batch_item),
+                                               C.POINTER(rfi_batch_params)]
+        L.rfi_batch_workspace_size.restype = C.c_size_t
+        L.rfi_process_batch.argtypes = [i32, C.POINTER(rfi_batch_item),
+                                        C.POINTER(rfi_batch_params), vp, vp]
+        L.rfi_batch_graph_create.argtypes = [i32, C.POINTER(rfi_batch_item),
+                                             C.POINTER(rfi_batch_params), vp, C.POINTER(vp)]
+        L.rfi_batch_graph_launch.argtypes = [vp, vp]
+        L.rfi_batch_graph_destroy.argtypes = [vp]
+        L.rfi_batch_graph_destroy.restype = None
         L.rfi_stream_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
         L.rfi_stream_import.argtypes = [vp, i32, vp, C.c_size_t]
         for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_eigvec_flag",
                   "rfi_process_block", "rfi_session_create", "rfi_stream_open",
                   "rfi_stream_close", "rfi_submit", "rfi_poll", "rfi_wait", "rfi_cancel",
                   "rfi_result_release", "rfi_stream_export", "rfi_stream_import",
-                  "rfi_result_copy"):
+                  "rfi_result_copy", "rfi_process_batch", "rfi_batch_graph_create",
+                  "rfi_batch_graph_launch"):
             getattr(L, f).restype = i32
         L.rfi_last_error.restype = C.c_char_p
         L.rfi_version.restype = C.c_char_p
@@ -246,6 +269,65 @@ def rfi_eigvec_flag(nbeam, nsub, nchan, v1, mask, status, beam_mask, protect_cha
     _check(lib().rfi_eigvec_flag(int(nbeam), int(nsub), int(nchan), _ptr(v1), _ptr(mask),
                                  _ptr(status), _ptr(protect_chan), float(kappa_v), _ptr(beam_mask),
                                  _ptr(beam_mu), _ptr(beam_sigma), _stream(stream)))
+
+
+# --- batched uneven blocks --------------------------------------------------------
+
+class Batch:
+    """Items for rfi_process_batch / rfi_batch_graph_*. Each item is
+    (block, t0, L, nsub, stat, status, mask[, out, state, protect_chan]) with
+    device tensors; the ctypes structures are kept alive here."""
+
+    def __init__(self, items, eig_precision=32, max_sweeps=12, max_iter=50, kappa=3.0):
+        self._blocks = [it["blk"] for it in items]
+        n = len(items)
+        self.n = n
+        self.arr = (rfi_batch_item * max(n, 1))()
+        for i, it in enumerate(items):
+            a = self.arr[i]
+            a.blk = C.pointer(self._blocks[i])
+            a.t0 = int(it.get("t0", 0))
+            a.L = int(it["L"])
+            a.nsub = int(it["nsub"])
+            a.protect_chan = _ptr(it.get("protect_chan"))
+            a.state = _ptr(it.get("state"))
+            a.stat = _ptr(it["stat"])
+            a.status = _ptr(it["status"])
+            a.mask = _ptr(it["mask"])
+            a.out = _ptr(it.get("out"))
+        self.p = rfi_batch_params(int(eig_precision), int(max_sweeps), int(max_iter), 0,
+                                  float(kappa))
+
+    def workspace_size(self):
+        return int(lib().rfi_batch_workspace_size(self.n, self.arr, C.byref(self.p)))
+
+    def run(self, workspace, stream=None):
+        _check(lib().rfi_process_batch(self.n, self.arr, C.byref(self.p), _ptr(workspace),
+                                       _stream(stream)))
+
+    def graph(self, workspace):
+        return BatchGraph(self, workspace)
+
+
+class BatchGraph:
+    def __init__(self, batch: Batch, workspace):
+        self.h = C.c_void_p()
+        _check(lib().rfi_batch_graph_create(batch.n, batch.arr, C.byref(batch.p), _ptr(workspace),
+                                            C.byref(self.h)))
+
+    def launch(self, stream=None):
+        _check(lib().rfi_batch_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().rfi_batch_graph_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # --- serving session ------------------------------------------------------------

@@ -1,0 +1,169 @@
+"""GPU: batched uneven blocks (rfi_process_batch) and its HIP graph.
+
+A batch of blocks with different beam counts (all four sums-engine classes
+and both eigen solvers), channel counts and sub-interval lengths, some with
+offsets, a stream state or preserved channels, must give for every block
+exactly what rfi_process_block gives for it alone (same kernels' arithmetic,
+bit for bit), and the statistic and mask of the oracle. The graph is replayed
+several times with eager work between replays; every replay must reproduce
+the eager batch.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import say, upload
+from oracle import clip, pipeline
+
+pytestmark = pytest.mark.gpu
+
+# (nbeam, nchan, L, nsub, t0)
+SHAPES = [(7, 100, 256, 5, 0), (19, 64, 512, 4, 3), (36, 40, 300, 3, 0), (72, 33, 128, 2, 0),
+          (19, 200, 128, 6, 0), (12, 64, 1000, 2, 5), (3, 17, 64, 3, 0)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2512_16278_amd import rfi
+    rfi.lib()
+    return torch.device("cuda:0")
+
+
+def _data(nbeam, nchan, nsamp, seed):
+    rng = np.random.default_rng(seed)
+    x = 128 + 20 * rng.standard_normal((nbeam, nsamp, nchan))
+    t = np.arange(nsamp)
+    for j in rng.choice(nchan, size=max(1, nchan // 20), replace=False):
+        g = rng.uniform(0.5, 1.5, nbeam)
+        x[:, :, j] += 12 * g[:, None] * np.sin(2 * np.pi * t / 31.0 + j)[None, :]
+    return np.clip(np.rint(x), 0, 255).astype(np.uint8)
+
+
+def _outputs(nb, nc, nsub, dev):
+    import torch
+    n = nsub * nc
+    return (torch.full((n,), -1.0, dtype=torch.float64, device=dev),
+            torch.full((n,), 0xEE, dtype=torch.uint8, device=dev),
+            torch.full((n,), 7, dtype=torch.uint8, device=dev),
+            torch.zeros(48, dtype=torch.uint8, device=dev))
+
+
+def _make(dev):
+    import torch
+    from paper_2512_16278_amd import rfi
+    blocks = []
+    for i, (nb, nc, L, nsub, t0) in enumerate(SHAPES):
+        x = _data(nb, nc, t0 + nsub * L + 7, 300 + i)
+        buf = upload(x, dev)
+        prot = None
+        if i == 4:
+            p = np.zeros(nc, np.uint8)
+            p[10:20] = 1
+            prot = torch.from_numpy(p).to(dev)
+        state = torch.zeros(len(bytes(rfi.rfi_stream_state())), dtype=torch.uint8,
+                            device=dev) if i == 1 else None
+        blocks.append(dict(x=x, buf=buf, blk=rfi.make_block(buf, nc), nb=nb, nc=nc, L=L,
+                           nsub=nsub, t0=t0, protect_chan=prot, state=state))
+    return blocks
+
+
+def _single(b, dev, state=None):
+    import torch
+    from paper_2512_16278_amd import rfi
+    stat, status, mask, out = _outputs(b["nb"], b["nc"], b["nsub"], dev)
+    p = rfi.process_params(b["L"], b["nsub"], t0=b["t0"])
+    ws = torch.empty(rfi.rfi_process_workspace_size(b["nb"], b["nc"], p), dtype=torch.uint8,
+                     device=dev)
+    rfi.rfi_process_block(b["blk"], p, stat, status, mask, ws, protect_chan=b["protect_chan"],
+                          state=state, out=out)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in (stat, status, mask, out)]
+
+
+def _batch_items(blocks, dev):
+    items = []
+    for b in blocks:
+        stat, status, mask, out = _outputs(b["nb"], b["nc"], b["nsub"], dev)
+        items.append(dict(blk=b["blk"], t0=b["t0"], L=b["L"], nsub=b["nsub"], stat=stat,
+                          status=status, mask=mask, out=out, protect_chan=b["protect_chan"],
+                          state=b["state"]))
+    return items
+
+
+def test_batch_equals_single_blocks_and_oracle(dev):
+    import torch
+    from paper_2512_16278_amd import rfi
+    blocks = _make(dev)
+    ref = []
+    for b in blocks:
+        st = None
+        if b["state"] is not None:
+            st = torch.zeros_like(b["state"])
+        say("batch: single block", b["nb"], b["nc"], b["L"], b["nsub"])
+        ref.append(_single(b, dev, st) + [None if st is None else st.cpu().numpy()])
+    items = _batch_items(blocks, dev)
+    bt = rfi.Batch(items)
+    ws = torch.empty(bt.workspace_size(), dtype=torch.uint8, device=dev)
+    say("batch: rfi_process_batch of", len(items))
+    bt.run(ws)
+    torch.cuda.synchronize()
+    for b, it, r in zip(blocks, items, ref):
+        got = [it[k].cpu().numpy() for k in ("stat", "status", "mask", "out")]
+        for u, v in zip(got, r[:4]):
+            assert np.array_equal(u, v), (b["nb"], b["nc"])
+        if r[4] is not None:
+            assert np.array_equal(b["state"].cpu().numpy(), r[4])
+    for b, it in zip(blocks, items):
+        cr = pipeline.cells(b["x"], b["L"], b["nsub"], t0=b["t0"])
+        ok = pipeline.eligible_cells(cr.degenerate, None if b["protect_chan"] is None
+                                     else b["protect_chan"].cpu().numpy())
+        res = clip.clip_iterative(cr.stat.ravel(), ok.ravel())
+        assert np.abs(it["stat"].cpu().numpy() - cr.stat.ravel()).max() <= 1e-9, b["nb"]
+        assert np.array_equal(it["mask"].cpu().numpy().astype(bool), res.mask), b["nb"]
+
+
+def test_batch_graph_replays(dev):
+    import torch
+    from paper_2512_16278_amd import rfi
+    blocks = [b for b in _make(dev)]
+    for b in blocks:
+        b["state"] = None
+    items = _batch_items(blocks, dev)
+    bt = rfi.Batch(items)
+    ws = torch.empty(bt.workspace_size(), dtype=torch.uint8, device=dev)
+    bt.run(ws)
+    torch.cuda.synchronize()
+    eager = [[it[k].cpu().numpy() for k in ("stat", "status", "mask", "out")] for it in items]
+    say("batch: graph")
+    g = bt.graph(ws)
+    for rep in range(3):
+        for it in items:                               # eager work between replays
+            it["stat"].fill_(-3.0)
+            it["mask"].fill_(9)
+            it["status"].fill_(0xAB)
+        junk = torch.randn(1 << 20, device=dev).sum()
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+        for it, e in zip(items, eager):
+            got = [it[k].cpu().numpy() for k in ("stat", "status", "mask", "out")]
+            for u, v in zip(got, e):
+                assert np.array_equal(u, v), rep
+    g.close()
+
+
+def test_batch_empty_and_errors(dev):
+    import torch
+    from paper_2512_16278_amd import rfi
+    bt = rfi.Batch([])
+    assert bt.workspace_size() > 0
+    bt.run(torch.empty(256, dtype=torch.uint8, device=dev))
+    b = _make(dev)[0]
+    stat, status, mask, out = _outputs(b["nb"], b["nc"], b["nsub"], dev)
+    bad = rfi.Batch([dict(blk=b["blk"], L=b["L"], nsub=b["nsub"] + 50, stat=stat, status=status,
+                          mask=mask)])
+    assert bad.workspace_size() == 0
+    with pytest.raises(rfi.RfiError):
+        bad.run(torch.empty(256, dtype=torch.uint8, device=dev))
