@@ -245,6 +245,8 @@ def main():
                     help="arrival rates (blocks/s) of the serving run; empty = skip it")
     ap.add_argument("--serve-blocks", type=int, default=40, help="blocks per serving rate")
     ap.add_argument("--no-precision-split", action="store_true")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving loop and print its JSON")
     ap.add_argument("--quick", action="store_true",
                     help="time the steps only (no latency, stage split or CPU baseline)")
     ap.add_argument("--profile-run", action="store_true",
@@ -261,6 +263,10 @@ def main():
     from paper_2512_16278_amd import rfi, synth
 
     dev = torch.device("cuda:0")
+    if args.serve_only:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        print(json.dumps({"serving": serve_bench(dev, rates, args.serve_blocks)}), flush=True)
+        return
     spec = synth.fast_spec(seconds=args.seconds)
     nb, nc, ns, L = spec.nbeam, spec.nchan, spec.nsamp, spec.L
     nsub = ns // L

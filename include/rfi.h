@@ -97,14 +97,23 @@ rfi_status rfi_ccm_accumulate(const rfi_block* blk /* host */, int64_t t0, int32
                               int32_t* count, int32_t accumulate, int32_t variant,
                               rfi_stream_t stream);
 
-/* Eigen solver selection */
-enum { RFI_EIG_AUTO = 0, RFI_EIG_LANE = 1, RFI_EIG_WAVE = 2 };
+/* Eigen solver selection:
+ *  RFI_EIG_LANE    cyclic Jacobi, FP32, one cell per lane in registers, nbeam <= 20;
+ *  RFI_EIG_WAVE    cyclic Jacobi (round-robin parallel ordering), one cell per
+ *                  wavefront in LDS, FP32 or FP64, any nbeam;
+ *  RFI_EIG_TRIDIAG Householder reduction to tridiagonal form and Sturm
+ *                  bisection (Golub & Van Loan Sec. 8.3-8.4), FP64, one cell per
+ *                  wavefront in LDS, any nbeam: about (4/3) n^3 flops per cell
+ *                  instead of 6 n^3 per Jacobi sweep.
+ *  RFI_EIG_AUTO    LANE for FP32 and nbeam <= 20, TRIDIAG for FP32 and more
+ *                  beams, WAVE for FP64 (FP64 Jacobi). */
+enum { RFI_EIG_AUTO = 0, RFI_EIG_LANE = 1, RFI_EIG_WAVE = 2, RFI_EIG_TRIDIAG = 3 };
 
 typedef struct {
   int32_t precision;     /* 32: FP32 Jacobi (default); 64: FP64 Jacobi */
   int32_t max_sweeps;    /* cyclic Jacobi sweep cap, 1..30 (default 12) */
   int32_t refine;        /* 1: lambda_1 by an FP64 Rayleigh quotient (default) */
-  int32_t solver;        /* RFI_EIG_AUTO | _LANE (nbeam <= 20, FP32) | _WAVE */
+  int32_t solver;        /* RFI_EIG_AUTO | _LANE (nbeam <= 20, FP32) | _WAVE | _TRIDIAG */
 } rfi_eig_params;
 
 /* Per cell (Sec. 3.2-3.3): the Pearson correlation matrix

@@ -1,6 +1,6 @@
 """Build the HIP libraries in-tree for gfx950 (hipcc cross-compiles; no GPU needed).
 
-librfi.so       -- the method (csrc/api.cpp, pipeline.cpp, ccm.hip, eig_lane.hip, eig_wave.hip,
+librfi.so       -- the method (csrc/api.cpp, pipeline.cpp, ccm.hip, eig_lane.hip, eig_wave.hip, eig_tri.hip,
                    flag.hip, serve.cpp, batch.cpp)
 librfi_synth.so -- the GPU input generator (csrc/synth.hip) and the streaming-read
                    reference of the HBM roofline (csrc/stream_read.hip)
@@ -30,7 +30,7 @@ COMMON = [
 ]
 
 LIBS = {
-    "librfi.so": ["api.cpp", "pipeline.cpp", "ccm.hip", "eig_lane.hip", "eig_wave.hip", "flag.hip",
+    "librfi.so": ["api.cpp", "pipeline.cpp", "ccm.hip", "eig_lane.hip", "eig_wave.hip", "eig_tri.hip", "flag.hip",
                   "serve.cpp", "batch.cpp"],
     "librfi_synth.so": ["synth.hip", "stream_read.hip"],
 }

@@ -72,13 +72,22 @@ rfi_status resolve_eig(int nbeam, const rfi_eig_params* p, rfi_eig_params* out,
   if (prm.max_sweeps < 1 || prm.max_sweeps > 30)
     return fail(RFI_E_INVALID, "%s: max_sweeps %d outside 1..30", who, prm.max_sweeps);
   if (prm.solver == RFI_EIG_AUTO)
-    prm.solver = (prm.precision == 32 && nbeam <= 20) ? RFI_EIG_LANE : RFI_EIG_WAVE;
+    prm.solver = prm.precision == 64 ? RFI_EIG_WAVE
+                                     : (nbeam <= 20 ? RFI_EIG_LANE : RFI_EIG_TRIDIAG);
   if (prm.solver == RFI_EIG_LANE && (prm.precision != 32 || nbeam > 20))
     return fail(RFI_E_INVALID, "%s: the per-lane solver is FP32 and nbeam <= 20", who);
-  if (prm.solver != RFI_EIG_LANE && prm.solver != RFI_EIG_WAVE)
+  if (prm.solver != RFI_EIG_LANE && prm.solver != RFI_EIG_WAVE && prm.solver != RFI_EIG_TRIDIAG)
     return fail(RFI_E_INVALID, "%s: unknown solver %d", who, prm.solver);
   *out = prm;
   return RFI_OK;
+}
+
+hipError_t launch_eig(const EigArgs& a, const rfi_eig_params& p, hipStream_t s, int lane_wg) {
+  switch (p.solver) {
+    case RFI_EIG_LANE: return launch_eig_lane(a, s, lane_wg);
+    case RFI_EIG_TRIDIAG: return launch_eig_tri(a, s);
+    default: return launch_eig_wave(a, p.precision, s);
+  }
 }
 
 }  // namespace rfi
@@ -150,9 +159,7 @@ rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan, const int
     const int v = e ? atoi(e) : 256;
     return v == 64 || v == 128 ? v : 256;
   }();
-  const hipError_t e = prm.solver == RFI_EIG_LANE ? rfi::launch_eig_lane(a, s, wg)
-                                                  : rfi::launch_eig_wave(a, prm.precision, s);
-  return check_hip(e, "rfi_eig_batched launch");
+  return check_hip(rfi::launch_eig(a, prm, s, wg), "rfi_eig_batched launch");
 }
 
 size_t rfi_flag_workspace_size(int32_t nsub, int32_t nchan) {

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <vector>
 
@@ -32,13 +33,13 @@ struct ItemPlan {
   int nbeam, nchan;
   int64_t ncell;
   CcmClass cc;
-  int solver, precision;   // eigen class
+  int solver, precision;   // eigen class (solver, precision)
   int lane_cls;
   size_t sums_off;         // byte offset of the item's sums in the workspace
 };
 
 struct EigClass {
-  int lane_cls, precision, max_nbeam;
+  int lane_cls, solver, precision, max_nbeam;
   std::vector<int> items;  // indices into plans
 };
 
@@ -97,14 +98,16 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
   const int n = (int)bpn->plans.size();
   // classes
   std::map<int, std::vector<int>> ccm;
-  std::map<std::pair<int, int>, std::vector<int>> eig;   // (lane class or 0, precision)
+  // (lane class or 0, solver, precision)
+  std::map<std::tuple<int, int, int>, std::vector<int>> eig;
   for (int k = 0; k < n; ++k) {
     ccm[bpn->plans[k].cc.key].push_back(k);
-    eig[{bpn->plans[k].lane_cls, bpn->plans[k].precision}].push_back(k);
+    eig[{bpn->plans[k].lane_cls, bpn->plans[k].solver, bpn->plans[k].precision}].push_back(k);
   }
   for (auto& kv : ccm) bpn->ccm_classes.push_back({bpn->plans[kv.second[0]].nbeam, kv.second});
   for (auto& kv : eig) {
-    EigClass ec{kv.first.first, kv.first.second, 0, kv.second};
+    EigClass ec{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), 0,
+                kv.second};
     for (int k : kv.second) ec.max_nbeam = std::max(ec.max_nbeam, bpn->plans[k].nbeam);
     bpn->eig_classes.push_back(ec);
   }
@@ -227,9 +230,12 @@ hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipSt
   for (const EigClass& ec : bpn.eig_classes) {
     const int m = (int)ec.items.size();
     const int64_t total = hc0[cpos + m];
-    e = ec.lane_cls ? launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s)
-                    : launch_eig_wave_batch(ec.precision, ec.max_nbeam, ea + pos, c0 + cpos, m,
-                                            total, s);
+    if (ec.solver == RFI_EIG_LANE)
+      e = launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s);
+    else if (ec.solver == RFI_EIG_TRIDIAG)
+      e = launch_eig_tri_batch(ec.max_nbeam, ea + pos, c0 + cpos, m, total, s);
+    else
+      e = launch_eig_wave_batch(ec.precision, ec.max_nbeam, ea + pos, c0 + cpos, m, total, s);
     if (e != hipSuccess) return e;
     pos += m;
     cpos += m + 1;

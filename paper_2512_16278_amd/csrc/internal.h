@@ -60,6 +60,9 @@ struct EigArgs {
 // FP32, nbeam <= 20; wg = lanes (cells) per workgroup: 64, 128 or 256
 hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg = 256);
 hipError_t launch_eig_wave(const EigArgs& a, int precision, hipStream_t s);  // any nbeam
+hipError_t launch_eig_tri(const EigArgs& a, hipStream_t s);               // any nbeam, FP64
+// The eigen stage of one block with resolved parameters (solver, precision).
+hipError_t launch_eig(const EigArgs& a, const rfi_eig_params& p, hipStream_t s, int lane_wg = 256);
 // Batched eigen stage over the cells of several blocks, one index space:
 // items[i] (device) describes block i, cell0[i] (device, ascending) is its
 // first global cell, total the number of cells. The per-lane solver takes
@@ -70,6 +73,8 @@ hipError_t launch_eig_lane_batch(int cls, const EigArgs* items, const int64_t* c
                                  int64_t total, hipStream_t s);
 hipError_t launch_eig_wave_batch(int precision, int max_nbeam, const EigArgs* items,
                                  const int64_t* cell0, int nitem, int64_t total, hipStream_t s);
+hipError_t launch_eig_tri_batch(int max_nbeam, const EigArgs* items, const int64_t* cell0,
+                                int nitem, int64_t total, hipStream_t s);
 
 size_t flag_workspace_size(int nsub, int nchan);
 // One block of a batched clip (device descriptor); one workgroup per block.

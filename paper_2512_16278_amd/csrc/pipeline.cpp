@@ -150,8 +150,7 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
     EigArgs a{pl.nbeam, ks, pl.nchan, sx, sxy, cnt, pl.eig.max_sweeps, 1,
               eigvals ? eigvals + off : nullptr, stat + off, v1 ? v1 + off : nullptr,
               status + off, out_stride};
-    e = pl.eig.solver == RFI_EIG_LANE ? launch_eig_lane(a, ev.aux, lane_wg())
-                                      : launch_eig_wave(a, pl.eig.precision, ev.aux);
+    e = launch_eig(a, pl.eig, ev.aux, lane_wg());
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ev.eig[slot], ev.aux)) != hipSuccess) return e;
   }

@@ -250,8 +250,7 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
   if (b.carried) {
     EigArgs a{n, 1, F, st.carry_sx(), st.carry_sxy(), st.carry_cnt(), b.pl.eig.max_sweeps, 1,
               nullptr, r->stat, nullptr, r->cstat, (int64_t)b.nsub * F};
-    e = b.pl.eig.solver == RFI_EIG_LANE ? launch_eig_lane(a, s)
-                                        : launch_eig_wave(a, b.pl.eig.precision, s);
+    e = launch_eig(a, b.pl.eig, s);
     if (e != hipSuccess) return dev(e, "rfi_submit: carry eigen stage");
   }
   // 2. full sub-intervals

@@ -194,13 +194,28 @@ def test_eig_wave(dev, nbeam, precision):
     _check_eig(x, L, nsub, out, tol_l, tol_s)
 
 
+@pytest.mark.parametrize("nbeam", [2, 3, 7, 19, 36, 47, 64, 65, 72, 79])
+def test_eig_tridiag(dev, nbeam):
+    """Householder-tridiagonal FP64 solver: eigenvalues (FP32 output) within
+    1e-6 of lambda_1, statistic within 1e-12, v1 as for the other solvers."""
+    rng = np.random.default_rng(400 + nbeam)
+    L, nsub, nc = 160, 2, 11
+    x = np.clip(np.rint(128 + 20 * rng.standard_normal((nbeam, nsub * L, nc))), 0, 255).astype(np.uint8)
+    common = np.rint(12 * np.sin(np.arange(nsub * L) / 3.0)).astype(np.int64)
+    x[:, :, 2] = np.clip(x[:, :, 2].astype(np.int64) + common[None, :], 0, 255)
+    x[: nbeam // 2, :, 5] = np.clip(x[: nbeam // 2, :, 5].astype(np.int64) + common[None, :], 0, 255)
+    out = _eig_case(dev, x, L, nsub, 32, 3)
+    status, _ = _check_eig(x, L, nsub, out, 1e-6, 1e-12)
+    assert (status == 0).all()
+
+
 def test_eig_degenerate_cells(dev):
     rng = np.random.default_rng(7)
     nb, L, nsub, nc = 19, 64, 2, 20
     x = rng.integers(0, 256, size=(nb, nsub * L, nc), dtype=np.uint8)
     x[4, :L, 5] = 77                 # constant beam in cell (0, 5)
     x[:, L:, 9] = 3                  # every beam constant in cell (1, 9)
-    for solver, prec in ((1, 32), (2, 32), (2, 64)):
+    for solver, prec in ((1, 32), (2, 32), (2, 64), (3, 32)):
         stat, status, ev, v1 = _eig_case(dev, x, L, nsub, prec, solver)
         cr = pipeline.cells(x, L, nsub)
         deg = cr.degenerate.ravel()
