@@ -144,6 +144,84 @@ def precision_split(dev, spec, data, blk, nsub, ev_time):
     return out
 
 
+def batch_bench(dev, nblocks=24, seed=11):
+    """Uneven blocks (beam counts 7/19/36/72, channels 1024/4096/8192, L
+    512/1024/4096, 0.1-2 s each) through (a) one rfi_process_block per
+    block on one stream, (b) one rfi_process_batch, (c) one replay of the
+    batch's HIP graph. Same blocks, same outputs; throughput in beam-sample
+    GB/s of the full sub-intervals."""
+    import torch
+    from paper_2512_16278_amd import rfi, synth
+    rng = np.random.default_rng(seed)
+    pools = {}
+    for F in MIX_NCHAN:
+        spec = synth.mixed_spec(seed + F, max(MIX_NBEAM), F, 512, 2.1)
+        t = torch.empty((spec.nbeam, spec.nsamp, F), dtype=torch.uint8, device=dev)
+        ds = rfi.DeviceSynth(spec, dev)
+        for b in range(spec.nbeam):
+            ds.fill(t[b], b)
+        pools[F] = t
+    items, blocks, nbytes = [], [], 0
+    per_class = {}
+    for _ in range(nblocks):
+        nb, F, L = int(rng.choice(MIX_NBEAM)), int(rng.choice(MIX_NCHAN)), int(rng.choice(MIX_L))
+        nsamp = int(rng.uniform(0.1, 2.0) / synth.TSAMP)
+        nsub = nsamp // L
+        if nsub == 0:
+            continue
+        start = int(rng.integers(0, pools[F].shape[1] - nsamp))
+        pool = pools[F]
+        blk = rfi.make_block([pool[b, start:start + nsamp] for b in range(nb)], F)
+        n = nsub * F
+        it = dict(blk=blk, L=L, nsub=nsub,
+                  stat=torch.empty(n, dtype=torch.float64, device=dev),
+                  status=torch.empty(n, dtype=torch.uint8, device=dev),
+                  mask=torch.empty(n, dtype=torch.uint8, device=dev))
+        items.append(it)
+        nbytes += nb * F * nsub * L
+        per_class[nb] = per_class.get(nb, 0) + nb * F * nsub * L
+    stream = torch.cuda.current_stream()
+    wss = []
+    for it in items:
+        p = rfi.process_params(it["L"], it["nsub"])
+        nbm = it["blk"].nbeam
+        wss.append((p, torch.empty(rfi.rfi_process_workspace_size(nbm, it["blk"].nchan, p),
+                                   dtype=torch.uint8, device=dev)))
+
+    def separate():
+        for it, (p, ws) in zip(items, wss):
+            rfi.rfi_process_block(it["blk"], p, it["stat"], it["status"], it["mask"], ws)
+
+    bt = rfi.Batch(items)
+    bws = torch.empty(bt.workspace_size(), dtype=torch.uint8, device=dev)
+    g = bt.graph(bws)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    t_sep = timed(separate)
+    t_bat = timed(lambda: bt.run(bws))
+    t_gr = timed(lambda: g.launch())
+    g.close()
+    out = {"blocks": len(items), "bytes_gb": round(nbytes / 1e9, 2),
+           "bytes_by_nbeam_gb": {str(k): round(v / 1e9, 2) for k, v in sorted(per_class.items())},
+           "separate_ms": round(t_sep, 3), "batch_ms": round(t_bat, 3), "graph_ms": round(t_gr, 3),
+           "separate_gbs": round(nbytes / t_sep / 1e6, 1), "graph_gbs": round(nbytes / t_gr / 1e6, 1)}
+    del pools
+    torch.cuda.empty_cache()
+    return out
+
+
 def serve_bench(dev, rates, nblocks, nstreams=8, seed=7, slots=8, budget=64 << 30):
     """Serving loop: Poisson arrivals of uneven blocks from nstreams streams.
 
@@ -245,6 +323,7 @@ def main():
                     help="arrival rates (blocks/s) of the serving run; empty = skip it")
     ap.add_argument("--serve-blocks", type=int, default=40, help="blocks per serving rate")
     ap.add_argument("--no-precision-split", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving loop and print its JSON")
     ap.add_argument("--quick", action="store_true",
@@ -397,11 +476,20 @@ def main():
     ccm_bytes = nbytes_in + 4 * (nb + npair) * ncell          # bytes in + sums out
     ccm_gbs = ccm_bytes / (ms_ccm / 1e3) / 1e9
     flags = rfi.flag_stats_from_bytes(fstats.cpu().numpy().tobytes())
+    # HBM bytes of the sums kernel from the committed counter summary, while
+    # the kernel's source is the one those counters were taken on
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "ccm_traffic_fast19x4096.json")
+    if os.path.exists(tpath):
+        from paper_2512_16278_amd import prof_summary
+        rec = json.load(open(tpath))
+        if rec.get("source_sha256") == prof_summary.source_hash() and rec.get("traffic_bytes"):
+            traffic = int(rec["traffic_bytes"])
     if ms_ccm >= ms_eig:
         roof = {"kernel": "ccm_mfma_kernel (64-channel tile, one launch per block)"
                           if variant == rfi.RFI_CCM_MFMA else "ccm_valu_kernel",
                 "bound": "hbm", "achieved": round(ccm_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ccm_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ccm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "ms": round(float(ms_ccm), 4)}
     else:
         # algorithmic FP32 flops of the Jacobi: per sweep n(n-1)/2 rotations of
@@ -432,8 +520,14 @@ def main():
         log(f"precision split: {psplit}")
 
     serving = None
-    if args.serve_rates:
+    batch = None
+    if args.serve_rates or not args.no_batch:
         del data
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        batch = batch_bench(dev)
+        log(f"uneven batch: {batch}")
+    if args.serve_rates:
         torch.cuda.empty_cache()
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         serving = serve_bench(dev, rates, args.serve_blocks)
@@ -465,6 +559,7 @@ def main():
         "flagged_cells": int(flags["nflag"]), "clip_iterations": int(flags["iterations"]),
         "roofline": roof,
         "precision_split": psplit,
+        "batch": batch,
         "serving": serving,
         "cpu_baseline": cpu,
     }
