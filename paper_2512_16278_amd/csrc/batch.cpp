@@ -34,7 +34,7 @@ struct ItemPlan {
   int64_t ncell;
   CcmClass cc;
   int solver, precision;   // eigen class (solver, precision)
-  int lane_cls;
+  int lane_cls;            // template class of the per-lane or per-wave tridiagonal solver
   size_t sums_off;         // byte offset of the item's sums in the workspace
 };
 
@@ -91,14 +91,16 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
       return fail(RFI_E_INVALID, "%s: item %d: no sums instance for %d beams", who, i, ip.nbeam);
     ip.solver = res.solver;
     ip.precision = res.precision;
-    ip.lane_cls = res.solver == RFI_EIG_LANE ? eig_lane_class(ip.nbeam) : 0;
+    ip.lane_cls = res.solver == RFI_EIG_LANE      ? eig_lane_class(ip.nbeam)
+                  : res.solver == RFI_EIG_TRIDIAG ? eig_tri_class(ip.nbeam)
+                                                  : 0;
     tab_bytes += (size_t)ip.nbeam * sizeof(void*);
     bpn->plans.push_back(ip);
   }
   const int n = (int)bpn->plans.size();
   // classes
   std::map<int, std::vector<int>> ccm;
-  // (lane class or 0, solver, precision)
+  // (solver template class or 0, solver, precision)
   std::map<std::tuple<int, int, int>, std::vector<int>> eig;
   for (int k = 0; k < n; ++k) {
     ccm[bpn->plans[k].cc.key].push_back(k);
@@ -233,7 +235,7 @@ hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipSt
     if (ec.solver == RFI_EIG_LANE)
       e = launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s);
     else if (ec.solver == RFI_EIG_TRIDIAG)
-      e = launch_eig_tri_batch(ec.max_nbeam, ea + pos, c0 + cpos, m, total, s);
+      e = launch_eig_tri_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s);
     else
       e = launch_eig_wave_batch(ec.precision, ec.max_nbeam, ea + pos, c0 + cpos, m, total, s);
     if (e != hipSuccess) return e;

@@ -5,22 +5,54 @@
 //
 // Work per cell is about (4/3) n^3 flops for the reduction instead of the
 // 6 n^3 per sweep of cyclic Jacobi, and it runs in FP64 at the full vector
-// rate of the chip, so lambda_1 needs no separate refinement:
-//  - reduction: for k = 0 .. n-3 the reflector of column k below the diagonal
-//    (v, beta with v_0 = 1), p = beta A22 v, w = p - (beta p.v / 2) v and
-//    A22 -= v w^T + w v^T; rows are spread over the lanes;
+// rate of the chip, so lambda_1 needs no separate refinement.
+//
+// Register-resident layout: the cell's matrix (padded to 8 NL x 8 NL with
+// zeros) lives in the registers of one wave as an 8 x 8 grid of lanes, lane
+// 8 r + c holding the entries (r + 8 ii, c + 8 jj), ii, jj < NL (a cyclic 2-D
+// distribution, so the shrinking active block stays spread over all lanes).
+// Step k of the reduction:
+//  - row k (= column k) is broadcast through LDS by the 8 lanes that hold it;
+//  - the reflector v (v_{k+1} = 1, zero at indices <= k) and beta;
+//  - p = A v: each lane sums its partial rows, then a DPP reduction over the
+//    8 lanes of a lane row; p goes through LDS to the lanes that hold it as
+//    column indices;
+//  - w = beta p - (beta^2 p.v / 2) v and A -= v w^T + w v^T.
+// The update is the full two-sided product H A H on the whole padded matrix:
+// rows and columns already reduced are only multiplied by the orthogonal H
+// (v vanishes there), so their leftover entries stay bounded and never reach
+// the active block; local rows / columns whose every index is reduced are
+// skipped at compile time (the loop over blocks of 8 steps is unrolled). The
+// diagonal is read back at the end of each block of 8 steps; the
+// sub-diagonal is the reflected column norm of each step (the last step, a
+// single entry, needs no reflection).
+//
+// Then:
 //  - lambda_1 = largest eigenvalue (a correlation matrix is positive
 //    semidefinite, so it is also the largest in magnitude): multisection, the
 //    64 lanes each evaluating the Sturm count at one point of the bracket;
 //  - all eigenvalues (optional): bisection, one eigenvalue index per lane;
 //  - v1 (optional): inverse iteration on the tridiagonal with the shift
-//    lambda_1, then the reflectors applied in reverse order.
+//    lambda_1, then the reflectors (kept in LDS) applied in reverse order.
 #include <math.h>
+
+#include <type_traits>
 
 #include "internal.h"
 
 namespace rfi {
 namespace {
+
+// Compile-time loop: every index into the register-resident matrix must be a
+// constant.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+#define RFI_CI(v) decltype(v)::value
 
 __device__ __forceinline__ int64_t pidx(int a, int b, int n) {
   return (int64_t)a * n - (int64_t)a * (a - 1) / 2 + (b - a);
@@ -32,33 +64,62 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-// LDS layout for an n-beam cell (doubles unless noted): A [n][ld] with the
-// odd row stride ld = n | 1 (rows of one column fall in different banks),
-// then v, w, dinv, alpha (diagonal of T), beta_off (sub-diagonal of T),
-// tau (reflector scales), z, then S (int32).
-struct TriLds {
-  static __host__ __device__ int ld(int n) { return n | 1; }
-  static __host__ __device__ size_t bytes(int n) {
-    return ((size_t)n * ld(n) + 7 * (size_t)n + 64) * sizeof(double) + (size_t)n * 4;
-  }
-};
+// DPP move of a double (two 32-bit halves); every source lane is valid for
+// the patterns used here, so no old value is needed.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 
-// Number of eigenvalues of the tridiagonal (alpha, off) below x (Sturm
-// count: negative pivots of the LDL^T factorisation of T - x I). A pivot
-// that is zero (or nearly) is replaced by a tiny negative one, which keeps
-// the count exact for x on an eigenvalue of a leading block.
-__device__ __forceinline__ int sturm_below(const double* alpha, const double* off, int n,
-                                           double x) {
+// Sum over the 8 consecutive lanes of a lane row (lanes 8 r .. 8 r + 7):
+// lane ^ 1, lane ^ 2 (quad permutations), then the mirror within the 8
+// lanes, which pairs each lane with one of the other quad. Every lane of the
+// row ends with the same bits (each stage adds the same two operands).
+__device__ __forceinline__ double sum8(double x) {
+  x += dpp_mov<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_mov<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_mov<0x141>(x);  // row_half_mirror
+  return x;
+}
+
+// Reciprocal of q to about full FP64 precision: the hardware estimate and one
+// Newton step (a Sturm count needs each pivot to a few ulps only: the count
+// is then exact for a tridiagonal within a few ulps of this one).
+__device__ __forceinline__ double rcp1(double q) {
+  const double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
+// Number of eigenvalues of the tridiagonal below x (Sturm count: negative
+// pivots of the LDL^T factorisation of T - x I), for two points at once.
+// ae[i] = (alpha_i, off_{i-1}^2), off_{-1} = 0. A pivot that is zero (or
+// nearly) is replaced by a tiny negative one, which keeps the count exact for
+// x on an eigenvalue of a leading block.
+__device__ __forceinline__ void sturm_below2(const double2* ae, int n, double x1, double x2,
+                                             int& c1, int& c2) {
   constexpr double PIV = 1e-290;
-  double q = alpha[0] - x;
-  if (fabs(q) < PIV) q = -PIV;
-  int c = q < 0.0;
-  for (int i = 1; i < n; ++i) {
-    q = (alpha[i] - x) - off[i - 1] * off[i - 1] / q;
-    if (fabs(q) < PIV) q = -PIV;
-    c += q < 0.0;
+  double q1 = 1.0, q2 = 1.0;   // with off_{-1}^2 = 0 the first step is alpha_0 - x
+  int n1 = 0, n2 = 0;
+  for (int i = 0; i < n; ++i) {
+    const double2 v = ae[i];
+    q1 = fma(-v.y, rcp1(q1), v.x - x1);
+    q2 = fma(-v.y, rcp1(q2), v.x - x2);
+    if (fabs(q1) < PIV) q1 = -PIV;
+    if (fabs(q2) < PIV) q2 = -PIV;
+    n1 += q1 < 0.0;
+    n2 += q2 < 0.0;
   }
-  return c;
+  c1 = n1;
+  c2 = n2;
+}
+
+__device__ __forceinline__ int sturm_below(const double2* ae, int n, double x) {
+  int c1, c2;
+  sturm_below2(ae, n, x, x, c1, c2);
+  return c1;
 }
 
 // Inverse iteration for the eigenvector of the tridiagonal (alpha, off)
@@ -109,6 +170,14 @@ __device__ void tri_inverse_iteration(const double* alpha, const double* off, in
   }
 }
 
+// Workgroup b runs on XCD b mod 8; give each XCD a contiguous run of cells
+// (a bijection of [0, total)), so the cells that share the cache lines of the
+// structure-of-arrays sums are read through one L2 at about the same time.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t total) {
+  const int64_t q = total >> 3, rem = total & 7, x = b & 7;
+  return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
 __device__ __forceinline__ int find_item_t(const int64_t* cell0, int nitem, int64_t c) {
   int lo = 0, hi = nitem - 1;
   while (lo < hi) {
@@ -118,27 +187,24 @@ __device__ __forceinline__ int find_item_t(const int64_t* cell0, int nitem, int6
   return lo;
 }
 
+// vcap: doubles of dynamic LDS for the reflectors ((n - 1) 8 NL are needed
+// when v1 is requested; 0 in launches that never ask for v1).
+template <int NL>
 __global__ __launch_bounds__(64) void eig_tri_kernel(EigArgs g, const EigArgs* items,
-                                                     const int64_t* cell0, int nitem) {
-  extern __shared__ __attribute__((aligned(16))) double tsm[];
-  int64_t cell = blockIdx.x;
+                                                     const int64_t* cell0, int nitem, int vcap) {
+  constexpr int NN = 8 * NL;
+  __shared__ double X[NN], P[NN], alpha[NN], offd[NN], tau[NN], dinv[NN], z[NN];
+  __shared__ double2 ae[NN];
+  __shared__ int32_t S[NN], SP[NN * (NN + 1) / 2];
+  extern __shared__ __attribute__((aligned(16))) double vst[];
+  int64_t cell = xcd_order(blockIdx.x, gridDim.x);
   if (items) {
     const int i = find_item_t(cell0, nitem, cell);
     g = items[i];
     cell -= cell0[i];
   }
   const int n = g.nbeam;
-  const int ld = TriLds::ld(n);
-  double* A = tsm;
-  double* v = A + (size_t)n * ld;
-  double* w = v + n;
-  double* dinv = w + n;
-  double* alpha = dinv + n;
-  double* off = alpha + n;
-  double* tau = off + n;
-  double* z = tau + n;
-  int32_t* S = (int32_t*)(z + n + 64);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, r = lane >> 3, c = lane & 7;
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
   const int64_t cnt = g.count[cell / g.nchan];
   if (cnt < 2 || cnt > RFI_MAX_COUNT) {
@@ -152,116 +218,178 @@ __global__ __launch_bounds__(64) void eig_tri_kernel(EigArgs g, const EigArgs* i
     }
     return;
   }
+  const bool want_v1 = g.v1 && (int64_t)(n - 1) * NN <= vcap;
 
-  // correlation matrix in FP64 (full, both triangles) and ||C||_F^2
+  // correlation matrix in FP64 and ||C||_F^2 (the cell's sums first go to
+  // LDS, one pair per lane)
+  const int np = n * (n + 1) / 2;
+  for (int q = lane; q < np; q += 64) SP[q] = g.sum_xy[(int64_t)q * ncell + cell];
+  for (int a = lane; a < n; a += 64) S[a] = g.sum_x[a * ncell + cell];
+  __syncthreads();
   int dead = 0;
   for (int a = lane; a < n; a += 64) {
-    S[a] = g.sum_x[a * ncell + cell];
-    const int64_t Saa = g.sum_xy[pidx(a, a, n) * ncell + cell];
-    const int64_t Naa = cnt * Saa - (int64_t)S[a] * S[a];
+    const int64_t Naa = cnt * (int64_t)SP[pidx(a, a, n)] - (int64_t)S[a] * S[a];
     dinv[a] = Naa > 0 ? 1.0 / sqrt((double)Naa) : 0.0;
     dead |= Naa <= 0;
   }
   const int degenerate = __syncthreads_or(dead);
+  double A[NL][NL];
   double offsq = 0.0;
-  for (int e = lane; e < n * n; e += 64) {
-    const int i = e / n, j = e - (e / n) * n;
-    double r = 1.0;
-    if (i != j) {
-      const int a = i < j ? i : j, b = i < j ? j : i;
-      const int64_t Sab = g.sum_xy[pidx(a, b, n) * ncell + cell];
-      const int64_t Nab = cnt * Sab - (int64_t)S[a] * S[b];
-      r = (double)Nab * dinv[a] * dinv[b];
-      if (i < j) offsq += r * r;
-    }
-    A[i * ld + j] = r;
-  }
+  static_for<0, NL>([&](auto II) {
+    constexpr int ii = RFI_CI(II);
+    static_for<0, NL>([&](auto JJ) {
+      constexpr int jj = RFI_CI(JJ);
+      const int gi = r + 8 * ii, gj = c + 8 * jj;
+      double val = 0.0;
+      if (gi < n && gj < n) {
+        if (gi == gj) {
+          val = 1.0;
+        } else {
+          const int a = gi < gj ? gi : gj, b = gi < gj ? gj : gi;
+          const int64_t Nab = cnt * (int64_t)SP[pidx(a, b, n)] - (int64_t)S[a] * S[b];
+          val = (double)Nab * dinv[a] * dinv[b];
+          if (gi < gj) offsq += val * val;
+        }
+      }
+      A[ii][jj] = val;
+    });
+  });
   const double frob2 = (double)n + 2.0 * wave_sum(offsq);
+
+  // Householder reduction: steps k = 0 .. n - 2 (the last one only records
+  // the final sub-diagonal entry)
+  static_for<0, NL>([&](auto IKc) {
+    constexpr int IK = RFI_CI(IKc);
+    const int nk = min(8, n - 1 - 8 * IK);   // steps of this block (may be <= 0)
+#pragma unroll 1
+    for (int rk = 0; rk < nk; ++rk) {
+      const int k = 8 * IK + rk;
+      __syncthreads();
+      if (r == rk) {
+        static_for<IK, NL>([&](auto JJ) { X[c + 8 * RFI_CI(JJ)] = A[IK][RFI_CI(JJ)]; });
+      }
+      __syncthreads();
+      const double x0 = X[k + 1];
+      double s2 = 0.0;
+      double vc[NL];
+      static_for<IK, NL>([&](auto JJ) {
+        constexpr int jj = RFI_CI(JJ);
+        const double x = X[c + 8 * jj];
+        vc[jj] = x;
+        s2 += c + 8 * jj > k + 1 ? x * x : 0.0;
+      });
+      s2 = sum8(s2);
+      // reflector of (x0, x_{k+2}, ...) onto (mu, 0, ...): v0 = x0 - mu (formed
+      // without cancellation), beta = 2 v0^2 / (s2 + v0^2) = -v0 / mu
+      double beta = 0.0, sub = x0, iv0 = 0.0;
+      if (s2 > 0.0) {
+        const double mu = sqrt(fma(x0, x0, s2));
+        const double v0 = x0 <= 0.0 ? x0 - mu : -s2 * rcp1(x0 + mu);
+        beta = -v0 * rcp1(mu);
+        iv0 = rcp1(v0);
+        sub = mu;
+      }
+      if (lane == 0) {
+        offd[k] = sub;
+        tau[k] = beta;
+      }
+      {
+        // with beta = 0 (nothing below the sub-diagonal) v = e_{k+1} and w = 0:
+        // the update below leaves A unchanged, so it runs without a branch
+        double vr[NL], pr[NL];
+        static_for<IK, NL>([&](auto II) {
+          constexpr int ii = RFI_CI(II);
+          const int gi = r + 8 * ii;
+          vr[ii] = gi > k + 1 ? X[gi] * iv0 : (gi == k + 1 ? 1.0 : 0.0);
+        });
+        static_for<IK, NL>([&](auto JJ) {
+          constexpr int jj = RFI_CI(JJ);
+          const int gj = c + 8 * jj;
+          vc[jj] = gj > k + 1 ? vc[jj] * iv0 : (gj == k + 1 ? 1.0 : 0.0);
+        });
+        if (want_v1 && r == 0) {
+          static_for<IK, NL>([&](auto JJ) {
+            const int gj = c + 8 * RFI_CI(JJ);
+            if (gj < n) vst[k * NN + gj] = vc[RFI_CI(JJ)];
+          });
+        }
+        // p = A v (unscaled) for this lane's rows
+        static_for<IK, NL>([&](auto II) {
+          constexpr int ii = RFI_CI(II);
+          double acc = 0.0;
+          static_for<IK, NL>([&](auto JJ) { acc = fma(A[ii][RFI_CI(JJ)], vc[RFI_CI(JJ)], acc); });
+          pr[ii] = sum8(acc);
+        });
+        if (c == 0) {
+          static_for<IK, NL>([&](auto II) { P[r + 8 * RFI_CI(II)] = pr[RFI_CI(II)]; });
+        }
+        __syncthreads();
+        double pv = 0.0;
+        static_for<IK, NL>([&](auto JJ) {
+          pv = fma(P[c + 8 * RFI_CI(JJ)], vc[RFI_CI(JJ)], pv);
+        });
+        pv = sum8(pv);
+        const double K = 0.5 * beta * beta * pv;
+        // w = beta p - K v; A -= v w^T + w v^T
+        static_for<IK, NL>([&](auto II) {
+          constexpr int ii = RFI_CI(II);
+          pr[ii] = beta * pr[ii] - K * vr[ii];
+        });
+        static_for<IK, NL>([&](auto JJ) {
+          constexpr int jj = RFI_CI(JJ);
+          const double wc = beta * P[c + 8 * jj] - K * vc[jj];
+          static_for<IK, NL>([&](auto II) {
+            constexpr int ii = RFI_CI(II);
+            A[ii][jj] = fma(-vr[ii], wc, fma(-pr[ii], vc[jj], A[ii][jj]));
+          });
+        });
+      }
+    }
+    // diagonal entries of block IK are final
+    if (r == c && r + 8 * IK < n) alpha[r + 8 * IK] = A[IK][IK];
+  });
   __syncthreads();
 
-  // Householder reduction to tridiagonal form
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;                 // length of the column below the diagonal
-    const int r0 = k + 1;
-    double s2 = 0.0;
-    for (int i = lane + 1; i < m; i += 64) {
-      const double x = A[(r0 + i) * ld + k];
-      s2 += x * x;
-    }
-    s2 = wave_sum(s2);
-    const double x0 = A[r0 * ld + k];
-    double beta = 0.0, sub = x0, v0 = 1.0;
-    if (s2 > 0.0) {
-      const double mu = sqrt(x0 * x0 + s2);
-      v0 = x0 <= 0.0 ? x0 - mu : -s2 / (x0 + mu);
-      beta = 2.0 * v0 * v0 / (s2 + v0 * v0);
-      sub = mu;
-    }
-    for (int i = lane; i < m; i += 64) v[i] = i == 0 ? 1.0 : A[(r0 + i) * ld + k] / v0;
-    if (lane == 0) {
-      off[k] = sub;
-      tau[k] = beta;
-    }
-    __syncthreads();
-    if (beta != 0.0) {
-      // p = beta A22 v (rows over lanes); K = beta p.v / 2; w = p - K v
-      double pv = 0.0;
-      for (int i = lane; i < m; i += 64) {
-        const double* row = A + (r0 + i) * ld + r0;
-        double p = 0.0;
-        for (int j = 0; j < m; ++j) p += row[j] * v[j];
-        p *= beta;
-        w[i] = p;
-        pv += p * v[i];
-      }
-      const double K = 0.5 * beta * wave_sum(pv);
-      __syncthreads();
-      for (int i = lane; i < m; i += 64) w[i] -= K * v[i];
-      __syncthreads();
-      // A22 -= v w^T + w v^T
-      for (int i = lane; i < m; i += 64) {
-        double* row = A + (r0 + i) * ld + r0;
-        const double vi = v[i], wi = w[i];
-        for (int j = 0; j < m; ++j) row[j] -= vi * w[j] + wi * v[j];
-      }
-    }
-    // keep the reflector (v_1.. below the sub-diagonal) for the eigenvector
-    for (int i = lane; i < m; i += 64) A[(r0 + i) * ld + k] = v[i];
-    __syncthreads();
-  }
-  for (int i = lane; i < n; i += 64) alpha[i] = A[i * ld + i];
-  if (lane == 0 && n >= 2) off[n - 2] = A[(n - 1) * ld + (n - 2)];
-  __syncthreads();
-
-  // Gershgorin bracket of the spectrum
-  double glo = 1e300, ghi = -1e300;
+  for (int i = lane; i < n; i += 64) ae[i] = make_double2(alpha[i], i ? offd[i - 1] * offd[i - 1] : 0.0);
+  // Gershgorin bracket of the spectrum; lambda_1 is at least the largest
+  // eigenvalue of every 2 x 2 principal block (Cauchy interlacing)
+  double glo = 1e300, ghi = -1e300, lb = -1e300;
   for (int i = lane; i < n; i += 64) {
-    const double rad = (i > 0 ? fabs(off[i - 1]) : 0.0) + (i + 1 < n ? fabs(off[i]) : 0.0);
+    const double rad = (i > 0 ? fabs(offd[i - 1]) : 0.0) + (i + 1 < n ? fabs(offd[i]) : 0.0);
     glo = fmin(glo, alpha[i] - rad);
     ghi = fmax(ghi, alpha[i] + rad);
+    double m = alpha[i];
+    if (i + 1 < n) {
+      const double h = 0.5 * (alpha[i] - alpha[i + 1]);
+      m = 0.5 * (alpha[i] + alpha[i + 1]) + sqrt(h * h + offd[i] * offd[i]);
+    }
+    lb = fmax(lb, m);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     glo = fmin(glo, __shfl_xor(glo, o));
     ghi = fmax(ghi, __shfl_xor(ghi, o));
+    lb = fmax(lb, __shfl_xor(lb, o));
   }
   const double span = fmax(ghi - glo, 1e-300);
   glo -= 1e-12 * span;
   ghi += 1e-12 * span;
+  __syncthreads();
 
   // lambda_1 = the largest eigenvalue: multisection. The bracket [lo, hi]
   // always holds exactly one crossing of count n-1 -> n (count(lo) <= n-1,
-  // count(hi) = n); lane l tests lo + (l + 1) (hi - lo) / 65.
-  double lo = glo, hi = ghi;
+  // count(hi) = n); lane l tests the points l + 1 and l + 65 of the 129
+  // equal parts of the bracket.
+  double lo = fmax(glo, lb - 1e-12 * span), hi = ghi;
   for (int it = 0; it < 12 && hi - lo > 4e-16 * fmax(fabs(hi), 1.0); ++it) {
-    const double h = (hi - lo) / 65.0;
-    const double x = lo + (lane + 1) * h;
-    const int c = sturm_below(alpha, off, n, x);
-    // the first lane whose point has all n eigenvalues below it
-    const unsigned long long ball = __ballot(c >= n);
-    const int first = ball ? __builtin_ctzll(ball) : 64;
-    const double nlo = first == 0 ? lo : lo + first * h;
-    const double nhi = first == 64 ? hi : lo + (first + 1) * h;
+    const double h = (hi - lo) * (1.0 / 129.0);
+    int c1, c2;
+    sturm_below2(ae, n, lo + (lane + 1) * h, lo + (lane + 65) * h, c1, c2);
+    // the first point with all n eigenvalues below it
+    const unsigned long long b1 = __ballot(c1 >= n), b2 = __ballot(c2 >= n);
+    const int first = b1 ? __builtin_ctzll(b1) + 1 : (b2 ? __builtin_ctzll(b2) + 65 : 129);
+    const double nlo = lo + (first - 1) * h;
+    const double nhi = first == 129 ? hi : lo + first * h;
     lo = nlo;
     hi = nhi;
   }
@@ -280,7 +408,7 @@ __global__ __launch_bounds__(64) void eig_tri_kernel(EigArgs g, const EigArgs* i
       double a = glo, b = ghi;
       for (int it = 0; it < 64 && b - a > 2e-16 * fmax(fabs(b), 1.0); ++it) {
         const double mid = 0.5 * (a + b);
-        if (sturm_below(alpha, off, n, mid) > i) b = mid; else a = mid;
+        if (sturm_below(ae, n, mid) > i) b = mid; else a = mid;
       }
       z[i] = 0.5 * (a + b);
     }
@@ -298,22 +426,28 @@ __global__ __launch_bounds__(64) void eig_tri_kernel(EigArgs g, const EigArgs* i
   }
 
   if (g.v1) {
+    if (!want_v1) {
+      // no room for the reflectors in this launch (the launchers below always
+      // give it when v1 is asked for): NaN rather than a wrong vector
+      for (int i = lane; i < n; i += 64) g.v1[i * g.out_stride + cell] = __builtin_nanf("");
+      return;
+    }
     // inverse iteration on T - sigma I, sigma just above lambda_1 (lane 0):
     // Gaussian elimination with partial pivoting of the tridiagonal into
     // U = (ud, ue, uf) (diagonal and two upper diagonals), then back
     // substitution; three iterations from the all-ones vector
-    if (lane == 0) tri_inverse_iteration(alpha, off, n, lam1 + 1e-13 * fmax(fabs(lam1), 1.0),
-                                         v, w, dinv, z);
+    if (lane == 0) tri_inverse_iteration(alpha, offd, n, lam1 + 1e-13 * fmax(fabs(lam1), 1.0),
+                                         X, P, dinv, z);
     __syncthreads();
     // back-transform: v1 = H_0 H_1 ... H_{n-3} z, applied from the last
     for (int k = n - 3; k >= 0; --k) {
-      const int m = n - k - 1, r0 = k + 1;
       const double beta = tau[k];
       if (beta == 0.0) continue;
+      const double* vk = vst + (size_t)k * NN;
       double dot = 0.0;
-      for (int i = lane; i < m; i += 64) dot += A[(r0 + i) * ld + k] * z[r0 + i];
+      for (int i = k + 1 + lane; i < n; i += 64) dot += vk[i] * z[i];
       dot = beta * wave_sum(dot);
-      for (int i = lane; i < m; i += 64) z[r0 + i] -= dot * A[(r0 + i) * ld + k];
+      for (int i = k + 1 + lane; i < n; i += 64) z[i] -= dot * vk[i];
       __syncthreads();
     }
     // sign: sum_b v_b >= 0, else first non-zero component positive
@@ -328,31 +462,57 @@ __global__ __launch_bounds__(64) void eig_tri_kernel(EigArgs g, const EigArgs* i
   }
 }
 
-}  // namespace
-
-size_t eig_tri_lds(int nbeam) { return TriLds::bytes(nbeam); }
-
-hipError_t launch_eig_tri(const EigArgs& a, hipStream_t s) {
-  const int64_t ncell = (int64_t)a.nsub * a.nchan;
-  const size_t shm = TriLds::bytes(a.nbeam);
-  hipError_t e = hipFuncSetAttribute((const void*)eig_tri_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(eig_tri_kernel, dim3((unsigned)ncell), dim3(64), shm, s, a,
-                     (const EigArgs*)nullptr, (const int64_t*)nullptr, 0);
+template <int NL>
+hipError_t launch_nl(int nbeam, const EigArgs& a, const EigArgs* items, const int64_t* cell0,
+                     int nitem, int64_t total, bool v1, hipStream_t s) {
+  const int vcap = v1 ? (nbeam - 1) * 8 * NL : 0;
+  const size_t shm = (size_t)vcap * sizeof(double);
+  if (shm > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)eig_tri_kernel<NL>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(eig_tri_kernel<NL>, dim3((unsigned)total), dim3(64), shm, s, a, items,
+                     cell0, nitem, vcap);
   return hipGetLastError();
 }
 
-hipError_t launch_eig_tri_batch(int max_nbeam, const EigArgs* items, const int64_t* cell0,
-                                int nitem, int64_t total, hipStream_t s) {
-  const size_t shm = TriLds::bytes(max_nbeam);
-  hipError_t e = hipFuncSetAttribute((const void*)eig_tri_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (e != hipSuccess) return e;
+hipError_t launch_cls(int cls, int nbeam, const EigArgs& a, const EigArgs* items,
+                      const int64_t* cell0, int nitem, int64_t total, bool v1, hipStream_t s) {
+  switch (cls) {
+    case 3: return launch_nl<3>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 5: return launch_nl<5>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 8: return launch_nl<8>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 9: return launch_nl<9>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 10: return launch_nl<10>(nbeam, a, items, cell0, nitem, total, v1, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int eig_tri_class(int n) {
+  if (n < 2) return 0;
+  if (n <= 24) return 3;
+  if (n <= 40) return 5;
+  if (n <= 64) return 8;
+  if (n <= 72) return 9;
+  if (n <= 80) return 10;
+  return 0;
+}
+
+hipError_t launch_eig_tri(const EigArgs& a, hipStream_t s) {
+  const int64_t ncell = (int64_t)a.nsub * a.nchan;
+  if (ncell == 0) return hipSuccess;
+  return launch_cls(eig_tri_class(a.nbeam), a.nbeam, a, nullptr, nullptr, 0, ncell,
+                    a.v1 != nullptr, s);
+}
+
+hipError_t launch_eig_tri_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
+                                int64_t total, hipStream_t s) {
+  if (total == 0) return hipSuccess;
   EigArgs none{};
-  hipLaunchKernelGGL(eig_tri_kernel, dim3((unsigned)total), dim3(64), shm, s, none, items, cell0,
-                     nitem);
-  return hipGetLastError();
+  return launch_cls(cls, 0, none, items, cell0, nitem, total, false, s);
 }
 
 }  // namespace rfi

@@ -73,8 +73,12 @@ hipError_t launch_eig_lane_batch(int cls, const EigArgs* items, const int64_t* c
                                  int64_t total, hipStream_t s);
 hipError_t launch_eig_wave_batch(int precision, int max_nbeam, const EigArgs* items,
                                  const int64_t* cell0, int nitem, int64_t total, hipStream_t s);
-hipError_t launch_eig_tri_batch(int max_nbeam, const EigArgs* items, const int64_t* cell0,
-                                int nitem, int64_t total, hipStream_t s);
+// The per-wave tridiagonal solver: template class of a beam count (local
+// block size of its 8 x 8 lane grid; 0 = none) and its batched launch over
+// items of one class.
+int eig_tri_class(int n);
+hipError_t launch_eig_tri_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
+                                int64_t total, hipStream_t s);
 
 size_t flag_workspace_size(int nsub, int nchan);
 // One block of a batched clip (device descriptor); one workgroup per block.
