@@ -213,10 +213,33 @@ def batch_bench(dev, nblocks=24, seed=11):
     t_bat = timed(lambda: bt.run(bws))
     t_gr = timed(lambda: g.launch())
     g.close()
+    # autotuner: per shape class, on the block with the most cells of the class
+    sample = {}
+    for it in items:
+        nb = it["blk"].nbeam
+        c = (nb + 16) // 16
+        if c not in sample or it["nsub"] * it["blk"].nchan > sample[c]["nsub"] * sample[c]["blk"].nchan:
+            sample[c] = it
+    st = rfi.Batch(list(sample.values()))
+    sws = torch.empty(st.workspace_size(), dtype=torch.uint8, device=dev)
+    t0 = time.perf_counter()
+    table = st.tune(sws)
+    tune_s = time.perf_counter() - t0
+    del sws
+    tb = rfi.Batch(items, tune=table)
+    tws = bws if tb.workspace_size() <= bws.numel() else torch.empty(
+        tb.workspace_size(), dtype=torch.uint8, device=dev)
+    tg = tb.graph(tws)
+    t_tg = timed(lambda: tg.launch())
+    tg.close()
     out = {"blocks": len(items), "bytes_gb": round(nbytes / 1e9, 2),
            "bytes_by_nbeam_gb": {str(k): round(v / 1e9, 2) for k, v in sorted(per_class.items())},
            "separate_ms": round(t_sep, 3), "batch_ms": round(t_bat, 3), "graph_ms": round(t_gr, 3),
-           "separate_gbs": round(nbytes / t_sep / 1e6, 1), "graph_gbs": round(nbytes / t_gr / 1e6, 1)}
+           "tuned_graph_ms": round(t_tg, 3),
+           "separate_gbs": round(nbytes / t_sep / 1e6, 1), "graph_gbs": round(nbytes / t_gr / 1e6, 1),
+           "tuned_graph_gbs": round(nbytes / t_tg / 1e6, 1), "tune_s": round(tune_s, 2),
+           "tune_table": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in e.items()}
+                          for e in rfi.tune_table_dict(table)]}
     del pools
     torch.cuda.empty_cache()
     return out
@@ -326,6 +349,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving loop and print its JSON")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the uneven-batch comparison and print its JSON")
     ap.add_argument("--quick", action="store_true",
                     help="time the steps only (no latency, stage split or CPU baseline)")
     ap.add_argument("--profile-run", action="store_true",
@@ -333,15 +358,17 @@ def main():
                          "step and one whole-block step, then the JSON line of those")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(cells are independent; sharding by channel range is described in DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (cells are "
+              "independent; several GPUs would each take a channel range)", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2512_16278_amd import rfi, synth
 
     dev = torch.device("cuda:0")
+    if args.batch_only:
+        print(json.dumps({"batch": batch_bench(dev)}), flush=True)
+        return
     if args.serve_only:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         print(json.dumps({"serving": serve_bench(dev, rates, args.serve_blocks)}), flush=True)
@@ -493,7 +520,7 @@ def main():
                 "ms": round(float(ms_ccm), 4)}
     else:
         # algorithmic FP32 flops of the Jacobi: per sweep n(n-1)/2 rotations of
-        # 6(n-2) + 12 flops; sweep count taken as 6
+        # 6(n-2) + 12 flops; 6 sweeps (the typical count on noise-dominated cells)
         flop = ncell * 6 * (nb * (nb - 1) / 2) * (6 * (nb - 2) + 12)
         ach = flop / (ms_eig / 1e3)
         roof = {"kernel": "eig_lane_jacobi", "bound": "alu", "achieved": round(ach / 1e12, 2),

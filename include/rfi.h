@@ -103,8 +103,8 @@ rfi_status rfi_ccm_accumulate(const rfi_block* blk /* host */, int64_t t0, int32
  *                  wavefront in LDS, FP32 or FP64, any nbeam;
  *  RFI_EIG_TRIDIAG Householder reduction to tridiagonal form and Sturm
  *                  bisection (Golub & Van Loan Sec. 8.3-8.4), FP64, one cell per
- *                  wavefront in LDS, any nbeam: about (4/3) n^3 flops per cell
- *                  instead of 6 n^3 per Jacobi sweep.
+ *                  wavefront with the matrix in registers, any nbeam: about
+ *                  (4/3) n^3 flops per cell instead of 6 n^3 per Jacobi sweep.
  *  RFI_EIG_AUTO    LANE for FP32 and nbeam <= 20, TRIDIAG for FP32 and more
  *                  beams, WAVE for FP64 (FP64 Jacobi). */
 enum { RFI_EIG_AUTO = 0, RFI_EIG_LANE = 1, RFI_EIG_WAVE = 2, RFI_EIG_TRIDIAG = 3 };
@@ -271,12 +271,46 @@ typedef struct {
   rfi_flag_stats* out;           /* device or NULL */
 } rfi_batch_item;
 
+/* Launch configuration of one shape class of the batched path. A class is
+ * the range of beam counts [nbeam_lo, nbeam_hi] that one sums-engine tile
+ * family serves (2-15, 16-31, 32-47, 48-63, 64-79); 0 in a choice field
+ * means the library default:
+ *  ccm_tile        sums tile variant, 0 .. rfi_ccm_tile_variants(nbeam) - 1
+ *                  (16-31 beams: 0 = 64 channels on 8 waves, 1 = 64 channels
+ *                  on 16 waves, 2 = 32 channels on 8 waves; others: 0 only);
+ *  ccm_stages      cap of the global-to-LDS load ring depth, 2..4;
+ *  ccm_group_bytes contiguous row bytes of the tiles one XCD takes in turn
+ *                  (16 .. 16384; default 1024);
+ *  eig_solver      RFI_EIG_* for the class (AUTO: the default rule; LANE
+ *                  needs FP32 and nbeam <= 20);
+ *  eig_wg          cells per workgroup of the per-lane solver: 64, 128, 256.
+ * ms_default / ms_tuned: class time (sums + eigen launches, ms) with the
+ * defaults and with the entry's choices, as measured by rfi_tune_batch. */
+typedef struct {
+  int32_t nbeam_lo, nbeam_hi;
+  int32_t ccm_tile, ccm_stages, ccm_group_bytes;
+  int32_t eig_solver, eig_wg, pad;
+  double ms_default, ms_tuned;
+} rfi_tune_entry;
+
+#define RFI_TUNE_MAX 8
+typedef struct {
+  int32_t n;                     /* entries in use */
+  int32_t pad;
+  rfi_tune_entry e[RFI_TUNE_MAX];
+} rfi_tune_table;
+
+/* Tile variants of the sums engine for a beam count (0 if unsupported). */
+int32_t rfi_ccm_tile_variants(int32_t nbeam);
+
 typedef struct {
   int32_t eig_precision;         /* 32 (0 = 32) or 64 */
   int32_t max_sweeps;            /* 0 = 12 */
   int32_t max_iter;              /* clip fits, 0 = 50 */
   int32_t pad;
   double kappa;                  /* clip multiple, >= 0 */
+  const rfi_tune_table* tune;    /* host, nullable: per-class launch choices
+                                    (read when the call plans the batch) */
 } rfi_batch_params;
 
 /* Workspace bytes for the batch (0 on invalid arguments; rfi_last_error). */
@@ -287,6 +321,21 @@ size_t rfi_batch_workspace_size(int32_t nitem, const rfi_batch_item* items /* ho
 rfi_status rfi_process_batch(int32_t nitem, const rfi_batch_item* items /* host */,
                              const rfi_batch_params* p /* host */, void* workspace,
                              rfi_stream_t stream);
+
+/* Autotuner (batched path): for every shape class of the batch, times the
+ * class's sums launch for each tile variant and ring depth, then for each
+ * XCD group size, and its eigen launch for each applicable solver (and
+ * per-lane workgroup size), on the caller's blocks, and writes the fastest
+ * choices to *table (host), one entry per class, ordered by beam count.
+ * Every candidate computes the same sums (exact integers) and, per solver,
+ * the same statistic bits, so only time differs. Synchronous: it runs the
+ * candidates on stream and waits for them (a warm-up and three timed runs
+ * each). workspace as for rfi_process_batch (rfi_batch_workspace_size of the
+ * same items); the items' stat/status buffers are written as scratch, the
+ * masks are not. p->tune is ignored. */
+rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items /* host */,
+                          const rfi_batch_params* p /* host */, void* workspace,
+                          rfi_tune_table* table /* host */, rfi_stream_t stream);
 
 typedef struct rfi_batch_graph rfi_batch_graph;
 rfi_status rfi_batch_graph_create(int32_t nitem, const rfi_batch_item* items /* host */,

@@ -134,6 +134,10 @@ rfi_status rfi_ccm_accumulate(const rfi_block* blk, int64_t t0, int32_t L, int32
   return check_hip(e, "rfi_ccm_accumulate launch");
 }
 
+int32_t rfi_ccm_tile_variants(int32_t nbeam) {
+  return nbeam < 2 || nbeam > RFI_MAX_BEAMS ? 0 : rfi::ccm_tile_variants(nbeam);
+}
+
 rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan, const int32_t* sum_x,
                            const int32_t* sum_xy, const int32_t* count, const rfi_eig_params* p,
                            float* eigvals, double* stat, float* v1, uint8_t* status,

@@ -1,5 +1,6 @@
 // Batched uneven blocks: the whole path for many blocks with one launch per
-// kernel class (rfi_process_batch) and its capture into a HIP graph.
+// kernel class (rfi_process_batch), its capture into a HIP graph, and the
+// autotuner of the per-class launch choices (rfi_tune_batch).
 //
 // Workspace layout: one descriptor area, uploaded by one host-to-device copy,
 // then the sums of every block (sum_x, sum_xy, count; 256-byte aligned):
@@ -13,6 +14,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <tuple>
 #include <memory>
@@ -33,15 +35,35 @@ struct ItemPlan {
   int nbeam, nchan;
   int64_t ncell;
   CcmClass cc;
+  CcmTune ct;              // sums-engine choices of the item's shape class
   int solver, precision;   // eigen class (solver, precision)
   int lane_cls;            // template class of the per-lane or per-wave tridiagonal solver
+  int wg;                  // per-lane solver workgroup
   size_t sums_off;         // byte offset of the item's sums in the workspace
 };
 
 struct EigClass {
-  int lane_cls, solver, precision, max_nbeam;
+  int lane_cls, solver, precision, wg, max_nbeam;
   std::vector<int> items;  // indices into plans
 };
+
+struct CcmLaunchClass {
+  int nbeam;               // any member's beam count
+  CcmTune ct;
+  std::vector<int> items;  // indices into plans
+};
+
+// Shape class of a beam count: the sums engine's 16-row block count.
+inline int shape_class(int nbeam) { return (nbeam + 1 + 15) / 16; }
+inline int class_lo(int sc) { return std::max(2, 16 * (sc - 1)); }
+inline int class_hi(int sc) { return 16 * sc - 1; }
+
+const rfi_tune_entry* find_tune(const rfi_tune_table* t, int nbeam) {
+  if (!t) return nullptr;
+  for (int i = 0; i < std::min<int>(t->n, RFI_TUNE_MAX); ++i)
+    if (t->e[i].nbeam_lo <= nbeam && nbeam <= t->e[i].nbeam_hi) return &t->e[i];
+  return nullptr;
+}
 
 struct BatchPlan {
   std::vector<ItemPlan> plans;
@@ -51,7 +73,7 @@ struct BatchPlan {
   // descriptor area
   size_t tab_off = 0, ccm_off = 0, eig_off = 0, cell0_off = 0, flag_off = 0, desc_bytes = 0;
   size_t ws_bytes = 0;
-  std::vector<std::pair<int, std::vector<int>>> ccm_classes;  // (nbeam of class, plans)
+  std::vector<CcmLaunchClass> ccm_classes;
   std::vector<EigClass> eig_classes;
   std::vector<char> host;  // descriptor bytes (device addresses resolved for ws)
 };
@@ -60,8 +82,10 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
                       BatchPlan* bpn, const char* who) {
   if (nitem < 0) return fail(RFI_E_INVALID, "%s: nitem < 0", who);
   if (nitem > 0 && !items) return fail(RFI_E_INVALID, "%s: items is NULL", who);
-  rfi_batch_params prm{32, 12, 50, 0, 3.0};
+  rfi_batch_params prm{32, 12, 50, 0, 3.0, nullptr};
   if (p) prm = *p;
+  if (prm.tune && (prm.tune->n < 0 || prm.tune->n > RFI_TUNE_MAX))
+    return fail(RFI_E_INVALID, "%s: tune table with %d entries", who, prm.tune->n);
   if (prm.eig_precision == 0) prm.eig_precision = 32;
   if (prm.max_sweeps == 0) prm.max_sweeps = 12;
   if (prm.max_iter == 0) prm.max_iter = 50;
@@ -80,36 +104,48 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
     if (it.nsub == 0) continue;
     if (!it.stat || !it.status || !it.mask)
       return fail(RFI_E_INVALID, "%s: item %d has a NULL output", who, i);
-    rfi_eig_params ep{prm.eig_precision, prm.max_sweeps, 1, RFI_EIG_AUTO};
+    const rfi_tune_entry* te = find_tune(prm.tune, it.blk->nbeam);
+    rfi_eig_params ep{prm.eig_precision, prm.max_sweeps, 1, te ? te->eig_solver : RFI_EIG_AUTO};
     rfi_eig_params res;
     if ((st = resolve_eig(it.blk->nbeam, &ep, &res, who)) != RFI_OK) return st;
     bpn->eig = res;
     ip.nbeam = it.blk->nbeam;
     ip.nchan = it.blk->nchan;
     ip.ncell = (int64_t)it.nsub * it.blk->nchan;
-    if (ccm_class(ip.nbeam, &ip.cc) != hipSuccess)
+    ip.ct = CcmTune{te ? te->ccm_tile : 0, te ? te->ccm_stages : 0, te ? te->ccm_group_bytes : 0};
+    if (te && (te->ccm_stages < 0 || te->ccm_stages > 4 || te->ccm_group_bytes < 0 ||
+               te->ccm_group_bytes > 16384 || te->ccm_tile < 0 ||
+               te->ccm_tile >= ccm_tile_variants(ip.nbeam)))
+      return fail(RFI_E_INVALID, "%s: item %d: tune entry out of range", who, i);
+    if (ccm_class(ip.nbeam, &ip.cc, &ip.ct) != hipSuccess)
       return fail(RFI_E_INVALID, "%s: item %d: no sums instance for %d beams", who, i, ip.nbeam);
     ip.solver = res.solver;
     ip.precision = res.precision;
     ip.lane_cls = res.solver == RFI_EIG_LANE      ? eig_lane_class(ip.nbeam)
                   : res.solver == RFI_EIG_TRIDIAG ? eig_tri_class(ip.nbeam)
                                                   : 0;
+    ip.wg = te && te->eig_wg ? te->eig_wg : 256;
+    if (ip.wg != 64 && ip.wg != 128 && ip.wg != 256)
+      return fail(RFI_E_INVALID, "%s: item %d: eig_wg %d not 64, 128 or 256", who, i, ip.wg);
     tab_bytes += (size_t)ip.nbeam * sizeof(void*);
     bpn->plans.push_back(ip);
   }
   const int n = (int)bpn->plans.size();
   // classes
-  std::map<int, std::vector<int>> ccm;
-  // (solver template class or 0, solver, precision)
-  std::map<std::tuple<int, int, int>, std::vector<int>> eig;
+  std::map<long long, std::vector<int>> ccm;
+  // (solver template class or 0, solver, precision, workgroup)
+  std::map<std::tuple<int, int, int, int>, std::vector<int>> eig;
   for (int k = 0; k < n; ++k) {
-    ccm[bpn->plans[k].cc.key].push_back(k);
-    eig[{bpn->plans[k].lane_cls, bpn->plans[k].solver, bpn->plans[k].precision}].push_back(k);
+    const ItemPlan& ip = bpn->plans[k];
+    ccm[ip.cc.key].push_back(k);
+    eig[{ip.lane_cls, ip.solver, ip.precision, ip.solver == RFI_EIG_LANE ? ip.wg : 0}].push_back(k);
   }
-  for (auto& kv : ccm) bpn->ccm_classes.push_back({bpn->plans[kv.second[0]].nbeam, kv.second});
+  for (auto& kv : ccm)
+    bpn->ccm_classes.push_back({bpn->plans[kv.second[0]].nbeam, bpn->plans[kv.second[0]].ct,
+                                kv.second});
   for (auto& kv : eig) {
-    EigClass ec{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), 0,
-                kv.second};
+    EigClass ec{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                std::get<3>(kv.first), 0, kv.second};
     for (int k : kv.second) ec.max_nbeam = std::max(ec.max_nbeam, bpn->plans[k].nbeam);
     bpn->eig_classes.push_back(ec);
   }
@@ -160,7 +196,7 @@ void fill_descriptors(const rfi_batch_item* items, BatchPlan* bpn, char* ws) {
   int pos = 0;
   for (auto& cls : bpn->ccm_classes) {
     int wg = 0;
-    for (int k : cls.second) {
+    for (int k : cls.items) {
       const ItemPlan& ip = bpn->plans[k];
       const rfi_batch_item& it = items[ip.idx];
       CcmItem& c = ci[pos++];
@@ -207,33 +243,39 @@ void fill_descriptors(const rfi_batch_item* items, BatchPlan* bpn, char* ws) {
   }
 }
 
-// Enqueue the batch on s; desc is the host copy of the descriptors (pinned
-// for graph capture, where the copy node reads it at every replay).
-hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipStream_t s) {
-  const int n = (int)bpn.plans.size();
-  if (n == 0) return hipSuccess;
-  hipError_t e = hipMemcpyAsync(ws, desc, bpn.desc_bytes, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
+// The batch's launches on s, in three parts; desc is the host copy of the
+// descriptors (pinned for graph capture, where the copy node reads it at
+// every replay).
+hipError_t enqueue_desc(const BatchPlan& bpn, const void* desc, char* ws, hipStream_t s) {
+  return hipMemcpyAsync(ws, desc, bpn.desc_bytes, hipMemcpyHostToDevice, s);
+}
+
+hipError_t enqueue_ccm(const BatchPlan& bpn, const void* desc, char* ws, hipStream_t s) {
   const CcmItem* ci = (const CcmItem*)(ws + bpn.ccm_off);
   const CcmItem* hci = (const CcmItem*)((const char*)desc + bpn.ccm_off);
   int pos = 0;
-  for (auto& cls : bpn.ccm_classes) {
-    const int m = (int)cls.second.size();
+  for (const CcmLaunchClass& cls : bpn.ccm_classes) {
+    const int m = (int)cls.items.size();
     const CcmItem& last = hci[pos + m - 1];
     const int total = last.wg0 + (last.nsub * last.nct + 7) / 8 * 8;
-    if ((e = launch_ccm_batch(cls.first, ci + pos, m, total, s)) != hipSuccess) return e;
+    hipError_t e = launch_ccm_batch(cls.nbeam, &cls.ct, ci + pos, m, total, s);
+    if (e != hipSuccess) return e;
     pos += m;
   }
+  return hipSuccess;
+}
+
+hipError_t enqueue_eig(const BatchPlan& bpn, const void* desc, char* ws, hipStream_t s) {
   const EigArgs* ea = (const EigArgs*)(ws + bpn.eig_off);
   const int64_t* c0 = (const int64_t*)(ws + bpn.cell0_off);
   const int64_t* hc0 = (const int64_t*)((const char*)desc + bpn.cell0_off);
-  pos = 0;
-  int cpos = 0;
+  int pos = 0, cpos = 0;
   for (const EigClass& ec : bpn.eig_classes) {
     const int m = (int)ec.items.size();
     const int64_t total = hc0[cpos + m];
+    hipError_t e;
     if (ec.solver == RFI_EIG_LANE)
-      e = launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s);
+      e = launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s, ec.wg);
     else if (ec.solver == RFI_EIG_TRIDIAG)
       e = launch_eig_tri_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s);
     else
@@ -242,7 +284,51 @@ hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipSt
     pos += m;
     cpos += m + 1;
   }
+  return hipSuccess;
+}
+
+hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipStream_t s) {
+  const int n = (int)bpn.plans.size();
+  if (n == 0) return hipSuccess;
+  hipError_t e = enqueue_desc(bpn, desc, ws, s);
+  if (e == hipSuccess) e = enqueue_ccm(bpn, desc, ws, s);
+  if (e == hipSuccess) e = enqueue_eig(bpn, desc, ws, s);
+  if (e != hipSuccess) return e;
   return launch_flag_batch((const FlagItem*)(ws + bpn.flag_off), n, s);
+}
+
+// Median time (ms) of three runs of fn on s after one warm-up; -1 on a
+// launch error; the warm-up time alone when it exceeds `cutoff` ms.
+float time_ms(const std::function<hipError_t()>& fn, hipStream_t s, float cutoff) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess) return -1.f;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return -1.f;
+  }
+  float res = -1.f, t[3] = {0, 0, 0};
+  int run = 0;
+  for (; run < 4; ++run) {
+    if (hipEventRecord(a, s) != hipSuccess || fn() != hipSuccess ||
+        hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess)
+      break;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (run == 0 && ms > cutoff) {
+      res = ms;
+      run = 5;
+      break;
+    }
+    if (run > 0) t[run - 1] = ms;
+  }
+  if (run == 4) {
+    std::sort(t, t + 3);
+    res = t[1];
+  }
+  (void)hipGetLastError();
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return res;
 }
 
 }  // namespace
@@ -281,6 +367,133 @@ rfi_status rfi_process_batch(int32_t nitem, const rfi_batch_item* items,
   return rfi::check_hip(rfi::enqueue_batch(bpn, bpn.host.data(), (char*)workspace,
                                            (hipStream_t)stream),
                         who);
+}
+
+rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items, const rfi_batch_params* p,
+                          void* workspace, rfi_tune_table* table, rfi_stream_t stream) {
+  rfi::clear_error();
+  const char* who = "rfi_tune_batch";
+  if (!table) return fail(RFI_E_INVALID, "%s: table is NULL", who);
+  std::memset(table, 0, sizeof(*table));
+  rfi_batch_params base{32, 12, 50, 0, 3.0, nullptr};
+  if (p) base = *p;
+  base.tune = nullptr;
+  rfi::BatchPlan full;
+  rfi_status st = rfi::plan_batch(nitem, items, &base, &full, who);
+  if (st != RFI_OK) return st;
+  if (full.plans.empty()) return RFI_OK;
+  if (!workspace || (uintptr_t)workspace % 256 != 0)
+    return fail(RFI_E_INVALID, "%s: workspace NULL or not 256-byte aligned", who);
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  // the items of each shape class
+  std::map<int, std::vector<rfi_batch_item>> by_class;
+  std::map<int, int> max_nbeam;
+  for (const rfi::ItemPlan& ip : full.plans) {
+    const int sc = rfi::shape_class(ip.nbeam);
+    by_class[sc].push_back(items[ip.idx]);
+    max_nbeam[sc] = std::max(max_nbeam[sc], ip.nbeam);
+  }
+  const int precision = full.eig.precision;
+  int ne = 0;
+  for (auto& kv : by_class) {
+    if (ne >= RFI_TUNE_MAX) break;
+    const int sc = kv.first;
+    std::vector<rfi_batch_item>& sub = kv.second;
+    rfi_tune_entry cur{};
+    cur.nbeam_lo = rfi::class_lo(sc);
+    cur.nbeam_hi = rfi::class_hi(sc);
+    rfi_tune_table one{};
+    one.n = 1;
+    // plan the class's items with the entry `e`; run one part of it
+    auto measure = [&](const rfi_tune_entry& e, int part, float cutoff) -> float {
+      one.e[0] = e;
+      rfi_batch_params q = base;
+      q.tune = &one;
+      rfi::BatchPlan bp;
+      if (rfi::plan_batch((int32_t)sub.size(), sub.data(), &q, &bp, who) != RFI_OK) return -1.f;
+      rfi::fill_descriptors(sub.data(), &bp, ws);
+      if (rfi::enqueue_desc(bp, bp.host.data(), ws, s) != hipSuccess) return -1.f;
+      if (part == 1) {
+        // sums first (the eigen stage reads them), then the eigen launches
+        if (rfi::enqueue_ccm(bp, bp.host.data(), ws, s) != hipSuccess) return -1.f;
+        return rfi::time_ms([&] { return rfi::enqueue_eig(bp, bp.host.data(), ws, s); }, s,
+                            cutoff);
+      }
+      return rfi::time_ms([&] { return rfi::enqueue_ccm(bp, bp.host.data(), ws, s); }, s, cutoff);
+    };
+    const float big = 1e30f;
+    const float ccm_def = measure(cur, 0, big);
+    const float eig_def = measure(cur, 1, big);
+    if (ccm_def < 0.f || eig_def < 0.f) {
+      (void)hipGetLastError();
+      return fail(RFI_E_DEVICE, "%s: default launch of class %d-%d failed", who, cur.nbeam_lo,
+                  cur.nbeam_hi);
+    }
+    // sums: tile variant x ring depth, then the XCD group size
+    rfi_tune_entry best = cur;
+    float best_ccm = ccm_def;
+    std::vector<long long> seen;
+    {
+      rfi::CcmClass c0;
+      if (rfi::ccm_class(kv.second.empty() ? 19 : max_nbeam[sc], &c0, nullptr) == hipSuccess)
+        seen.push_back(c0.key);
+    }
+    for (int tile = 0; tile < rfi::ccm_tile_variants(max_nbeam[sc]); ++tile) {
+      for (int stages = 4; stages >= 2; --stages) {
+        rfi_tune_entry e = cur;
+        e.ccm_tile = tile;
+        e.ccm_stages = stages;
+        rfi::CcmTune ct{tile, stages, 0};
+        rfi::CcmClass cc;
+        if (rfi::ccm_class(max_nbeam[sc], &cc, &ct) != hipSuccess) continue;
+        if (std::find(seen.begin(), seen.end(), cc.key) != seen.end()) continue;
+        seen.push_back(cc.key);
+        const float t = measure(e, 0, 4.f * best_ccm);
+        if (t > 0.f && t < best_ccm) {
+          best_ccm = t;
+          best.ccm_tile = tile;
+          best.ccm_stages = stages;
+        }
+      }
+    }
+    for (int gb : {256, 512, 2048, 4096, 8192}) {
+      rfi_tune_entry e = best;
+      e.ccm_group_bytes = gb;
+      const float t = measure(e, 0, 4.f * best_ccm);
+      if (t > 0.f && t < best_ccm) {
+        best_ccm = t;
+        best.ccm_group_bytes = gb;
+      }
+    }
+    // eigen: the solvers that apply to every block of the class
+    float best_eig = eig_def;
+    std::vector<std::pair<int, int>> cands;  // (solver, wg)
+    if (precision == 32 && max_nbeam[sc] <= 20) {
+      cands = {{RFI_EIG_LANE, 256}, {RFI_EIG_LANE, 128}, {RFI_EIG_LANE, 64}, {RFI_EIG_TRIDIAG, 0}};
+    } else {
+      cands = {{RFI_EIG_TRIDIAG, 0}, {RFI_EIG_WAVE, 0}};
+    }
+    const int def_solver = precision == 64 ? RFI_EIG_WAVE
+                           : (max_nbeam[sc] <= 20 ? RFI_EIG_LANE : RFI_EIG_TRIDIAG);
+    for (auto& c : cands) {
+      if (c.first == def_solver && (c.second == 0 || c.second == 256)) continue;  // measured
+      rfi_tune_entry e = best;
+      e.eig_solver = c.first;
+      e.eig_wg = c.second;
+      const float t = measure(e, 1, 4.f * best_eig);
+      if (t > 0.f && t < best_eig) {
+        best_eig = t;
+        best.eig_solver = c.first;
+        best.eig_wg = c.second;
+      }
+    }
+    best.ms_default = (double)ccm_def + eig_def;
+    best.ms_tuned = (double)best_ccm + best_eig;
+    table->e[ne++] = best;
+  }
+  table->n = ne;
+  return rfi::check_hip(hipGetLastError(), who);
 }
 
 rfi_status rfi_batch_graph_create(int32_t nitem, const rfi_batch_item* items,

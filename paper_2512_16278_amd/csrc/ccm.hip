@@ -119,13 +119,14 @@ __device__ __forceinline__ void wait_chunk(int ahead) {
 
 // Tiles per XCD group: 1 KB of contiguous row bytes by default (measured best
 // for the 4 KB-row FAST layout); RFI_CCM_GROUP_BYTES overrides.
-int group_tiles(int cw) {
+int group_tiles(int cw, int group_bytes_override = 0) {
   static const int group_bytes = [] {
     const char* v = getenv("RFI_CCM_GROUP_BYTES");
     const int g = v ? atoi(v) : 1024;
     return g < 16 ? 16 : g;
   }();
-  return group_bytes / cw > 1 ? group_bytes / cw : 1;
+  const int gb = group_bytes_override > 0 ? group_bytes_override : group_bytes;
+  return gb / cw > 1 ? gb / cw : 1;
 }
 
 template <int NB, int CW, int CPW, int IPW, int NST>
@@ -445,7 +446,7 @@ int epilogue_passes(int nbeam) {
 template <int NB, int CW, int CPW, int IPW, int NST>
 hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
-                           int32_t* count, int accumulate, hipStream_t s) {
+                           int32_t* count, int accumulate, int group_bytes, hipStream_t s) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   if ((int64_t)nbeam * C::UPB > (int64_t)64 * IPW * C::NWAVE) return hipErrorInvalidValue;
   if (nbeam > C::MAXB) return hipErrorInvalidValue;
@@ -457,7 +458,7 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
                                      hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
   if (e != hipSuccess) return e;
   const int64_t ntiles = (int64_t)nsub * nct;
-  const int G = group_tiles(CW);
+  const int G = group_tiles(CW, group_bytes);
   // tuning knob: RFI_CCM_PRIO=1 raises the streaming waves' issue priority
   static const int prio = [] {
     const char* v = getenv("RFI_CCM_PRIO");
@@ -470,13 +471,14 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
 }
 
 template <int NB, int CW, int CPW, int IPW, int NST>
-hipError_t launch_batch_cfg(const CcmItem* items, int nitem, int total_wg, hipStream_t s) {
+hipError_t launch_batch_cfg(const CcmItem* items, int nitem, int total_wg, int group_bytes,
+                            hipStream_t s) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   const auto kern = ccm_mfma_kernel<NB, CW, CPW, IPW, NST>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, C::LDS);
   if (e != hipSuccess) return e;
-  const int G = group_tiles(CW);
+  const int G = group_tiles(CW, group_bytes);
   BeamPtrs none;
   memset(&none, 0, sizeof(none));
   hipLaunchKernelGGL(kern, dim3((unsigned)total_wg), dim3(C::NTHR), C::LDS, s, none, 0, 0,
@@ -501,9 +503,10 @@ hipError_t dispatch_nst(int max_stages, Op& op) {
 
 // The MFMA engine's instance for a beam count: 16-row blocks NB (including
 // the ones row), tile width CW channels, CPW channels per wave, IPW loads per
-// wave per chunk, ring depth NST.
+// wave per chunk, ring depth NST. t (nullable) selects another tile variant
+// of the beam count and caps the ring depth.
 template <class Op>
-hipError_t ccm_dispatch(int nbeam, int shared_cu, Op& op) {
+hipError_t ccm_dispatch(int nbeam, int shared_cu, Op& op, const CcmTune* t = nullptr) {
   const int nb = (nbeam + 1 + 15) / 16;
   // tile shape per block count: (CW channels, CPW channels per wave). With
   // shared_cu the 19-beam tile is 32 channels on 8 waves of ~120 VGPRs.
@@ -512,21 +515,26 @@ hipError_t ccm_dispatch(int nbeam, int shared_cu, Op& op) {
     const char* e = getenv("RFI_CCM_CPW");
     return e && atoi(e) == 4 ? 4 : 8;
   }();
+  const int tile = t ? t->tile : 0;
+  if (tile < 0 || tile >= ccm_tile_variants(nbeam)) return hipErrorInvalidValue;
   switch (nb) {
     case 1: cw = 64; cpw = 8; break;
     case 2:
-      if (shared_cu) { cw = 32; cpw = 4; } else { cw = 64; cpw = cpw2; }
+      if (tile == 1) { cw = 64; cpw = 4; }
+      else if (tile == 2 || shared_cu) { cw = 32; cpw = 4; }
+      else { cw = 64; cpw = cpw2; }
       break;
     case 3: cw = 32; cpw = 4; break;
     case 4: case 5: cw = 16; cpw = 2; break;
     default: return hipErrorInvalidValue;
   }
   // ring depth cap (tuning knob; default: the largest ring that fits)
-  static const int max_stages = [] {
+  static const int env_stages = [] {
     const char* e = getenv("RFI_CCM_STAGES");
     const int v = e ? atoi(e) : 4;
     return v < 2 ? 2 : v;
   }();
+  const int max_stages = t && t->stages >= 2 ? t->stages : env_stages;
   const int nwave = cw / cpw;
   const int units = nbeam * 32 * (cw / 16);        // 16-byte units per chunk
   const int ipw = (units + 64 * nwave - 1) / (64 * nwave);  // loads per wave per chunk
@@ -551,12 +559,12 @@ struct LaunchOne {
   int64_t row_stride, t0;
   int L, nsub;
   int32_t *sum_x, *sum_xy, *count;
-  int accumulate;
+  int accumulate, group_bytes;
   hipStream_t s;
   template <int NB, int CW, int CPW, int IPW, int NST>
   hipError_t run() {
     return launch_mfma_cfg<NB, CW, CPW, IPW, NST>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
-                                                  sum_xy, count, accumulate, s);
+                                                  sum_xy, count, accumulate, group_bytes, s);
   }
 };
 
@@ -574,11 +582,11 @@ struct Describe {
 
 struct LaunchBatch {
   const CcmItem* items;
-  int nitem, total_wg;
+  int nitem, total_wg, group_bytes;
   hipStream_t s;
   template <int NB, int CW, int CPW, int IPW, int NST>
   hipError_t run() {
-    return launch_batch_cfg<NB, CW, CPW, IPW, NST>(items, nitem, total_wg, s);
+    return launch_batch_cfg<NB, CW, CPW, IPW, NST>(items, nitem, total_wg, group_bytes, s);
   }
 };
 
@@ -647,22 +655,33 @@ __global__ __launch_bounds__(256) void ccm_valu_kernel(BeamPtrs bp, int nbeam, i
 
 }  // namespace
 
+int ccm_tile_variants(int nbeam) {
+  const int nb = (nbeam + 1 + 15) / 16;
+  return nb == 2 ? 3 : (nb >= 1 && nb <= 5 ? 1 : 0);
+}
+
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
-                           int32_t* count, int accumulate, int shared_cu, hipStream_t s) {
-  LaunchOne op{bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, sum_xy, count, accumulate, s};
-  return ccm_dispatch(nbeam, shared_cu, op);
+                           int32_t* count, int accumulate, int shared_cu, hipStream_t s,
+                           const CcmTune* t) {
+  LaunchOne op{bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, sum_xy, count, accumulate,
+               t ? t->group_bytes : 0, s};
+  return ccm_dispatch(nbeam, shared_cu, op, t);
 }
 
-hipError_t ccm_class(int nbeam, CcmClass* c) {
+hipError_t ccm_class(int nbeam, CcmClass* c, const CcmTune* t) {
   Describe op{nbeam, c};
-  return ccm_dispatch(nbeam, 0, op);
+  hipError_t e = ccm_dispatch(nbeam, 0, op, t);
+  // the tile group size is a launch argument: part of the class
+  c->group_bytes = t ? t->group_bytes : 0;
+  c->key = c->key * 65536 + (c->group_bytes & 0xFFFF);
+  return e;
 }
 
-hipError_t launch_ccm_batch(int nbeam_of_class, const CcmItem* items, int nitem, int total_wg,
-                            hipStream_t s) {
-  LaunchBatch op{items, nitem, total_wg, s};
-  return ccm_dispatch(nbeam_of_class, 0, op);
+hipError_t launch_ccm_batch(int nbeam_of_class, const CcmTune* t, const CcmItem* items,
+                            int nitem, int total_wg, hipStream_t s) {
+  LaunchBatch op{items, nitem, total_wg, t ? t->group_bytes : 0, s};
+  return ccm_dispatch(nbeam_of_class, 0, op, t);
 }
 
 hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,

@@ -379,12 +379,12 @@ __global__ __launch_bounds__(256) void eig_lane_refine_batch(const EigArgs* item
 
 template <int N>
 hipError_t launch_batch_n(const EigArgs* items, const int64_t* cell0, int nitem, int64_t total,
-                          hipStream_t s) {
-  const dim3 grid((unsigned)((total + 255) / 256));
-  hipLaunchKernelGGL(eig_lane_jacobi_batch<N>, grid, dim3(256), 0, s, items, cell0, nitem, total);
+                          int wg, hipStream_t s) {
+  const dim3 grid((unsigned)((total + wg - 1) / wg));
+  hipLaunchKernelGGL(eig_lane_jacobi_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem, total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(eig_lane_refine_batch<N>, grid, dim3(256), 0, s, items, cell0, nitem, total);
+  hipLaunchKernelGGL(eig_lane_refine_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem, total);
   return hipGetLastError();
 }
 
@@ -412,14 +412,15 @@ int eig_lane_class(int n) {
 }
 
 hipError_t launch_eig_lane_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
-                                 int64_t total, hipStream_t s) {
+                                 int64_t total, hipStream_t s, int wg) {
+  if (wg != 64 && wg != 128 && wg != 256) return hipErrorInvalidValue;
   switch (cls) {
-    case 4: return launch_batch_n<4>(items, cell0, nitem, total, s);
-    case 8: return launch_batch_n<8>(items, cell0, nitem, total, s);
-    case 12: return launch_batch_n<12>(items, cell0, nitem, total, s);
-    case 16: return launch_batch_n<16>(items, cell0, nitem, total, s);
-    case 19: return launch_batch_n<19>(items, cell0, nitem, total, s);
-    case 20: return launch_batch_n<20>(items, cell0, nitem, total, s);
+    case 4: return launch_batch_n<4>(items, cell0, nitem, total, wg, s);
+    case 8: return launch_batch_n<8>(items, cell0, nitem, total, wg, s);
+    case 12: return launch_batch_n<12>(items, cell0, nitem, total, wg, s);
+    case 16: return launch_batch_n<16>(items, cell0, nitem, total, wg, s);
+    case 19: return launch_batch_n<19>(items, cell0, nitem, total, wg, s);
+    case 20: return launch_batch_n<20>(items, cell0, nitem, total, wg, s);
     default: return hipErrorInvalidValue;
   }
 }

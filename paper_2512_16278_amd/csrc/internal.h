@@ -26,21 +26,31 @@ struct CcmItem {
   int32_t nbeam, nchan, L, nsub;
   int32_t nct, nh, wg0, pad;
 };
+// Launch choices of the MFMA sums engine (all 0 = defaults): tile = variant
+// index of the beam count's tile shapes (< ccm_tile_variants), stages = cap
+// of the load ring depth (2..4), group_bytes = contiguous row bytes of the
+// tiles given to one XCD in turn.
+struct CcmTune {
+  int tile, stages, group_bytes;
+};
+int ccm_tile_variants(int nbeam);
 // Instance class of the MFMA sums engine for a beam count: blocks of one
 // class share a batched launch; cw = channels per tile, nh = epilogue passes.
 struct CcmClass {
-  int key, cw, nh;
+  long long key;
+  int cw, nh, group_bytes;
 };
-hipError_t ccm_class(int nbeam, CcmClass* c);
+hipError_t ccm_class(int nbeam, CcmClass* c, const CcmTune* t = nullptr);
 // Batched sums launch over the items of one class (items in device memory,
-// sorted by wg0); nbeam_of_class is any member's beam count.
-hipError_t launch_ccm_batch(int nbeam_of_class, const CcmItem* items, int nitem, int total_wg,
-                            hipStream_t s);
+// sorted by wg0); nbeam_of_class is any member's beam count, t its choices.
+hipError_t launch_ccm_batch(int nbeam_of_class, const CcmTune* t, const CcmItem* items,
+                            int nitem, int total_wg, hipStream_t s);
 
 // Kernel launchers (return a HIP error code; arguments already validated).
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
-                           int32_t* count, int accumulate, int shared_cu, hipStream_t s);
+                           int32_t* count, int accumulate, int shared_cu, hipStream_t s,
+                           const CcmTune* t = nullptr);
 hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, hipStream_t s);
@@ -70,7 +80,7 @@ hipError_t launch_eig(const EigArgs& a, const rfi_eig_params& p, hipStream_t s, 
 // per-wave solver any beam counts up to max_nbeam.
 int eig_lane_class(int n);
 hipError_t launch_eig_lane_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
-                                 int64_t total, hipStream_t s);
+                                 int64_t total, hipStream_t s, int wg = 256);
 hipError_t launch_eig_wave_batch(int precision, int max_nbeam, const EigArgs* items,
                                  const int64_t* cell0, int nitem, int64_t total, hipStream_t s);
 // The per-wave tridiagonal solver: template class of a beam count (local

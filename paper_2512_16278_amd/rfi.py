@@ -71,9 +71,29 @@ class rfi_batch_item(C.Structure):
                 ("out", C.c_void_p)]
 
 
+class rfi_tune_entry(C.Structure):
+    _fields_ = [("nbeam_lo", C.c_int32), ("nbeam_hi", C.c_int32), ("ccm_tile", C.c_int32),
+                ("ccm_stages", C.c_int32), ("ccm_group_bytes", C.c_int32),
+                ("eig_solver", C.c_int32), ("eig_wg", C.c_int32), ("pad", C.c_int32),
+                ("ms_default", C.c_double), ("ms_tuned", C.c_double)]
+
+
+RFI_TUNE_MAX = 8
+
+
+class rfi_tune_table(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad", C.c_int32), ("e", rfi_tune_entry * RFI_TUNE_MAX)]
+
+
+def tune_table_dict(t: rfi_tune_table) -> list:
+    """Entries of a tune table as dicts."""
+    return [{f: getattr(t.e[i], f) for f, _ in rfi_tune_entry._fields_ if f != "pad"}
+            for i in range(t.n)]
+
+
 class rfi_batch_params(C.Structure):
     _fields_ = [("eig_precision", C.c_int32), ("max_sweeps", C.c_int32), ("max_iter", C.c_int32),
-                ("pad", C.c_int32), ("kappa", C.c_double)]
+                ("pad", C.c_int32), ("kappa", C.c_double), ("tune", C.POINTER(rfi_tune_table))]
 
 
 class rfi_session_config(C.Structure):
@@ -157,6 +177,10 @@ def lib():
         L.rfi_batch_graph_create.argtypes = [i32, C.POINTER(rfi_batch_item),
                                              C.POINTER(rfi_batch_params), vp, C.POINTER(vp)]
         L.rfi_batch_graph_launch.argtypes = [vp, vp]
+        L.rfi_tune_batch.argtypes = [i32, C.POINTER(rfi_batch_item), C.POINTER(rfi_batch_params),
+                                     vp, C.POINTER(rfi_tune_table), vp]
+        L.rfi_ccm_tile_variants.argtypes = [i32]
+        L.rfi_ccm_tile_variants.restype = i32
         L.rfi_batch_graph_destroy.argtypes = [vp]
         L.rfi_batch_graph_destroy.restype = None
         L.rfi_stream_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
@@ -166,7 +190,7 @@ def lib():
                   "rfi_stream_close", "rfi_submit", "rfi_poll", "rfi_wait", "rfi_cancel",
                   "rfi_result_release", "rfi_stream_export", "rfi_stream_import",
                   "rfi_result_copy", "rfi_process_batch", "rfi_batch_graph_create",
-                  "rfi_batch_graph_launch"):
+                  "rfi_batch_graph_launch", "rfi_tune_batch"):
             getattr(L, f).restype = i32
         L.rfi_last_error.restype = C.c_char_p
         L.rfi_version.restype = C.c_char_p
@@ -278,7 +302,8 @@ class Batch:
     (block, t0, L, nsub, stat, status, mask[, out, state, protect_chan]) with
     device tensors; the ctypes structures are kept alive here."""
 
-    def __init__(self, items, eig_precision=32, max_sweeps=12, max_iter=50, kappa=3.0):
+    def __init__(self, items, eig_precision=32, max_sweeps=12, max_iter=50, kappa=3.0,
+                 tune: "rfi_tune_table | None" = None):
         self._blocks = [it["blk"] for it in items]
         n = len(items)
         self.n = n
@@ -295,8 +320,9 @@ class Batch:
             a.status = _ptr(it["status"])
             a.mask = _ptr(it["mask"])
             a.out = _ptr(it.get("out"))
+        self.tune_table = tune
         self.p = rfi_batch_params(int(eig_precision), int(max_sweeps), int(max_iter), 0,
-                                  float(kappa))
+                                  float(kappa), C.pointer(tune) if tune is not None else None)
 
     def workspace_size(self):
         return int(lib().rfi_batch_workspace_size(self.n, self.arr, C.byref(self.p)))
@@ -304,6 +330,14 @@ class Batch:
     def run(self, workspace, stream=None):
         _check(lib().rfi_process_batch(self.n, self.arr, C.byref(self.p), _ptr(workspace),
                                        _stream(stream)))
+
+    def tune(self, workspace, stream=None) -> rfi_tune_table:
+        """rfi_tune_batch on these items: the per-class launch choices (the
+        table is not applied; pass it as Batch(..., tune=table))."""
+        t = rfi_tune_table()
+        _check(lib().rfi_tune_batch(self.n, self.arr, C.byref(self.p), _ptr(workspace), C.byref(t),
+                                    _stream(stream)))
+        return t
 
     def graph(self, workspace):
         return BatchGraph(self, workspace)

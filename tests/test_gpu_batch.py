@@ -167,3 +167,110 @@ def test_batch_empty_and_errors(dev):
     assert bad.workspace_size() == 0
     with pytest.raises(rfi.RfiError):
         bad.run(torch.empty(256, dtype=torch.uint8, device=dev))
+
+
+def _run_batch(blocks, dev, tune=None):
+    import torch
+    from paper_2512_16278_amd import rfi
+    items = _batch_items(blocks, dev)
+    bt = rfi.Batch(items, tune=tune)
+    ws = torch.empty(bt.workspace_size(), dtype=torch.uint8, device=dev)
+    bt.run(ws)
+    torch.cuda.synchronize()
+    return [[it[k].cpu().numpy() for k in ("stat", "status", "mask", "out")] for it in items]
+
+
+def _table(entries):
+    from paper_2512_16278_amd import rfi
+    t = rfi.rfi_tune_table()
+    t.n = len(entries)
+    for i, e in enumerate(entries):
+        for k, v in e.items():
+            setattr(t.e[i], k, v)
+    return t
+
+
+CLASSES = [(2, 15), (16, 31), (32, 47), (48, 63), (64, 79)]
+
+
+def test_forced_launch_choices_are_bit_exact(dev):
+    """Every sums-engine choice (tile variant, ring depth, XCD group size) and
+    every per-lane workgroup size computes the same bits as the defaults."""
+    from paper_2512_16278_amd import rfi
+    blocks = _make(dev)
+    for b in blocks:
+        b["state"] = None
+    ref = _run_batch(blocks, dev)
+    L = rfi.lib()
+    for lo, hi in CLASSES:
+        nb = next((b["nb"] for b in blocks if lo <= b["nb"] <= hi), None)
+        if nb is None:
+            continue
+        for tile in range(L.rfi_ccm_tile_variants(nb)):
+            for stages in (2, 3, 4):
+                for gb in (0, 256, 4096):
+                    say("forced", lo, hi, "tile", tile, "stages", stages, "group", gb)
+                    t = _table([dict(nbeam_lo=lo, nbeam_hi=hi, ccm_tile=tile, ccm_stages=stages,
+                                     ccm_group_bytes=gb)])
+                    got = _run_batch(blocks, dev, t)
+                    for g, r in zip(got, ref):
+                        for u, v in zip(g, r):
+                            assert np.array_equal(u, v), (lo, tile, stages, gb)
+    for wg in (64, 128):
+        t = _table([dict(nbeam_lo=2, nbeam_hi=15, eig_solver=rfi.RFI_EIG_LANE, eig_wg=wg),
+                    dict(nbeam_lo=16, nbeam_hi=31, eig_solver=rfi.RFI_EIG_LANE, eig_wg=wg)])
+        # the 16-31 class holds a 19-beam block only (per-lane solver applies)
+        got = _run_batch([b for b in blocks if b["nb"] <= 20], dev, t)
+        want = [r for b, r in zip(blocks, ref) if b["nb"] <= 20]
+        for g, r in zip(got, want):
+            for u, v in zip(g, r):
+                assert np.array_equal(u, v), wg
+
+
+def test_tuned_batch_matches_oracle_and_graph(dev):
+    import torch
+    from paper_2512_16278_amd import rfi
+    blocks = _make(dev)
+    for b in blocks:
+        b["state"] = None
+    items = _batch_items(blocks, dev)
+    bt = rfi.Batch(items)
+    ws = torch.empty(bt.workspace_size(), dtype=torch.uint8, device=dev)
+    say("tune: rfi_tune_batch")
+    table = bt.tune(ws)
+    ents = rfi.tune_table_dict(table)
+    present = sorted({next(i for i, (lo, hi) in enumerate(CLASSES) if lo <= b["nb"] <= hi)
+                      for b in blocks})
+    assert [(e["nbeam_lo"], e["nbeam_hi"]) for e in ents] == [CLASSES[i] for i in present]
+    for e in ents:
+        assert 0 < e["ms_tuned"] <= e["ms_default"] + 1e-9, e
+        assert 0 <= e["ccm_tile"] < 3 and e["ccm_stages"] in (0, 2, 3, 4)
+        assert e["ccm_group_bytes"] in (0, 256, 512, 2048, 4096, 8192)
+        assert e["eig_solver"] in (0, rfi.RFI_EIG_LANE, rfi.RFI_EIG_WAVE, rfi.RFI_EIG_TRIDIAG)
+        if e["eig_solver"] == rfi.RFI_EIG_LANE:
+            assert e["nbeam_hi"] <= 31 and e["eig_wg"] in (64, 128, 256)
+    tuned = rfi.Batch(items, tune=table)
+    ws2 = torch.empty(tuned.workspace_size(), dtype=torch.uint8, device=dev)
+    tuned.run(ws2)
+    torch.cuda.synchronize()
+    eager = [[it[k].cpu().numpy() for k in ("stat", "status", "mask", "out")] for it in items]
+    for b, it in zip(blocks, items):
+        cr = pipeline.cells(b["x"], b["L"], b["nsub"], t0=b["t0"])
+        ok = pipeline.eligible_cells(cr.degenerate, None if b["protect_chan"] is None
+                                     else b["protect_chan"].cpu().numpy())
+        res = clip.clip_iterative(cr.stat.ravel(), ok.ravel())
+        assert np.abs(it["stat"].cpu().numpy() - cr.stat.ravel()).max() <= 1e-9, b["nb"]
+        assert np.array_equal(it["mask"].cpu().numpy().astype(bool), res.mask), b["nb"]
+    g = tuned.graph(ws2)
+    for rep in range(2):
+        for it in items:
+            it["stat"].fill_(-3.0)
+            it["mask"].fill_(9)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for it, e in zip(items, eager):
+            got = [it[k].cpu().numpy() for k in ("stat", "status", "mask", "out")]
+            for u, v in zip(got, e):
+                assert np.array_equal(u, v), rep
+    g.close()

@@ -86,6 +86,76 @@ def test_struct_layouts_match_header():
     assert f"#define RFI_MAX_COUNT {rfi.RFI_MAX_COUNT}" in hdr
 
 
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """sizeof / offsetof of the ABI structures as gcc sees include/rfi.h equal
+    the ctypes mirrors of the binding."""
+    import shutil
+    import subprocess
+    from paper_2512_16278_amd import rfi
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("gcc not found")
+    checks = {
+        "rfi_tune_entry": rfi.rfi_tune_entry, "rfi_tune_table": rfi.rfi_tune_table,
+        "rfi_batch_params": rfi.rfi_batch_params, "rfi_batch_item": rfi.rfi_batch_item,
+        "rfi_block": rfi.rfi_block, "rfi_flag_stats": rfi.rfi_flag_stats,
+        "rfi_stream_state": rfi.rfi_stream_state, "rfi_eig_params": rfi.rfi_eig_params,
+        "rfi_process_params": rfi.rfi_process_params,
+        "rfi_session_config": rfi.rfi_session_config,
+        "rfi_stream_config": rfi.rfi_stream_config, "rfi_result": rfi.rfi_result,
+    }
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rfi.h"', "int main(void) {"]
+    for name, st in checks.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for name, st in checks.items():
+        assert int(got[name]) == C.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, (name, f)
+
+
+def test_tune_arguments():
+    from paper_2512_16278_amd import rfi
+    L = rfi.lib()
+    assert [L.rfi_ccm_tile_variants(n) for n in (1, 2, 15, 16, 19, 31, 36, 72, 79, 80)] == \
+        [0, 1, 1, 3, 3, 3, 1, 1, 1, 0]
+    blk = rfi.rfi_block()
+    blk.nbeam, blk.nchan, blk.nsamp, blk.row_stride = 19, 64, 1024, 64
+    for b in range(19):
+        blk.beam[b] = 256 * (b + 1)          # never dereferenced
+    items = (rfi.rfi_batch_item * 1)()
+    items[0].blk = C.pointer(blk)
+    items[0].L, items[0].nsub = 256, 2
+    items[0].stat = items[0].status = items[0].mask = 256
+    t = rfi.rfi_tune_table()
+    p = rfi.rfi_batch_params(32, 12, 50, 0, 3.0, C.pointer(t))
+    assert L.rfi_batch_workspace_size(1, items, C.byref(p)) > 0      # empty table
+    t.n = 1
+    t.e[0].nbeam_lo, t.e[0].nbeam_hi = 16, 31
+    for field, val in (("ccm_tile", 3), ("ccm_stages", 5), ("ccm_group_bytes", 1 << 20),
+                       ("eig_wg", 96), ("eig_solver", 9)):
+        setattr(t.e[0], field, val)
+        assert L.rfi_batch_workspace_size(1, items, C.byref(p)) == 0, field
+        assert L.rfi_last_error()
+        setattr(t.e[0], field, 0)
+    t.e[0].ccm_tile, t.e[0].eig_wg, t.e[0].eig_solver = 2, 64, rfi.RFI_EIG_TRIDIAG
+    assert L.rfi_batch_workspace_size(1, items, C.byref(p)) > 0
+    t.n = 99
+    assert L.rfi_batch_workspace_size(1, items, C.byref(p)) == 0
+    assert L.rfi_tune_batch(1, items, C.byref(p), None, None, None) == rfi.RFI_E_INVALID
+    out = rfi.rfi_tune_table()
+    assert L.rfi_tune_batch(1, items, C.byref(p), None, C.byref(out), None) == rfi.RFI_E_INVALID
+
+
 def test_process_block_argument_errors():
     from paper_2512_16278_amd import rfi
     L = rfi.lib()
