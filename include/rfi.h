@@ -326,7 +326,8 @@ rfi_status rfi_process_batch(int32_t nitem, const rfi_batch_item* items /* host 
  * class's sums launch for each tile variant and ring depth, then for each
  * XCD group size, and its eigen launch for each applicable solver (and
  * per-lane workgroup size), on the caller's blocks, and writes the fastest
- * choices to *table (host), one entry per class, ordered by beam count.
+ * choices to *table (host), one entry per class, ordered by beam count (a
+ * choice replaces the default only when it is more than 2 % faster).
  * Every candidate computes the same sums (exact integers) and, per solver,
  * the same statistic bits, so only time differs. Synchronous: it runs the
  * candidates on stream and waits for them (a warm-up and three timed runs

@@ -211,6 +211,7 @@ void fill_descriptors(const rfi_batch_item* items, BatchPlan* bpn, char* ws) {
       c.nct = (ip.nchan + ip.cc.cw - 1) / ip.cc.cw;
       c.nh = ip.cc.nh;
       c.wg0 = wg;
+      c.layout = ip.solver == RFI_EIG_TRIDIAG ? 1 : 0;
       wg += (c.nsub * c.nct + 7) / 8 * 8;
     }
   }
@@ -228,7 +229,8 @@ void fill_descriptors(const rfi_batch_item* items, BatchPlan* bpn, char* ws) {
       int32_t *sx, *sxy, *cnt;
       sums(ip, &sx, &sxy, &cnt);
       a = EigArgs{ip.nbeam, it.nsub, ip.nchan, sx, sxy, cnt, bpn->eig.max_sweeps, 1,
-                  nullptr, it.stat, nullptr, it.status, ip.ncell};
+                  nullptr, it.stat, nullptr, it.status, ip.ncell,
+                  ip.solver == RFI_EIG_TRIDIAG ? 1 : 0};
       c0[cpos++] = cell;
       cell += ip.ncell;
     }
@@ -423,6 +425,8 @@ rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items, const rfi_
       return rfi::time_ms([&] { return rfi::enqueue_ccm(bp, bp.host.data(), ws, s); }, s, cutoff);
     };
     const float big = 1e30f;
+    // a candidate replaces the incumbent only when clearly faster (timing noise)
+    constexpr float kGain = 0.98f;
     const float ccm_def = measure(cur, 0, big);
     const float eig_def = measure(cur, 1, big);
     if (ccm_def < 0.f || eig_def < 0.f) {
@@ -450,7 +454,7 @@ rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items, const rfi_
         if (std::find(seen.begin(), seen.end(), cc.key) != seen.end()) continue;
         seen.push_back(cc.key);
         const float t = measure(e, 0, 4.f * best_ccm);
-        if (t > 0.f && t < best_ccm) {
+        if (t > 0.f && t < kGain * best_ccm) {
           best_ccm = t;
           best.ccm_tile = tile;
           best.ccm_stages = stages;
@@ -461,7 +465,7 @@ rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items, const rfi_
       rfi_tune_entry e = best;
       e.ccm_group_bytes = gb;
       const float t = measure(e, 0, 4.f * best_ccm);
-      if (t > 0.f && t < best_ccm) {
+      if (t > 0.f && t < kGain * best_ccm) {
         best_ccm = t;
         best.ccm_group_bytes = gb;
       }
@@ -482,7 +486,7 @@ rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items, const rfi_
       e.eig_solver = c.first;
       e.eig_wg = c.second;
       const float t = measure(e, 1, 4.f * best_eig);
-      if (t > 0.f && t < best_eig) {
+      if (t > 0.f && t < kGain * best_eig) {
         best_eig = t;
         best.eig_solver = c.first;
         best.eig_wg = c.second;

@@ -133,7 +133,7 @@ template <int NB, int CW, int CPW, int IPW, int NST>
 __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm_mfma_kernel(
     BeamPtrs bp, int nbeam, int nchan, int64_t row_stride, int64_t t0, int L, int nsub,
     int nct, int32_t* __restrict__ sum_x, int32_t* __restrict__ sum_xy,
-    int32_t* __restrict__ count, int accumulate, int G, int nh, int prio,
+    int32_t* __restrict__ count, int accumulate, int G, int nh, int prio, int layout,
     const CcmItem* __restrict__ items, int nitem) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   // the beam pointer table is the first kernel argument: index it in place
@@ -160,6 +160,7 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
     sum_x = it.sum_x;
     sum_xy = it.sum_xy;
     count = it.count;
+    layout = it.layout;
     w -= it.wg0;
     if (w >= nsub * nct) return;      // padding to a multiple of 8 workgroups
   }
@@ -380,20 +381,27 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
           }
       }
       lds_barrier();
-      // thread t stores channel t mod cwp of rows t / cwp, t / cwp + rstep, ...
-      const int chl = h * cwp + ch_st;
+      // rows layout: thread t stores channel t mod cwp of rows t / cwp,
+      // t / cwp + rstep, ... (runs of consecutive cells); cell records:
+      // thread t stores rows t mod rstep, + rstep, ... of channel t / rstep
+      // (runs of consecutive rows of one cell)
+      const int ch = layout ? tid / rstep : ch_st;
+      const int row0 = layout ? tid % rstep : row_st;
+      const int chl = h * cwp + ch;
       const int chan = c0 + chl;
       if (chan < nchan) {
         const int64_t cell = (int64_t)k * nchan + chan;
-        for (int row = row_st; row < nrow; row += rstep) {
-          const uint32_t v = (uint32_t)stg[row * (cwp + 1) + ch_st];
+        int32_t* rec = sum_x + cell * nrow;
+        for (int row = row0; row < nrow; row += rstep) {
+          const uint32_t v = (uint32_t)stg[row * (cwp + 1) + ch];
           const int ab = rowab[row];
           const int a = ab & 255, b = ab >> 8;
           const uint32_t raw = b == 255 ? v + 128u * cnt
                                         : v + 128u * ((uint32_t)sxl[a * CW + chl] +
                                                       (uint32_t)sxl[b * CW + chl]) + 16384u * cnt;
-          int32_t* dst = (row < nbeam ? sum_x + (int64_t)row * ncell
-                                      : sum_xy + (int64_t)(row - nbeam) * ncell) + cell;
+          int32_t* dst = layout ? rec + row
+                                : (row < nbeam ? sum_x + (int64_t)row * ncell
+                                               : sum_xy + (int64_t)(row - nbeam) * ncell) + cell;
           *dst = accumulate ? (int32_t)((uint32_t)*dst + raw) : (int32_t)raw;
         }
       }
@@ -446,7 +454,8 @@ int epilogue_passes(int nbeam) {
 template <int NB, int CW, int CPW, int IPW, int NST>
 hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
-                           int32_t* count, int accumulate, int group_bytes, hipStream_t s) {
+                           int32_t* count, int accumulate, int group_bytes, int layout,
+                           hipStream_t s) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   if ((int64_t)nbeam * C::UPB > (int64_t)64 * IPW * C::NWAVE) return hipErrorInvalidValue;
   if (nbeam > C::MAXB) return hipErrorInvalidValue;
@@ -466,7 +475,7 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
   }();
   hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), C::LDS, s, bp, nbeam, nchan,
                      row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate, G, nh, prio,
-                     (const CcmItem*)nullptr, 0);
+                     layout, (const CcmItem*)nullptr, 0);
   return hipGetLastError();
 }
 
@@ -483,7 +492,7 @@ hipError_t launch_batch_cfg(const CcmItem* items, int nitem, int total_wg, int g
   memset(&none, 0, sizeof(none));
   hipLaunchKernelGGL(kern, dim3((unsigned)total_wg), dim3(C::NTHR), C::LDS, s, none, 0, 0,
                      (int64_t)0, (int64_t)0, 0, 0, 0, (int32_t*)nullptr, (int32_t*)nullptr,
-                     (int32_t*)nullptr, 0, G, 1, 0, items, nitem);
+                     (int32_t*)nullptr, 0, G, 1, 0, 0, items, nitem);
   return hipGetLastError();
 }
 
@@ -559,12 +568,13 @@ struct LaunchOne {
   int64_t row_stride, t0;
   int L, nsub;
   int32_t *sum_x, *sum_xy, *count;
-  int accumulate, group_bytes;
+  int accumulate, group_bytes, layout;
   hipStream_t s;
   template <int NB, int CW, int CPW, int IPW, int NST>
   hipError_t run() {
     return launch_mfma_cfg<NB, CW, CPW, IPW, NST>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
-                                                  sum_xy, count, accumulate, group_bytes, s);
+                                                  sum_xy, count, accumulate, group_bytes, layout,
+                                                  s);
   }
 };
 
@@ -663,9 +673,9 @@ int ccm_tile_variants(int nbeam) {
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, int shared_cu, hipStream_t s,
-                           const CcmTune* t) {
+                           const CcmTune* t, int layout) {
   LaunchOne op{bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, sum_xy, count, accumulate,
-               t ? t->group_bytes : 0, s};
+               t ? t->group_bytes : 0, layout, s};
   return ccm_dispatch(nbeam, shared_cu, op, t);
 }
 

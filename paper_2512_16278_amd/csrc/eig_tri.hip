@@ -189,9 +189,13 @@ __device__ __forceinline__ int find_item_t(const int64_t* cell0, int nitem, int6
 
 // vcap: doubles of dynamic LDS for the reflectors ((n - 1) 8 NL are needed
 // when v1 is requested; 0 in launches that never ask for v1).
+// Two waves per SIMD up to NL = 9 (72 beams: a few spilled registers cost less
+// than the latency one wave per SIMD leaves exposed); one beyond.
 template <int NL>
-__global__ __launch_bounds__(64) void eig_tri_kernel(EigArgs g, const EigArgs* items,
-                                                     const int64_t* cell0, int nitem, int vcap) {
+__global__ __launch_bounds__(64, NL <= 9 ? 2 : 1) void eig_tri_kernel(EigArgs g,
+                                                                      const EigArgs* items,
+                                                                      const int64_t* cell0,
+                                                                      int nitem, int vcap) {
   constexpr int NN = 8 * NL;
   __shared__ double X[NN], P[NN], alpha[NN], offd[NN], tau[NN], dinv[NN], z[NN];
   __shared__ double2 ae[NN];
@@ -223,8 +227,15 @@ __global__ __launch_bounds__(64) void eig_tri_kernel(EigArgs g, const EigArgs* i
   // correlation matrix in FP64 and ||C||_F^2 (the cell's sums first go to
   // LDS, one pair per lane)
   const int np = n * (n + 1) / 2;
-  for (int q = lane; q < np; q += 64) SP[q] = g.sum_xy[(int64_t)q * ncell + cell];
-  for (int a = lane; a < n; a += 64) S[a] = g.sum_x[a * ncell + cell];
+  if (g.layout) {
+    // one contiguous record per cell: coalesced
+    const int32_t* rec = g.sum_x + cell * (int64_t)(n + np);
+    for (int q = lane; q < np; q += 64) SP[q] = rec[n + q];
+    for (int a = lane; a < n; a += 64) S[a] = rec[a];
+  } else {
+    for (int q = lane; q < np; q += 64) SP[q] = g.sum_xy[(int64_t)q * ncell + cell];
+    for (int a = lane; a < n; a += 64) S[a] = g.sum_x[a * ncell + cell];
+  }
   __syncthreads();
   int dead = 0;
   for (int a = lane; a < n; a += 64) {
@@ -266,84 +277,82 @@ __global__ __launch_bounds__(64) void eig_tri_kernel(EigArgs g, const EigArgs* i
       const int k = 8 * IK + rk;
       __syncthreads();
       if (r == rk) {
-        static_for<IK, NL>([&](auto JJ) { X[c + 8 * RFI_CI(JJ)] = A[IK][RFI_CI(JJ)]; });
-      }
-      __syncthreads();
-      const double x0 = X[k + 1];
-      double s2 = 0.0;
-      double vc[NL];
-      static_for<IK, NL>([&](auto JJ) {
-        constexpr int jj = RFI_CI(JJ);
-        const double x = X[c + 8 * jj];
-        vc[jj] = x;
-        s2 += c + 8 * jj > k + 1 ? x * x : 0.0;
-      });
-      s2 = sum8(s2);
-      // reflector of (x0, x_{k+2}, ...) onto (mu, 0, ...): v0 = x0 - mu (formed
-      // without cancellation), beta = 2 v0^2 / (s2 + v0^2) = -v0 / mu
-      double beta = 0.0, sub = x0, iv0 = 0.0;
-      if (s2 > 0.0) {
-        const double mu = sqrt(fma(x0, x0, s2));
-        const double v0 = x0 <= 0.0 ? x0 - mu : -s2 * rcp1(x0 + mu);
-        beta = -v0 * rcp1(mu);
-        iv0 = rcp1(v0);
-        sub = mu;
-      }
-      if (lane == 0) {
-        offd[k] = sub;
-        tau[k] = beta;
-      }
-      {
-        // with beta = 0 (nothing below the sub-diagonal) v = e_{k+1} and w = 0:
-        // the update below leaves A unchanged, so it runs without a branch
-        double vr[NL], pr[NL];
-        static_for<IK, NL>([&](auto II) {
-          constexpr int ii = RFI_CI(II);
-          const int gi = r + 8 * ii;
-          vr[ii] = gi > k + 1 ? X[gi] * iv0 : (gi == k + 1 ? 1.0 : 0.0);
-        });
+        // this lane row holds row k (= column k) of A, at local row IK: it
+        // forms the reflector of (x0, x_{k+2}, ...) onto (mu, 0, ...) with
+        // v0 = x0 - mu (without cancellation), beta = 2 v0^2 / (s2 + v0^2)
+        // = -v0 / mu, and publishes v (v_{k+1} = 1) and beta
+        double s2 = 0.0, x0 = 0.0;
         static_for<IK, NL>([&](auto JJ) {
           constexpr int jj = RFI_CI(JJ);
           const int gj = c + 8 * jj;
-          vc[jj] = gj > k + 1 ? vc[jj] * iv0 : (gj == k + 1 ? 1.0 : 0.0);
+          const double x = A[IK][jj];
+          s2 += gj > k + 1 ? x * x : 0.0;
+          x0 += gj == k + 1 ? x : 0.0;
         });
-        if (want_v1 && r == 0) {
-          static_for<IK, NL>([&](auto JJ) {
-            const int gj = c + 8 * RFI_CI(JJ);
-            if (gj < n) vst[k * NN + gj] = vc[RFI_CI(JJ)];
-          });
+        s2 = sum8(s2);
+        x0 = sum8(x0);   // one non-zero term: exact
+        double beta = 0.0, sub = x0, iv0 = 0.0;
+        if (s2 > 0.0) {
+          const double mu = sqrt(fma(x0, x0, s2));
+          const double v0 = x0 <= 0.0 ? x0 - mu : -s2 * rcp1(x0 + mu);
+          beta = -v0 * rcp1(mu);
+          iv0 = rcp1(v0);
+          sub = mu;
         }
-        // p = A v (unscaled) for this lane's rows
-        static_for<IK, NL>([&](auto II) {
-          constexpr int ii = RFI_CI(II);
-          double acc = 0.0;
-          static_for<IK, NL>([&](auto JJ) { acc = fma(A[ii][RFI_CI(JJ)], vc[RFI_CI(JJ)], acc); });
-          pr[ii] = sum8(acc);
-        });
-        if (c == 0) {
-          static_for<IK, NL>([&](auto II) { P[r + 8 * RFI_CI(II)] = pr[RFI_CI(II)]; });
-        }
-        __syncthreads();
-        double pv = 0.0;
-        static_for<IK, NL>([&](auto JJ) {
-          pv = fma(P[c + 8 * RFI_CI(JJ)], vc[RFI_CI(JJ)], pv);
-        });
-        pv = sum8(pv);
-        const double K = 0.5 * beta * beta * pv;
-        // w = beta p - K v; A -= v w^T + w v^T
-        static_for<IK, NL>([&](auto II) {
-          constexpr int ii = RFI_CI(II);
-          pr[ii] = beta * pr[ii] - K * vr[ii];
-        });
         static_for<IK, NL>([&](auto JJ) {
           constexpr int jj = RFI_CI(JJ);
-          const double wc = beta * P[c + 8 * jj] - K * vc[jj];
-          static_for<IK, NL>([&](auto II) {
-            constexpr int ii = RFI_CI(II);
-            A[ii][jj] = fma(-vr[ii], wc, fma(-pr[ii], vc[jj], A[ii][jj]));
-          });
+          const int gj = c + 8 * jj;
+          const double v = gj > k + 1 ? A[IK][jj] * iv0 : (gj == k + 1 ? 1.0 : 0.0);
+          X[gj] = v;
+          if (want_v1 && gj < n) vst[k * NN + gj] = v;
         });
+        if (c == 0) {
+          offd[k] = sub;
+          tau[k] = beta;
+        }
       }
+      __syncthreads();
+      // with beta = 0 (nothing below the sub-diagonal) v = e_{k+1} and w = 0:
+      // the update below leaves A unchanged, so it runs without a branch
+      const double beta = tau[k];
+      // p = A v (unscaled) for this lane's rows; v is read from LDS per column
+      double pr[NL];
+      static_for<IK, NL>([&](auto II) { pr[RFI_CI(II)] = 0.0; });
+      static_for<IK, NL>([&](auto JJ) {
+        constexpr int jj = RFI_CI(JJ);
+        const double vcj = X[c + 8 * jj];
+        static_for<IK, NL>([&](auto II) {
+          constexpr int ii = RFI_CI(II);
+          pr[ii] = fma(A[ii][jj], vcj, pr[ii]);
+        });
+      });
+      static_for<IK, NL>([&](auto II) { pr[RFI_CI(II)] = sum8(pr[RFI_CI(II)]); });
+      if (c == 0) {
+        static_for<IK, NL>([&](auto II) { P[r + 8 * RFI_CI(II)] = pr[RFI_CI(II)]; });
+      }
+      __syncthreads();
+      double pv = 0.0;
+      static_for<IK, NL>([&](auto JJ) {
+        pv = fma(P[c + 8 * RFI_CI(JJ)], X[c + 8 * RFI_CI(JJ)], pv);
+      });
+      pv = sum8(pv);
+      const double K = 0.5 * beta * beta * pv;
+      // w = beta p - K v; A -= v w^T + w v^T
+      double vr[NL];
+      static_for<IK, NL>([&](auto II) {
+        constexpr int ii = RFI_CI(II);
+        vr[ii] = X[r + 8 * ii];
+        pr[ii] = beta * pr[ii] - K * vr[ii];
+      });
+      static_for<IK, NL>([&](auto JJ) {
+        constexpr int jj = RFI_CI(JJ);
+        const double vcj = X[c + 8 * jj];
+        const double wcj = beta * P[c + 8 * jj] - K * vcj;
+        static_for<IK, NL>([&](auto II) {
+          constexpr int ii = RFI_CI(II);
+          A[ii][jj] = fma(-vr[ii], wcj, fma(-pr[ii], vcj, A[ii][jj]));
+        });
+      });
     }
     // diagonal entries of block IK are final
     if (r == c && r + 8 * IK < n) alpha[r + 8 * IK] = A[IK][IK];

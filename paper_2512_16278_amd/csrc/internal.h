@@ -24,7 +24,7 @@ struct CcmItem {
   int32_t* sum_xy;
   int32_t* count;
   int32_t nbeam, nchan, L, nsub;
-  int32_t nct, nh, wg0, pad;
+  int32_t nct, nh, wg0, layout;  // layout: as the sums engine's argument
 };
 // Launch choices of the MFMA sums engine (all 0 = defaults): tile = variant
 // index of the beam count's tile shapes (< ccm_tile_variants), stages = cap
@@ -50,7 +50,11 @@ hipError_t launch_ccm_batch(int nbeam_of_class, const CcmTune* t, const CcmItem*
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, int shared_cu, hipStream_t s,
-                           const CcmTune* t = nullptr);
+                           const CcmTune* t = nullptr, int layout = 0);
+// Sums layouts: 0 = the C ABI's rows (sum_x[b][cell], sum_xy[pair][cell]);
+// 1 = one record per cell, sum_x[cell * (nbeam + npair) + row] with rows b
+// then nbeam + pair (sum_xy unused): what a one-cell-per-wave consumer reads
+// with coalesced loads.
 hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, hipStream_t s);
@@ -66,6 +70,7 @@ struct EigArgs {
   float* v1;
   uint8_t* status;
   int64_t out_stride;  // cell stride of the eigvals / v1 rows (>= nsub * nchan)
+  int layout;          // sums layout (1: cell records; the tridiagonal solver only)
 };
 // FP32, nbeam <= 20; wg = lanes (cells) per workgroup: 64, 128 or 256
 hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg = 256);

@@ -141,15 +141,17 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
                               up(cells_cap * npair_of(pl.nbeam) * 4));
     // the slot is free once the eigen stage of its previous group has run
     if (g >= pl.nslot && (e = hipStreamWaitEvent(s, ev.eig[slot], 0)) != hipSuccess) return e;
+    // the per-wave tridiagonal solver reads one cell record per wave
+    const int layout = pl.eig.solver == RFI_EIG_TRIDIAG ? 1 : 0;
     e = launch_ccm_mfma(bp, pl.nbeam, pl.nchan, row_stride, t0 + (int64_t)k0 * L, L, ks, sx, sxy,
-                        cnt, 0, shared_tile(), s);
+                        cnt, 0, shared_tile(), s, nullptr, layout);
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ev.ccm[slot], s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(ev.aux, ev.ccm[slot], 0)) != hipSuccess) return e;
     const int64_t off = (int64_t)k0 * pl.nchan;
     EigArgs a{pl.nbeam, ks, pl.nchan, sx, sxy, cnt, pl.eig.max_sweeps, 1,
               eigvals ? eigvals + off : nullptr, stat + off, v1 ? v1 + off : nullptr,
-              status + off, out_stride};
+              status + off, out_stride, layout};
     e = launch_eig(a, pl.eig, ev.aux, lane_wg());
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ev.eig[slot], ev.aux)) != hipSuccess) return e;
