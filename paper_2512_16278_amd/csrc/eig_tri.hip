@@ -94,32 +94,37 @@ __device__ __forceinline__ double rcp1(double q) {
 }
 
 // Number of eigenvalues of the tridiagonal below x (Sturm count: negative
-// pivots of the LDL^T factorisation of T - x I), for two points at once.
-// ae[i] = (alpha_i, off_{i-1}^2), off_{-1} = 0. A pivot that is zero (or
-// nearly) is replaced by a tiny negative one, which keeps the count exact for
-// x on an eigenvalue of a leading block.
-__device__ __forceinline__ void sturm_below2(const double2* ae, int n, double x1, double x2,
-                                             int& c1, int& c2) {
+// pivots of the LDL^T factorisation of T - x I), for P points at once (P
+// independent recurrences per lane). ae[i] = (alpha_i, off_{i-1}^2),
+// off_{-1} = 0. A pivot that is zero (or nearly) is replaced by a tiny
+// negative one, which keeps the count exact for x on an eigenvalue of a
+// leading block.
+template <int P>
+__device__ __forceinline__ void sturm_below_p(const double2* ae, int n, const double (&x)[P],
+                                              int (&cnt)[P]) {
   constexpr double PIV = 1e-290;
-  double q1 = 1.0, q2 = 1.0;   // with off_{-1}^2 = 0 the first step is alpha_0 - x
-  int n1 = 0, n2 = 0;
+  double q[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    q[j] = 1.0;   // with off_{-1}^2 = 0 the first step is alpha_0 - x
+    cnt[j] = 0;
+  }
   for (int i = 0; i < n; ++i) {
     const double2 v = ae[i];
-    q1 = fma(-v.y, rcp1(q1), v.x - x1);
-    q2 = fma(-v.y, rcp1(q2), v.x - x2);
-    if (fabs(q1) < PIV) q1 = -PIV;
-    if (fabs(q2) < PIV) q2 = -PIV;
-    n1 += q1 < 0.0;
-    n2 += q2 < 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      q[j] = fma(-v.y, rcp1(q[j]), v.x - x[j]);
+      if (fabs(q[j]) < PIV) q[j] = -PIV;
+      cnt[j] += q[j] < 0.0;
+    }
   }
-  c1 = n1;
-  c2 = n2;
 }
 
 __device__ __forceinline__ int sturm_below(const double2* ae, int n, double x) {
-  int c1, c2;
-  sturm_below2(ae, n, x, x, c1, c2);
-  return c1;
+  const double xs[1] = {x};
+  int c[1];
+  sturm_below_p<1>(ae, n, xs, c);
+  return c[0];
 }
 
 // Inverse iteration for the eigenvector of the tridiagonal (alpha, off)
@@ -387,18 +392,29 @@ __global__ __launch_bounds__(64, NL <= 9 ? 2 : 1) void eig_tri_kernel(EigArgs g,
 
   // lambda_1 = the largest eigenvalue: multisection. The bracket [lo, hi]
   // always holds exactly one crossing of count n-1 -> n (count(lo) <= n-1,
-  // count(hi) = n); lane l tests the points l + 1 and l + 65 of the 129
-  // equal parts of the bracket.
+  // count(hi) = n); lane l tests the points l + 1 + 64 j (j < NP) of the
+  // 64 NP + 1 equal parts of the bracket. One point per lane: the counts are
+  // issue-bound, so more points per pass cost more than the passes they save.
+  // The bracket stops at 2e-14 relative width, the order of the backward
+  // error of the FP64 reduction itself.
+  constexpr int NP = 1;
   double lo = fmax(glo, lb - 1e-12 * span), hi = ghi;
-  for (int it = 0; it < 12 && hi - lo > 4e-16 * fmax(fabs(hi), 1.0); ++it) {
-    const double h = (hi - lo) * (1.0 / 129.0);
-    int c1, c2;
-    sturm_below2(ae, n, lo + (lane + 1) * h, lo + (lane + 65) * h, c1, c2);
+  for (int it = 0; it < 16 && hi - lo > 2e-14 * fmax(fabs(hi), 1.0); ++it) {
+    const double h = (hi - lo) * (1.0 / (64 * NP + 1));
+    double xs[NP];
+    int cn[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) xs[j] = lo + (lane + 1 + 64 * j) * h;
+    sturm_below_p<NP>(ae, n, xs, cn);
     // the first point with all n eigenvalues below it
-    const unsigned long long b1 = __ballot(c1 >= n), b2 = __ballot(c2 >= n);
-    const int first = b1 ? __builtin_ctzll(b1) + 1 : (b2 ? __builtin_ctzll(b2) + 65 : 129);
+    int first = 64 * NP + 1;
+#pragma unroll
+    for (int j = NP - 1; j >= 0; --j) {
+      const unsigned long long bj = __ballot(cn[j] >= n);
+      if (bj) first = __builtin_ctzll(bj) + 1 + 64 * j;
+    }
     const double nlo = lo + (first - 1) * h;
-    const double nhi = first == 129 ? hi : lo + first * h;
+    const double nhi = first == 64 * NP + 1 ? hi : lo + first * h;
     lo = nlo;
     hi = nhi;
   }
