@@ -76,10 +76,11 @@ MIX_L = (512, 1024, 4096)
 
 def precision_split(dev, spec, data, blk, nsub, ev_time):
     """Precision split on the FAST-shaped block: exact int32 sums by the int8
-    MFMA engine vs the dot4 VALU engine (bit-exact, timed); FP32 Jacobi vs
-    FP64 Jacobi on the GPU (timed), each against the FP64 oracle on sampled
-    cells (per-cell eigenvalue error, residual of the dominant pair), and the
-    mask disagreement of the two precisions over every cell."""
+    MFMA engine vs the dot4 VALU engine (bit-exact, timed); FP32 Jacobi, FP32
+    Householder + Sturm and FP64 Jacobi on the GPU (timed), each against the
+    FP64 oracle on sampled cells (per-cell eigenvalue error, residual of the
+    dominant pair), and statistic and mask differences from the FP64 Jacobi
+    over every cell."""
     import torch
     from oracle import pipeline
     from paper_2512_16278_amd import rfi, synth
@@ -99,26 +100,31 @@ def precision_split(dev, spec, data, blk, nsub, ev_time):
                  torch.equal(sums["mfma"][1], sums["valu"][1]))
     del sums["valu"]
     sx, sxy, cnt = sums["mfma"]
+    # (name, precision, solver): the FP32 per-lane Jacobi, the FP32 per-lane
+    # Householder + Sturm solver (the default below 21 beams), the FP64 Jacobi
+    runs = (("fp32", 32, rfi.RFI_EIG_LANE), ("fp32_householder", 32, rfi.RFI_EIG_LANE_TRI),
+            ("fp64", 64, rfi.RFI_EIG_WAVE))
     res = {}
-    for prec in (32, 64):
+    for name, prec, solver in runs:
         stat = torch.empty(ncell, dtype=torch.float64, device=dev)
         status = torch.empty(ncell, dtype=torch.uint8, device=dev)
         ev = torch.empty((nb, ncell), dtype=torch.float32, device=dev)
         v1 = torch.empty((nb, ncell), dtype=torch.float32, device=dev)
         mask = torch.empty(ncell, dtype=torch.uint8, device=dev)
-        times[f"eig_fp{prec}_ms"] = ev_time(lambda: rfi.rfi_eig_batched(
-            nb, nsub, nc, sx, sxy, cnt, stat, status, eigvals=ev, v1=v1, precision=prec))
-        times[f"eig_fp{prec}_stat_only_ms"] = ev_time(lambda: rfi.rfi_eig_batched(
-            nb, nsub, nc, sx, sxy, cnt, stat, status, precision=prec))
+        times[f"eig_{name}_ms"] = ev_time(lambda: rfi.rfi_eig_batched(
+            nb, nsub, nc, sx, sxy, cnt, stat, status, eigvals=ev, v1=v1, precision=prec,
+            solver=solver))
+        times[f"eig_{name}_stat_only_ms"] = ev_time(lambda: rfi.rfi_eig_batched(
+            nb, nsub, nc, sx, sxy, cnt, stat, status, precision=prec, solver=solver))
         rfi.rfi_eig_batched(nb, nsub, nc, sx, sxy, cnt, stat, status, eigvals=ev, v1=v1,
-                            precision=prec)
+                            precision=prec, solver=solver)
         rfi.rfi_flag(nsub, nc, stat, status, mask)
         torch.cuda.synchronize()
-        res[prec] = dict(stat=stat.cpu().numpy().reshape(nsub, nc),
+        res[name] = dict(stat=stat.cpu().numpy().reshape(nsub, nc),
                          ev=ev.cpu().numpy().reshape(nb, nsub, nc),
                          v1=v1.cpu().numpy().reshape(nb, nsub, nc),
                          status=status.cpu().numpy(), mask=mask.cpu().numpy())
-    mask_diff = int(np.count_nonzero(res[32]["mask"] != res[64]["mask"]))
+    mask_diff = int(np.count_nonzero(res["fp32"]["mask"] != res["fp64"]["mask"]))
     # sampled cells against the oracle
     k, c_hi = 0, 256
     x = synth.generate(spec, k * L, (k + 1) * L, 0, c_hi)
@@ -127,18 +133,21 @@ def precision_split(dev, spec, data, blk, nsub, ev_time):
     r_ref = cr.r[0]                                  # [c, n, n]
     out = {"sums_bit_exact_mfma_vs_valu": exact, "mask_disagreements_fp32_vs_fp64": mask_diff,
            "cells": ncell, "sample": f"sub-interval {k}, channels 0..{c_hi - 1} ({c_hi} cells)"}
-    for prec in (32, 64):
-        ev = res[prec]["ev"][:, k, :c_hi].T.astype(np.float64)       # [c, n]
-        v = res[prec]["v1"][:, k, :c_hi].T.astype(np.float64)
+    for name, prec, solver in runs:
+        ev = res[name]["ev"][:, k, :c_hi].T.astype(np.float64)       # [c, n]
+        v = res[name]["v1"][:, k, :c_hi].T.astype(np.float64)
         lam1 = w_ref[:, :1]
         nrel = np.abs(ev - w_ref) / np.abs(lam1)
         erel = np.abs(ev - w_ref) / np.abs(w_ref)
-        s_err = np.abs(res[prec]["stat"][k, :c_hi] - cr.stat[0])
+        s_err = np.abs(res[name]["stat"][k, :c_hi] - cr.stat[0])
         resid = np.linalg.norm(np.einsum("cab,cb->ca", r_ref, v) - ev[:, :1] * v, axis=1)
-        out[f"fp{prec}"] = {
+        out[name] = {
             "eig_norm_rel_max": float(nrel.max()), "eig_elem_rel_max": float(erel.max()),
             "stat_abs_max": float(s_err.max()), "resid_max": float(resid.max()),
-            "not_converged": int(np.count_nonzero(res[prec]["status"] & rfi.RFI_CELL_NOT_CONVERGED)),
+            "not_converged": int(np.count_nonzero(res[name]["status"] & rfi.RFI_CELL_NOT_CONVERGED)),
+            # over every cell of the block, against the FP64 Jacobi
+            "stat_vs_fp64_all_cells_max": float(np.abs(res[name]["stat"] - res["fp64"]["stat"]).max()),
+            "mask_vs_fp64_all_cells": int(np.count_nonzero(res[name]["mask"] != res["fp64"]["mask"])),
         }
     out.update({k2: round(v2, 4) for k2, v2 in times.items()})
     return out
@@ -575,7 +584,8 @@ def main():
                                f"(10 s at 49.152 us), L={L}, {nsub} sub-ints, "
                                f"{nbytes_in / 1e9:.2f} GB", "nbeam": nb, "nchan": nc,
                    "L": L, "nsub": nsub, "path": args.path, "ccm": args.variant,
-                   "jacobi": f"fp{args.precision}"},
+                   "eigen": ("fp32 householder+sturm, fp64 refinement" if args.precision == 32
+                             else "fp64 jacobi")},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
         "stages_ms": {"path": "three calls", "ccm": round(float(ms_ccm), 4),

@@ -105,26 +105,38 @@ rfi_status rfi_ccm_accumulate(const rfi_block* blk /* host */, int64_t t0, int32
  *                  bisection (Golub & Van Loan Sec. 8.3-8.4), FP64, one cell per
  *                  wavefront with the matrix in registers, any nbeam: about
  *                  (4/3) n^3 flops per cell instead of 6 n^3 per Jacobi sweep.
- *  RFI_EIG_AUTO    LANE for FP32 and nbeam <= 20, TRIDIAG for FP32 and more
- *                  beams, WAVE for FP64 (FP64 Jacobi). */
-enum { RFI_EIG_AUTO = 0, RFI_EIG_LANE = 1, RFI_EIG_WAVE = 2, RFI_EIG_TRIDIAG = 3 };
+ *  RFI_EIG_LANE_TRI Householder reduction and Sturm bisection in FP32, one
+ *                  cell per lane in registers, nbeam <= 20 (about (4/3) n^3 flops
+ *                  instead of the Jacobi's 6 n^3 per sweep); lambda_1 refined in
+ *                  FP64 as for LANE.
+ *  RFI_EIG_AUTO    LANE_TRI for FP32 and nbeam <= 20, TRIDIAG for FP32 and
+ *                  more beams, WAVE for FP64 (FP64 Jacobi).
+ * The per-lane solvers refine lambda_1 in FP64 by two-vector block inverse
+ * iteration on the FP32 matrix and the Ritz value of the FP64 matrix on that
+ * subspace (exact to FP64 rounding also when lambda_2 is close to lambda_1). */
+enum {
+  RFI_EIG_AUTO = 0, RFI_EIG_LANE = 1, RFI_EIG_WAVE = 2, RFI_EIG_TRIDIAG = 3,
+  RFI_EIG_LANE_TRI = 4
+};
 
 typedef struct {
   int32_t precision;     /* 32: FP32 Jacobi (default); 64: FP64 Jacobi */
   int32_t max_sweeps;    /* cyclic Jacobi sweep cap, 1..30 (default 12) */
-  int32_t refine;        /* 1: lambda_1 by an FP64 Rayleigh quotient (default) */
-  int32_t solver;        /* RFI_EIG_AUTO | _LANE (nbeam <= 20, FP32) | _WAVE | _TRIDIAG */
+  int32_t refine;        /* 1: lambda_1 refined in FP64 (default) */
+  int32_t solver;        /* RFI_EIG_AUTO | _LANE, _LANE_TRI (nbeam <= 20, FP32) | _WAVE |
+                            _TRIDIAG */
 } rfi_eig_params;
 
 /* Per cell (Sec. 3.2-3.3): the Pearson correlation matrix
  *     r_ab = N_ab / sqrt(N_aa N_bb),  N_ab = count * S_ab - S_a S_b
  * (N exact in int64, r in FP64; a beam with N_aa = 0 gets r_ab = 0 off the
- * diagonal and the cell RFI_CELL_DEGENERATE), its eigenvalues by cyclic
- * Jacobi (eps-relative skip rule, stop after a sweep without rotations or
- * max_sweeps), and
+ * diagonal and the cell RFI_CELL_DEGENERATE), its eigenvalues by the
+ * selected solver (Jacobi: eps-relative skip rule, stop after a sweep without
+ * rotations or max_sweeps), and
  *     stat[cell] = lambda_1^2 / ||r||_F^2         (FP64)
- * with lambda_1 the eigenvalue of largest magnitude, refined in FP64 by the
- * Rayleigh quotient of its eigenvector when p->refine. Optional outputs
+ * with lambda_1 the eigenvalue of largest magnitude, refined in FP64 when
+ * p->refine (FP32 solvers: Ritz value of the FP64 matrix on two vectors of
+ * block inverse iteration; FP64 solvers need none). Optional outputs
  * (NULL = not computed): eigvals[i][cell] (FP32, |lambda| descending) and
  * v1[b][cell] (FP32 unit dominant eigenvector, sign: sum_b v1_b >= 0).
  * status[cell] gets RFI_CELL_* bits. Inputs are the outputs of
@@ -281,8 +293,8 @@ typedef struct {
  *  ccm_stages      cap of the global-to-LDS load ring depth, 2..4;
  *  ccm_group_bytes contiguous row bytes of the tiles one XCD takes in turn
  *                  (16 .. 16384; default 1024);
- *  eig_solver      RFI_EIG_* for the class (AUTO: the default rule; LANE
- *                  needs FP32 and nbeam <= 20);
+ *  eig_solver      RFI_EIG_* for the class (AUTO: the default rule; LANE and
+ *                  LANE_TRI need FP32 and nbeam <= 20);
  *  eig_wg          cells per workgroup of the per-lane solver: 64, 128, 256.
  * ms_default / ms_tuned: class time (sums + eigen launches, ms) with the
  * defaults and with the entry's choices, as measured by rfi_tune_batch. */

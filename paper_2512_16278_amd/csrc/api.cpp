@@ -73,10 +73,12 @@ rfi_status resolve_eig(int nbeam, const rfi_eig_params* p, rfi_eig_params* out,
     return fail(RFI_E_INVALID, "%s: max_sweeps %d outside 1..30", who, prm.max_sweeps);
   if (prm.solver == RFI_EIG_AUTO)
     prm.solver = prm.precision == 64 ? RFI_EIG_WAVE
-                                     : (nbeam <= 20 ? RFI_EIG_LANE : RFI_EIG_TRIDIAG);
-  if (prm.solver == RFI_EIG_LANE && (prm.precision != 32 || nbeam > 20))
-    return fail(RFI_E_INVALID, "%s: the per-lane solver is FP32 and nbeam <= 20", who);
-  if (prm.solver != RFI_EIG_LANE && prm.solver != RFI_EIG_WAVE && prm.solver != RFI_EIG_TRIDIAG)
+                                     : (nbeam <= 20 ? RFI_EIG_LANE_TRI : RFI_EIG_TRIDIAG);
+  if ((prm.solver == RFI_EIG_LANE || prm.solver == RFI_EIG_LANE_TRI) &&
+      (prm.precision != 32 || nbeam > 20))
+    return fail(RFI_E_INVALID, "%s: the per-lane solvers are FP32 and nbeam <= 20", who);
+  if (prm.solver != RFI_EIG_LANE && prm.solver != RFI_EIG_WAVE &&
+      prm.solver != RFI_EIG_TRIDIAG && prm.solver != RFI_EIG_LANE_TRI)
     return fail(RFI_E_INVALID, "%s: unknown solver %d", who, prm.solver);
   *out = prm;
   return RFI_OK;
@@ -85,6 +87,7 @@ rfi_status resolve_eig(int nbeam, const rfi_eig_params* p, rfi_eig_params* out,
 hipError_t launch_eig(const EigArgs& a, const rfi_eig_params& p, hipStream_t s, int lane_wg) {
   switch (p.solver) {
     case RFI_EIG_LANE: return launch_eig_lane(a, s, lane_wg);
+    case RFI_EIG_LANE_TRI: return launch_eig_lane(a, s, lane_wg, true);
     case RFI_EIG_TRIDIAG: return launch_eig_tri(a, s);
     default: return launch_eig_wave(a, p.precision, s);
   }

@@ -121,7 +121,8 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
       return fail(RFI_E_INVALID, "%s: item %d: no sums instance for %d beams", who, i, ip.nbeam);
     ip.solver = res.solver;
     ip.precision = res.precision;
-    ip.lane_cls = res.solver == RFI_EIG_LANE      ? eig_lane_class(ip.nbeam)
+    const bool lane = res.solver == RFI_EIG_LANE || res.solver == RFI_EIG_LANE_TRI;
+    ip.lane_cls = lane                            ? eig_lane_class(ip.nbeam)
                   : res.solver == RFI_EIG_TRIDIAG ? eig_tri_class(ip.nbeam)
                                                   : 0;
     ip.wg = te && te->eig_wg ? te->eig_wg : 256;
@@ -138,7 +139,8 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
   for (int k = 0; k < n; ++k) {
     const ItemPlan& ip = bpn->plans[k];
     ccm[ip.cc.key].push_back(k);
-    eig[{ip.lane_cls, ip.solver, ip.precision, ip.solver == RFI_EIG_LANE ? ip.wg : 0}].push_back(k);
+    const bool lane = ip.solver == RFI_EIG_LANE || ip.solver == RFI_EIG_LANE_TRI;
+    eig[{ip.lane_cls, ip.solver, ip.precision, lane ? ip.wg : 0}].push_back(k);
   }
   for (auto& kv : ccm)
     bpn->ccm_classes.push_back({bpn->plans[kv.second[0]].nbeam, bpn->plans[kv.second[0]].ct,
@@ -276,8 +278,9 @@ hipError_t enqueue_eig(const BatchPlan& bpn, const void* desc, char* ws, hipStre
     const int m = (int)ec.items.size();
     const int64_t total = hc0[cpos + m];
     hipError_t e;
-    if (ec.solver == RFI_EIG_LANE)
-      e = launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s, ec.wg);
+    if (ec.solver == RFI_EIG_LANE || ec.solver == RFI_EIG_LANE_TRI)
+      e = launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s, ec.wg,
+                                ec.solver == RFI_EIG_LANE_TRI);
     else if (ec.solver == RFI_EIG_TRIDIAG)
       e = launch_eig_tri_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s);
     else
@@ -474,12 +477,14 @@ rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items, const rfi_
     float best_eig = eig_def;
     std::vector<std::pair<int, int>> cands;  // (solver, wg)
     if (precision == 32 && max_nbeam[sc] <= 20) {
-      cands = {{RFI_EIG_LANE, 256}, {RFI_EIG_LANE, 128}, {RFI_EIG_LANE, 64}, {RFI_EIG_TRIDIAG, 0}};
+      cands = {{RFI_EIG_LANE, 256},     {RFI_EIG_LANE, 128},     {RFI_EIG_LANE, 64},
+               {RFI_EIG_LANE_TRI, 256}, {RFI_EIG_LANE_TRI, 128}, {RFI_EIG_LANE_TRI, 64},
+               {RFI_EIG_TRIDIAG, 0}};
     } else {
       cands = {{RFI_EIG_TRIDIAG, 0}, {RFI_EIG_WAVE, 0}};
     }
     const int def_solver = precision == 64 ? RFI_EIG_WAVE
-                           : (max_nbeam[sc] <= 20 ? RFI_EIG_LANE : RFI_EIG_TRIDIAG);
+                           : (max_nbeam[sc] <= 20 ? RFI_EIG_LANE_TRI : RFI_EIG_TRIDIAG);
     for (auto& c : cands) {
       if (c.first == def_solver && (c.second == 0 || c.second == 256)) continue;  // measured
       rfi_tune_entry e = best;

@@ -5,18 +5,24 @@
 //
 // Each lane holds its cell's symmetric matrix (packed upper triangle, N(N+1)/2
 // floats) entirely in registers; every index is a compile-time constant, so
-// the cyclic-by-row Jacobi sweep (Golub & Van Loan, Sec. 8.5) is straight-line
-// FP32 code with no LDS traffic and no cross-lane communication. Rotations
-// whose |a_pq| <= eps sqrt(|a_pp a_qq|) (eps = 2^-23) are skipped (relative
-// criterion of Demmel & Veselic); a lane stops after a sweep without rotations
-// or after max_sweeps.
+// the solvers are straight-line FP32 code with no LDS traffic and no
+// cross-lane communication. Two solvers for the first kernel:
+//  - cyclic-by-row Jacobi (Golub & Van Loan, Sec. 8.5). Rotations whose
+//    |a_pq| <= eps sqrt(|a_pp a_qq|) (eps = 2^-23) are skipped (relative
+//    criterion of Demmel & Veselic); a lane stops after a sweep without
+//    rotations or after max_sweeps;
+//  - Householder reduction to tridiagonal form (Sec. 8.3) and Sturm
+//    bisection (Sec. 8.4): about (4/3) n^3 flops instead of 6 n^3 per sweep.
 //
 // The dominant eigenvalue is then refined in FP64, since the clip compares the
-// statistic against a threshold at FP64 resolution: the eigenvector v1 comes
-// from inverse iteration with an FP32 Cholesky factor of (sigma I - C),
-// sigma just above the FP32 lambda_1, and lambda_1 is replaced by the FP64
-// Rayleigh quotient v1^T C v1 / v1^T v1 on the FP64 correlation matrix (error
-// of order ||dC||^2 / gap for an FP32 v1).
+// statistic against a threshold at FP64 resolution: two vectors of block
+// inverse iteration with an FP32 Cholesky factor of (sigma I - C), sigma just
+// above the FP32 lambda_1, span (nearly) the eigenvectors of lambda_1 and
+// lambda_2; lambda_1 is replaced by the largest Ritz value of the FP64
+// correlation matrix on that span. The subspace converges at the rate
+// (sigma - lambda_2) / (sigma - lambda_3), so a lambda_2 within the shift
+// distance of lambda_1 (where one vector of inverse iteration would stall and
+// its Rayleigh quotient miss lambda_1 by up to the gap) costs nothing.
 #include <float.h>
 #include <math.h>
 
@@ -192,7 +198,168 @@ __device__ __forceinline__ void jacobi_cell(const EigArgs& g, int64_t cell) {
   }
 }
 
-// Kernel 2: eigenvector by inverse iteration and FP64 Rayleigh quotient;
+// Sturm count of the lane's tridiagonal below x (FP32: negative pivots of the
+// LDL^T factorisation of T - x I; a zero pivot counts as negative). Only the
+// first n entries take part (the padding of a smaller beam count is a
+// decoupled identity block).
+template <int N>
+__device__ __forceinline__ int lane_sturm(const float (&dg)[N], const float (&e2)[N], int n,
+                                          float x) {
+  float q = 1.0f;
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    float t = fmaf(-e2[i], __builtin_amdgcn_rcpf(q), dg[i] - x);
+    if (fabsf(t) < 1e-30f) t = -1e-30f;
+    if (i < n) {
+      q = t;
+      c += t < 0.f;
+    }
+  }
+  return c;
+}
+
+// Kernel 1, alternative: Householder reduction of the FP32 correlation matrix
+// to tridiagonal form in the lane's registers (Golub & Van Loan Sec. 8.3:
+// about (4/3) n^3 flops instead of 6 n^3 per Jacobi sweep), then lambda_1 by
+// Sturm bisection on the tridiagonal (Sec. 8.4). Same outputs as the Jacobi
+// kernel: the FP32 dominant eigenvalue in stat[] (the shift of kernel 2,
+// which needs it to about 1e-5), optional sorted eigenvalues (one bisection
+// each), status bits.
+template <int N>
+__device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
+  const int64_t ncell = (int64_t)g.nsub * g.nchan;
+  const int n = g.nbeam;
+  const int64_t cnt = g.count[cell / g.nchan];
+  if (cnt < 2 || cnt > RFI_MAX_COUNT) {
+    g.stat[cell] = 1.0;
+    g.status[cell] = RFI_CELL_BAD_COUNT | RFI_CELL_DEGENERATE;
+    if (g.eigvals)
+      for (int i = 0; i < n; ++i) g.eigvals[i * g.out_stride + cell] = 0.f;
+    return;
+  }
+  float A[Sym<N>::NP];
+  bool degenerate;
+  load_corr32<N>(g, ncell, cell, n, cnt, A, degenerate);
+
+  // dg: diagonal of T; e2[i]: squared coupling of i - 1 and i (e2[0] = 0)
+  float dg[N], e2[N];
+  e2[0] = 0.f;
+  static_for<0, N - 2>([&](auto K) {
+    constexpr int k = RFI_CI(K);
+    // reflector of (x0, x_{k+2}, ...) onto (mu, 0, ...): v0 = x0 - mu without
+    // cancellation, beta = 2 v0^2 / (s2 + v0^2) = -v0 / mu; nothing to do
+    // (beta = 0, v = e_{k+1}) when the column is already reduced
+    float s2 = 0.f;
+    static_for<k + 2, N>([&](auto I) {
+      const float x = A[Sym<N>::idx(RFI_CI(I), k)];
+      s2 = fmaf(x, x, s2);
+    });
+    const float x0 = A[Sym<N>::idx(k + 1, k)];
+    const float mu2 = fmaf(x0, x0, s2);
+    const float mu = sqrtf(mu2);
+    const bool refl = s2 > 0.f;
+    const float v0 = x0 <= 0.f ? x0 - mu : -s2 / (x0 + mu);
+    const float beta = refl ? -v0 / mu : 0.f;
+    const float iv0 = refl ? 1.0f / v0 : 0.f;
+    dg[k] = A[Sym<N>::idx(k, k)];
+    e2[k + 1] = mu2;
+    float v[N], w[N];
+    static_for<k + 1, N>([&](auto I) {
+      constexpr int i = RFI_CI(I);
+      v[i] = i == k + 1 ? 1.0f : A[Sym<N>::idx(i, k)] * iv0;
+    });
+    // p = beta A22 v, K = beta p.v / 2, w = p - K v
+    float pv = 0.f;
+    static_for<k + 1, N>([&](auto I) {
+      constexpr int i = RFI_CI(I);
+      float acc = 0.f;
+      static_for<k + 1, N>([&](auto J) {
+        constexpr int j = RFI_CI(J);
+        acc = fmaf(A[Sym<N>::idx(i, j)], v[j], acc);
+      });
+      w[i] = beta * acc;
+      pv = fmaf(w[i], v[i], pv);
+    });
+    const float Kf = 0.5f * beta * pv;
+    static_for<k + 1, N>([&](auto I) {
+      constexpr int i = RFI_CI(I);
+      w[i] = fmaf(-Kf, v[i], w[i]);
+    });
+    // A22 -= v w^T + w v^T (upper triangle)
+    static_for<k + 1, N>([&](auto I) {
+      constexpr int i = RFI_CI(I);
+      static_for<i, N>([&](auto J) {
+        constexpr int j = RFI_CI(J);
+        A[Sym<N>::idx(i, j)] =
+            fmaf(-v[i], w[j], fmaf(-w[i], v[j], A[Sym<N>::idx(i, j)]));
+      });
+    });
+  });
+  dg[N - 2] = A[Sym<N>::idx(N - 2, N - 2)];
+  dg[N - 1] = A[Sym<N>::idx(N - 1, N - 1)];
+  {
+    const float x = A[Sym<N>::idx(N - 1, N - 2)];
+    e2[N - 1] = x * x;
+  }
+
+  // Gershgorin bracket of T; lambda_1 (the largest: a correlation matrix is
+  // positive semidefinite) is at least every diagonal entry
+  float glo = 3.0e38f, ghi = -3.0e38f, dmax = -3.0e38f;
+  static_for<0, N>([&](auto I) {
+    constexpr int i = RFI_CI(I);
+    if (i < n) {
+      const float rad = sqrtf(e2[i]) + (i + 1 < N ? sqrtf(e2[(i + 1) % N]) : 0.f);
+      glo = fminf(glo, dg[i] - rad);
+      ghi = fmaxf(ghi, dg[i] + rad);
+      dmax = fmaxf(dmax, dg[i]);
+    }
+  });
+  // padding of a smaller beam count is decoupled only below n - 1
+  const float span = fmaxf(ghi - glo, 1e-30f);
+  glo -= 1e-6f * span;
+  ghi += 1e-6f * span;
+  float lo = fmaxf(glo, dmax - 1e-6f * span), hi = ghi;
+  for (int it = 0; it < 26; ++it) {
+    const float mid = 0.5f * (lo + hi);
+    if (lane_sturm<N>(dg, e2, n, mid) >= n) hi = mid; else lo = mid;
+  }
+  const float lam1 = 0.5f * (lo + hi);
+  g.stat[cell] = (double)lam1;
+  g.status[cell] = degenerate ? RFI_CELL_DEGENERATE : 0;
+
+  if (g.eigvals) {
+    // eigenvalue j (ascending) by bisection, then |lambda| descending
+    float ev[N], key[N];
+    static_for<0, N>([&](auto J) {
+      constexpr int j = RFI_CI(J);
+      float a = glo, b = ghi;
+      if (j < n) {
+        for (int it = 0; it < 28; ++it) {
+          const float mid = 0.5f * (a + b);
+          if (lane_sturm<N>(dg, e2, n, mid) > j) b = mid; else a = mid;
+        }
+      }
+      ev[j] = 0.5f * (a + b);
+      key[j] = j < n ? fabsf(ev[j]) : -1.0f;
+    });
+#pragma unroll
+    for (int pass = 0; pass < N; ++pass) {
+#pragma unroll
+      for (int i = pass & 1; i + 1 < N; i += 2) {
+        const bool sw = key[i + 1] > key[i];
+        const float k0 = sw ? key[i + 1] : key[i], k1 = sw ? key[i] : key[i + 1];
+        const float e0 = sw ? ev[i + 1] : ev[i], e1 = sw ? ev[i] : ev[i + 1];
+        key[i] = k0; key[i + 1] = k1; ev[i] = e0; ev[i + 1] = e1;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (i < n) g.eigvals[i * g.out_stride + cell] = ev[i];
+  }
+}
+
+// Kernel 2: block inverse iteration and the FP64 Ritz value of lambda_1;
 // writes the statistic lambda_1^2 / ||C||_F^2, v1 and the remaining status bits.
 template <int N>
 __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
@@ -208,7 +375,11 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
   }
   const float lam1 = (float)g.stat[cell];
 
-  float v[N];
+  // Two vectors of block inverse iteration (v, u): the subspace converges to
+  // that of lambda_1 and lambda_2 at the rate (sigma - lambda_2) /
+  // (sigma - lambda_3), so the Ritz value below is exact to FP64 rounding
+  // even when lambda_2 is within the shift distance of lambda_1.
+  float v[N], u[N];
   bool have_v = false;
   if (g.refine || g.v1) {
     float A[Sym<N>::NP];
@@ -216,7 +387,6 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
     load_corr32<N>(g, ncell, cell, n, cnt, A, dg);
     const float sigma = lam1 * (1.0f + 2e-5f) + 1e-6f;
     bool ok = true;
-    float rinv[N];
     static_for<0, N>([&](auto J) {
       constexpr int j = RFI_CI(J);
       // column j of the factor R (B = R R^T, R lower), B = sigma I - C
@@ -226,7 +396,9 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
         d -= A[Sym<N>::idx(j, k)] * A[Sym<N>::idx(j, k)];
       });
       ok = ok && d > 0.f;
-      rinv[j] = 1.0f / sqrtf(fmaxf(d, 1e-30f));
+      // the diagonal of B is not read again: it keeps 1 / R_jj
+      const float rj = 1.0f / sqrtf(fmaxf(d, 1e-30f));
+      A[Sym<N>::idx(j, j)] = rj;
       static_for<j + 1, N>([&](auto I) {
         constexpr int i = RFI_CI(I);
         float x = -A[Sym<N>::idx(i, j)];
@@ -234,86 +406,163 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
           constexpr int k = RFI_CI(K);
           x -= A[Sym<N>::idx(i, k)] * A[Sym<N>::idx(j, k)];
         });
-        A[Sym<N>::idx(i, j)] = x * rinv[j];
+        A[Sym<N>::idx(i, j)] = x * rj;
       });
     });
-    // start vector with no exact linear relation to any eigenvector that a
+    // start vectors with no exact linear relation to any eigenvector that a
     // correlation matrix can have (all-ones is orthogonal to (1, -1) for two
-    // anticorrelated beams): components 0.5 + frac(0.5 + i g), g = 0.7548...
+    // anticorrelated beams): components 0.5 + frac(0.5 + i g), g = 0.7548...,
+    // and frac(0.5 + i h) - 0.5, h = 0.3819... (mixed signs)
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const float f = 0.5f + 0.7548776662466927f * (float)i;
+      const float h = 0.5f + 0.3819660112501051f * (float)i;
       v[i] = i < n ? 0.5f + (f - floorf(f)) : 0.0f;
+      u[i] = i < n ? (h - floorf(h)) - 0.5f : 0.0f;
     }
     for (int it = 0; it < 3; ++it) {
-      // R y = v (forward), then R^T w = y (backward), in place
+      // R y = x (forward), then R^T z = y (backward), in place, for x = v, u
       static_for<0, N>([&](auto I) {
         constexpr int i = RFI_CI(I);
-        float x = v[i];
+        float x = v[i], y = u[i];
         static_for<0, i>([&](auto K) {
           constexpr int k = RFI_CI(K);
           x -= A[Sym<N>::idx(i, k)] * v[k];
+          y -= A[Sym<N>::idx(i, k)] * u[k];
         });
-        v[i] = x * rinv[i];
+        v[i] = x * A[Sym<N>::idx(i, i)];
+        u[i] = y * A[Sym<N>::idx(i, i)];
       });
       static_for<0, N>([&](auto II) {
         constexpr int i = N - 1 - RFI_CI(II);
-        float x = v[i];
+        float x = v[i], y = u[i];
         static_for<i + 1, N>([&](auto K) {
           constexpr int k = RFI_CI(K);
           x -= A[Sym<N>::idx(k, i)] * v[k];
+          y -= A[Sym<N>::idx(k, i)] * u[k];
         });
-        v[i] = x * rinv[i];
+        v[i] = x * A[Sym<N>::idx(i, i)];
+        u[i] = y * A[Sym<N>::idx(i, i)];
       });
-      float nrm = 0.f;
+      // orthonormalise: v unit, u unit and orthogonal to v
+      float nv = 0.f;
 #pragma unroll
-      for (int i = 0; i < N; ++i) nrm += v[i] * v[i];
-      const float sc = 1.0f / sqrtf(nrm);
+      for (int i = 0; i < N; ++i) nv += v[i] * v[i];
+      const float sv = 1.0f / sqrtf(nv);
+      float vu = 0.f;
 #pragma unroll
-      for (int i = 0; i < N; ++i) v[i] *= sc;
+      for (int i = 0; i < N; ++i) {
+        v[i] *= sv;
+        vu += v[i] * u[i];
+      }
+      float nu = 0.f;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        u[i] -= vu * v[i];
+        nu += u[i] * u[i];
+      }
+      const float su = nu > 0.f ? 1.0f / sqrtf(nu) : 0.f;
+#pragma unroll
+      for (int i = 0; i < N; ++i) u[i] *= su;
     }
     have_v = ok;
     if (!ok) st |= RFI_CELL_REFINE_FAILED;
   }
 
-  // FP64 pass over the exact sums: ||C||_F^2 and the Rayleigh quotient
-  double num = 0.0, vv = 0.0, f2 = 0.0;
+  // FP64 pass over the exact sums: ||C||_F^2 and the projections of C on
+  // span(v, u): H = [v u]^T C [v u] and the Gram matrix of (v, u)
+  double f2 = 0.0, h11 = 0.0, h12 = 0.0, h22 = 0.0, gvv = 0.0, gvu = 0.0, guu = 0.0;
   {
     int32_t S[N];
-    double d[N];
-    double vd[N];
+    double d[N], vd[N], ud[N];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       S[a] = 0;
       d[a] = 0.0;
       vd[a] = have_v ? (double)v[a] : 0.0;
+      ud[a] = have_v ? (double)u[a] : 0.0;
       if (a < n) {
         S[a] = g.sum_x[a * ncell + cell];
         const int64_t Saa = g.sum_xy[pidx(a, a, n) * ncell + cell];
         const int64_t Naa = cnt * Saa - (int64_t)S[a] * S[a];
         d[a] = Naa > 0 ? 1.0 / sqrt((double)Naa) : 0.0;
-        num += vd[a] * vd[a];
-        vv += vd[a] * vd[a];
+        h11 += vd[a] * vd[a];
+        h12 += vd[a] * ud[a];
+        h22 += ud[a] * ud[a];
         f2 += 1.0;
       }
     }
-    double off = 0.0, offv = 0.0;
-#pragma unroll
-    for (int a = 0; a < N; ++a)
-#pragma unroll
-      for (int b = a + 1; b < N; ++b) {
+    gvv = h11;
+    gvu = h12;
+    guu = h22;
+    double off = 0.0, o11 = 0.0, o12 = 0.0, o22 = 0.0;
+    // one row at a time, so that only a row's raw sums are in flight at once
+    static_for<0, N>([&](auto Ai) {
+      constexpr int a = RFI_CI(Ai);
+      __builtin_amdgcn_sched_barrier(0);
+      static_for<a + 1, N>([&](auto Bi) {
+        constexpr int b = RFI_CI(Bi);
         if (b < n) {
           const int64_t Sab = g.sum_xy[pidx(a, b, n) * ncell + cell];
           const int64_t Nab = cnt * Sab - (int64_t)S[a] * S[b];
           const double r = (double)Nab * d[a] * d[b];
           off += r * r;
-          offv += r * vd[a] * vd[b];
+          o11 += r * (vd[a] * vd[b]);
+          o12 += r * (vd[a] * ud[b] + ud[a] * vd[b]);
+          o22 += r * (ud[a] * ud[b]);
         }
-      }
+      });
+    });
     f2 += 2.0 * off;
-    num += 2.0 * offv;
+    h11 += 2.0 * o11;
+    h12 += o12;
+    h22 += 2.0 * o22;
   }
-  const double lam = (g.refine && have_v) ? num / vv : (double)lam1;
+  // Ritz values of C on span(v, u) in FP64: with v' = v / |v| and
+  // u' = (u - al v) / |u - al v|, al = (v.u) / (v.v), the projected matrix is
+  // [[p, q], [q, r]]; lambda_1 = (p + r) / 2 + sqrt(((p - r) / 2)^2 + q^2)
+  double lam = (double)lam1;
+  double cv = 1.0, cu = 0.0;   // Ritz vector = cv v' + cu u'
+  double sv = 1.0, su = 0.0, al = 0.0;
+  if (have_v && gvv > 0.0) {
+    al = gvu / gvv;
+    const double nu2 = guu - al * gvu;
+    const double pp = h11 / gvv;
+    lam = pp;
+    sv = 1.0 / sqrt(gvv);
+    if (nu2 > 1e-12 * guu) {
+      su = 1.0 / sqrt(nu2);
+      const double qq = (h12 - al * h11) * sv * su;
+      const double rr = (h22 - 2.0 * al * h12 + al * al * h11) * su * su;
+      const double hd = 0.5 * (pp - rr);
+      const double rt = sqrt(hd * hd + qq * qq);
+      lam = 0.5 * (pp + rr) + rt;
+      // eigenvector of the 2 x 2 matrix for lam, from the better conditioned
+      // of its two expressions
+      if (hd >= 0.0) {
+        cv = hd + rt;
+        cu = qq;
+      } else {
+        cv = qq;
+        cu = rt - hd;
+      }
+      const double nc = sqrt(cv * cv + cu * cu);
+      if (nc > 0.0) {
+        cv /= nc;
+        cu /= nc;
+      } else {
+        cv = 1.0;
+        cu = 0.0;
+      }
+    }
+  }
+  if (!g.refine || !have_v) lam = (double)lam1;
+  if (have_v) {
+    // v1 = cv v' + cu u' in the original basis
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      v[i] = (float)(cv * sv * v[i] + cu * su * ((double)u[i] - al * (double)v[i]));
+  }
   g.stat[cell] = lam * lam / f2;
   g.status[cell] = st;
 
@@ -339,7 +588,13 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void eig_lane_refine(EigArgs g) {
+__global__ __launch_bounds__(256) void eig_lane_tri(EigArgs g) {
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell < (int64_t)g.nsub * g.nchan) lanetri_cell<N>(g, cell);
+}
+
+template <int N>
+__global__ __launch_bounds__(256, 2) void eig_lane_refine(EigArgs g) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell < (int64_t)g.nsub * g.nchan) refine_cell<N>(g, cell);
 }
@@ -367,7 +622,18 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi_batch(const EigArgs* item
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void eig_lane_refine_batch(const EigArgs* items,
+__global__ __launch_bounds__(256) void eig_lane_tri_batch(const EigArgs* items,
+                                                          const int64_t* cell0, int nitem,
+                                                          int64_t total) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= total) return;
+  const int i = find_item(cell0, nitem, c);
+  const EigArgs g = items[i];
+  lanetri_cell<N>(g, c - cell0[i]);
+}
+
+template <int N>
+__global__ __launch_bounds__(256, 2) void eig_lane_refine_batch(const EigArgs* items,
                                                              const int64_t* cell0, int nitem,
                                                              int64_t total) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -379,9 +645,13 @@ __global__ __launch_bounds__(256) void eig_lane_refine_batch(const EigArgs* item
 
 template <int N>
 hipError_t launch_batch_n(const EigArgs* items, const int64_t* cell0, int nitem, int64_t total,
-                          int wg, hipStream_t s) {
+                          int wg, bool tri, hipStream_t s) {
   const dim3 grid((unsigned)((total + wg - 1) / wg));
-  hipLaunchKernelGGL(eig_lane_jacobi_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem, total);
+  if (tri)
+    hipLaunchKernelGGL(eig_lane_tri_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem, total);
+  else
+    hipLaunchKernelGGL(eig_lane_jacobi_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem,
+                       total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(eig_lane_refine_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem, total);
@@ -389,10 +659,13 @@ hipError_t launch_batch_n(const EigArgs* items, const int64_t* cell0, int nitem,
 }
 
 template <int N>
-hipError_t launch_n(const EigArgs& a, int wg, hipStream_t s) {
+hipError_t launch_n(const EigArgs& a, int wg, bool tri, hipStream_t s) {
   const int64_t ncell = (int64_t)a.nsub * a.nchan;
   const dim3 grid((unsigned)((ncell + wg - 1) / wg));
-  hipLaunchKernelGGL(eig_lane_jacobi<N>, grid, dim3(wg), 0, s, a);
+  if (tri)
+    hipLaunchKernelGGL(eig_lane_tri<N>, grid, dim3(wg), 0, s, a);
+  else
+    hipLaunchKernelGGL(eig_lane_jacobi<N>, grid, dim3(wg), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(eig_lane_refine<N>, grid, dim3(wg), 0, s, a);
@@ -412,28 +685,28 @@ int eig_lane_class(int n) {
 }
 
 hipError_t launch_eig_lane_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
-                                 int64_t total, hipStream_t s, int wg) {
+                                 int64_t total, hipStream_t s, int wg, bool tri) {
   if (wg != 64 && wg != 128 && wg != 256) return hipErrorInvalidValue;
   switch (cls) {
-    case 4: return launch_batch_n<4>(items, cell0, nitem, total, wg, s);
-    case 8: return launch_batch_n<8>(items, cell0, nitem, total, wg, s);
-    case 12: return launch_batch_n<12>(items, cell0, nitem, total, wg, s);
-    case 16: return launch_batch_n<16>(items, cell0, nitem, total, wg, s);
-    case 19: return launch_batch_n<19>(items, cell0, nitem, total, wg, s);
-    case 20: return launch_batch_n<20>(items, cell0, nitem, total, wg, s);
+    case 4: return launch_batch_n<4>(items, cell0, nitem, total, wg, tri, s);
+    case 8: return launch_batch_n<8>(items, cell0, nitem, total, wg, tri, s);
+    case 12: return launch_batch_n<12>(items, cell0, nitem, total, wg, tri, s);
+    case 16: return launch_batch_n<16>(items, cell0, nitem, total, wg, tri, s);
+    case 19: return launch_batch_n<19>(items, cell0, nitem, total, wg, tri, s);
+    case 20: return launch_batch_n<20>(items, cell0, nitem, total, wg, tri, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg) {
+hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg, bool tri) {
   const int n = a.nbeam;
   if (wg != 64 && wg != 128 && wg != 256) return hipErrorInvalidValue;
-  if (n <= 4) return launch_n<4>(a, wg, s);
-  if (n <= 8) return launch_n<8>(a, wg, s);
-  if (n <= 12) return launch_n<12>(a, wg, s);
-  if (n <= 16) return launch_n<16>(a, wg, s);
-  if (n == 19) return launch_n<19>(a, wg, s);
-  if (n <= 20) return launch_n<20>(a, wg, s);
+  if (n <= 4) return launch_n<4>(a, wg, tri, s);
+  if (n <= 8) return launch_n<8>(a, wg, tri, s);
+  if (n <= 12) return launch_n<12>(a, wg, tri, s);
+  if (n <= 16) return launch_n<16>(a, wg, tri, s);
+  if (n == 19) return launch_n<19>(a, wg, tri, s);
+  if (n <= 20) return launch_n<20>(a, wg, tri, s);
   return hipErrorInvalidValue;
 }
 

@@ -72,8 +72,9 @@ struct EigArgs {
   int64_t out_stride;  // cell stride of the eigvals / v1 rows (>= nsub * nchan)
   int layout;          // sums layout (1: cell records; the tridiagonal solver only)
 };
-// FP32, nbeam <= 20; wg = lanes (cells) per workgroup: 64, 128 or 256
-hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg = 256);
+// FP32, nbeam <= 20; wg = lanes (cells) per workgroup: 64, 128 or 256; tri
+// = Householder + Sturm instead of Jacobi for the first kernel
+hipError_t launch_eig_lane(const EigArgs& a, hipStream_t s, int wg = 256, bool tri = false);
 hipError_t launch_eig_wave(const EigArgs& a, int precision, hipStream_t s);  // any nbeam
 hipError_t launch_eig_tri(const EigArgs& a, hipStream_t s);               // any nbeam, FP64
 // The eigen stage of one block with resolved parameters (solver, precision).
@@ -85,7 +86,7 @@ hipError_t launch_eig(const EigArgs& a, const rfi_eig_params& p, hipStream_t s, 
 // per-wave solver any beam counts up to max_nbeam.
 int eig_lane_class(int n);
 hipError_t launch_eig_lane_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
-                                 int64_t total, hipStream_t s, int wg = 256);
+                                 int64_t total, hipStream_t s, int wg = 256, bool tri = false);
 hipError_t launch_eig_wave_batch(int precision, int max_nbeam, const EigArgs* items,
                                  const int64_t* cell0, int nitem, int64_t total, hipStream_t s);
 // The per-wave tridiagonal solver: template class of a beam count (local

@@ -23,7 +23,7 @@ RFI_MAX_BEAMS = 79
 RFI_MAX_COUNT = 33025
 RFI_HIST_CAP = 1024
 RFI_CCM_AUTO, RFI_CCM_MFMA, RFI_CCM_VALU = 0, 1, 2
-RFI_EIG_AUTO, RFI_EIG_LANE, RFI_EIG_WAVE, RFI_EIG_TRIDIAG = 0, 1, 2, 3
+RFI_EIG_AUTO, RFI_EIG_LANE, RFI_EIG_WAVE, RFI_EIG_TRIDIAG, RFI_EIG_LANE_TRI = 0, 1, 2, 3, 4
 
 
 class RfiError(RuntimeError):

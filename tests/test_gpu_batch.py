@@ -216,15 +216,28 @@ def test_forced_launch_choices_are_bit_exact(dev):
                     for g, r in zip(got, ref):
                         for u, v in zip(g, r):
                             assert np.array_equal(u, v), (lo, tile, stages, gb)
+    # per-lane workgroup sizes of the default per-lane solver; the 16-31 class
+    # holds 19-beam blocks only (per-lane solvers apply)
+    small = [b for b in blocks if b["nb"] <= 20]
+    want = [r for b, r in zip(blocks, ref) if b["nb"] <= 20]
     for wg in (64, 128):
-        t = _table([dict(nbeam_lo=2, nbeam_hi=15, eig_solver=rfi.RFI_EIG_LANE, eig_wg=wg),
-                    dict(nbeam_lo=16, nbeam_hi=31, eig_solver=rfi.RFI_EIG_LANE, eig_wg=wg)])
-        # the 16-31 class holds a 19-beam block only (per-lane solver applies)
-        got = _run_batch([b for b in blocks if b["nb"] <= 20], dev, t)
-        want = [r for b, r in zip(blocks, ref) if b["nb"] <= 20]
+        t = _table([dict(nbeam_lo=2, nbeam_hi=15, eig_solver=rfi.RFI_EIG_LANE_TRI, eig_wg=wg),
+                    dict(nbeam_lo=16, nbeam_hi=31, eig_solver=rfi.RFI_EIG_LANE_TRI, eig_wg=wg)])
+        got = _run_batch(small, dev, t)
         for g, r in zip(got, want):
             for u, v in zip(g, r):
                 assert np.array_equal(u, v), wg
+    # the Jacobi per-lane solver at two workgroup sizes: the same bits as each
+    # other, and within 1e-12 of the default solver's statistic
+    jac = []
+    for wg in (64, 256):
+        t = _table([dict(nbeam_lo=2, nbeam_hi=15, eig_solver=rfi.RFI_EIG_LANE, eig_wg=wg),
+                    dict(nbeam_lo=16, nbeam_hi=31, eig_solver=rfi.RFI_EIG_LANE, eig_wg=wg)])
+        jac.append(_run_batch(small, dev, t))
+    for g0, g1, r in zip(jac[0], jac[1], want):
+        for u, v in zip(g0, g1):
+            assert np.array_equal(u, v)
+        assert np.abs(g0[0] - r[0]).max() <= 1e-12
 
 
 def test_tuned_batch_matches_oracle_and_graph(dev):
@@ -246,8 +259,9 @@ def test_tuned_batch_matches_oracle_and_graph(dev):
         assert 0 < e["ms_tuned"] <= e["ms_default"] + 1e-9, e
         assert 0 <= e["ccm_tile"] < 3 and e["ccm_stages"] in (0, 2, 3, 4)
         assert e["ccm_group_bytes"] in (0, 256, 512, 2048, 4096, 8192)
-        assert e["eig_solver"] in (0, rfi.RFI_EIG_LANE, rfi.RFI_EIG_WAVE, rfi.RFI_EIG_TRIDIAG)
-        if e["eig_solver"] == rfi.RFI_EIG_LANE:
+        assert e["eig_solver"] in (0, rfi.RFI_EIG_LANE, rfi.RFI_EIG_WAVE, rfi.RFI_EIG_TRIDIAG,
+                                   rfi.RFI_EIG_LANE_TRI)
+        if e["eig_solver"] in (rfi.RFI_EIG_LANE, rfi.RFI_EIG_LANE_TRI):
             assert e["nbeam_hi"] <= 31 and e["eig_wg"] in (64, 128, 256)
     tuned = rfi.Batch(items, tune=table)
     ws2 = torch.empty(tuned.workspace_size(), dtype=torch.uint8, device=dev)

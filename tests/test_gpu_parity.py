@@ -169,15 +169,26 @@ def test_eig_lane_tiny(dev, tiny):
     assert (status == 0).all()
 
 
+@pytest.mark.parametrize("solver", [1, 4])
 @pytest.mark.parametrize("nbeam", [2, 3, 5, 7, 8, 12, 16, 19, 20])
-def test_eig_lane_sizes(dev, nbeam):
+def test_eig_lane_sizes(dev, nbeam, solver):
+    """Per-lane solvers (1: Jacobi, 4: Householder + Sturm), FP32 with the FP64
+    refinement: eigenvalues within 1e-5 of lambda_1, statistic within 1e-9."""
     rng = np.random.default_rng(100 + nbeam)
     L, nsub, nc = 256, 2, 70
     x = np.clip(np.rint(128 + 20 * rng.standard_normal((nbeam, nsub * L, nc))), 0, 255).astype(np.uint8)
     common = np.rint(15 * np.sin(np.arange(nsub * L) / 5.0)).astype(np.int64)
     x[:, :, 3] = np.clip(x[:, :, 3].astype(np.int64) + common[None, :], 0, 255)
-    out = _eig_case(dev, x, L, nsub, 32, 1)
+    out = _eig_case(dev, x, L, nsub, 32, solver)
     _check_eig(x, L, nsub, out, 1e-5, 1e-9)
+
+
+def test_eig_lane_tri_tiny(dev, tiny):
+    spec, x = tiny
+    L, nsub = spec.L, spec.nsamp // spec.L
+    out = _eig_case(dev, x, L, nsub, 32, 4)
+    status, cr = _check_eig(x, L, nsub, out, 1e-5, 1e-9)
+    assert (status == 0).all()
 
 
 @pytest.mark.parametrize("precision", [32, 64])
@@ -215,7 +226,7 @@ def test_eig_degenerate_cells(dev):
     x = rng.integers(0, 256, size=(nb, nsub * L, nc), dtype=np.uint8)
     x[4, :L, 5] = 77                 # constant beam in cell (0, 5)
     x[:, L:, 9] = 3                  # every beam constant in cell (1, 9)
-    for solver, prec in ((1, 32), (2, 32), (2, 64), (3, 32)):
+    for solver, prec in ((1, 32), (2, 32), (2, 64), (3, 32), (4, 32)):
         stat, status, ev, v1 = _eig_case(dev, x, L, nsub, prec, solver)
         cr = pipeline.cells(x, L, nsub)
         deg = cr.degenerate.ravel()
