@@ -220,6 +220,45 @@ def test_eig_tridiag(dev, nbeam):
     assert (status == 0).all()
 
 
+def _close_pair_block(seed=91, nb=19, L=1024, nsub=2, nc=16):
+    """Two disjoint beam groups carrying two different Walsh sequences (exactly
+    orthogonal, zero-mean +-1 patterns over every sub-interval) at amplitude
+    100: group A (beams 0-8) without noise, so lambda = 9 exactly; group B
+    (beams 9-17) with unit noise, so its eigenvalue sits ~1e-4 below 9; beam
+    18 is noise. lambda_1 and lambda_2 are 3e-5 .. 1e-3 apart (relative)."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(nsub * L) % L
+    x = np.empty((nb, nsub * L, nc))
+    for j in range(nc):
+        w1 = 1 - 2 * (np.array([bin(v).count("1") for v in ((5 + 3 * j) & t)]) & 1)
+        w2 = 1 - 2 * (np.array([bin(v).count("1") for v in ((300 + 7 * j) & t)]) & 1)
+        for b in range(nb):
+            if b < 9:
+                x[b, :, j] = 128 + 100 * w1
+            elif b < 18:
+                x[b, :, j] = 128 + 100 * w2 + rng.standard_normal(nsub * L)
+            else:
+                x[b, :, j] = 128 + 20 * rng.standard_normal(nsub * L)
+    return np.clip(np.rint(x), 0, 255).astype(np.uint8)
+
+
+@pytest.mark.parametrize("solver,prec", [(1, 32), (4, 32), (3, 32), (2, 64)])
+def test_eig_close_dominant_pair(dev, solver, prec):
+    """lambda_1 and lambda_2 3e-5 .. 1e-3 apart (see _close_pair_block): the
+    statistic must still match the oracle to 1e-12. One vector of inverse
+    iteration shifted ~2e-5 above lambda_1 cannot separate such a pair, and
+    its Rayleigh quotient misses lambda_1 by a fraction of the gap."""
+    nb, L, nsub = 19, 1024, 2
+    x = _close_pair_block()
+    cr = pipeline.cells(x, L, nsub)
+    w = cr.w.reshape(-1, nb)
+    gap = (w[:, 0] - w[:, 1]) / w[:, 0]
+    assert gap.max() < 2e-3                       # the pair is close by construction
+    stat, status, ev, v1 = _eig_case(dev, x, L, nsub, prec, solver)
+    assert np.abs(stat - cr.stat.ravel()).max() <= 1e-12
+    assert (status & 8 == 0).all()                # refinement succeeded
+
+
 def test_eig_degenerate_cells(dev):
     rng = np.random.default_rng(7)
     nb, L, nsub, nc = 19, 64, 2, 20
