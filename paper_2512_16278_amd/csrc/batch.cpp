@@ -480,9 +480,12 @@ rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items, const rfi_
       cands = {{RFI_EIG_LANE, 256},     {RFI_EIG_LANE, 128},     {RFI_EIG_LANE, 64},
                {RFI_EIG_LANE_TRI, 256}, {RFI_EIG_LANE_TRI, 128}, {RFI_EIG_LANE_TRI, 64},
                {RFI_EIG_TRIDIAG, 0}};
-    } else {
+    } else if (precision == 64) {
       cands = {{RFI_EIG_TRIDIAG, 0}, {RFI_EIG_WAVE, 0}};
     }
+    // (FP32 above 20 beams: the tridiagonal solver only; the FP32 Jacobi wave
+    // solver there is the precision split's reference, 50-100x slower, and
+    // even one warm-up of it costs seconds on a large class)
     const int def_solver = precision == 64 ? RFI_EIG_WAVE
                            : (max_nbeam[sc] <= 20 ? RFI_EIG_LANE_TRI : RFI_EIG_TRIDIAG);
     for (auto& c : cands) {

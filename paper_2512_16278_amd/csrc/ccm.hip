@@ -83,10 +83,19 @@ struct MfmaCfg {
   static constexpr int SXL_OFF = 0;
   static constexpr int TAB_OFF = SXL_OFF + MAXB * CW * 4;
   static constexpr int STG_OFF = (TAB_OFF + MAXROW * 2 + 15) / 16 * 16;
-  static constexpr int STG_BYTES = LDS_MAX - STG_OFF;
-  // worst case: one wave's channels per pass at the largest beam count
-  static constexpr bool FITS = RING <= LDS_MAX && STG_BYTES >= MAXROW * (CPW + 1) * 4;
-  static constexpr int LDS = LDS_MAX;
+  // worst case of the staging: one wave's channels per pass at the largest
+  // beam count
+  static constexpr int STG_MIN = MAXROW * (CPW + 1) * 4;
+  // the workgroup's LDS: the ring, or the epilogue's minimum if larger (more
+  // epilogue passes in less space), 1 KB granules. A tile whose ring is at
+  // most half the CU's LDS leaves room for a second workgroup, whose loads
+  // then stream during this one's epilogue.
+  static constexpr int NEED = RING > STG_OFF + STG_MIN ? RING : STG_OFF + STG_MIN;
+  static constexpr int LDS = (NEED + 1023) / 1024 * 1024 < LDS_MAX
+                                 ? (NEED + 1023) / 1024 * 1024
+                                 : LDS_MAX;
+  static constexpr int STG_BYTES = LDS - STG_OFF;
+  static constexpr bool FITS = RING <= LDS_MAX && STG_BYTES >= STG_MIN;
 };
 
 // LDS unit (16 bytes) of (beam, row, segment) inside a chunk buffer

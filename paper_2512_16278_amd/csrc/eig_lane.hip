@@ -242,9 +242,9 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
   bool degenerate;
   load_corr32<N>(g, ncell, cell, n, cnt, A, degenerate);
 
-  // dg: diagonal of T; e2[i]: squared coupling of i - 1 and i (e2[0] = 0)
-  float dg[N], e2[N];
-  e2[0] = 0.f;
+  // The tridiagonal T stays in the matrix's own registers: its diagonal in
+  // A(i, i) (final once step i - 1 is done) and its squared couplings in
+  // A(i, i - 1) (the reduced column's head, dead after its step).
   static_for<0, N - 2>([&](auto K) {
     constexpr int k = RFI_CI(K);
     // reflector of (x0, x_{k+2}, ...) onto (mu, 0, ...): v0 = x0 - mu without
@@ -262,13 +262,12 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
     const float v0 = x0 <= 0.f ? x0 - mu : -s2 / (x0 + mu);
     const float beta = refl ? -v0 / mu : 0.f;
     const float iv0 = refl ? 1.0f / v0 : 0.f;
-    dg[k] = A[Sym<N>::idx(k, k)];
-    e2[k + 1] = mu2;
     float v[N], w[N];
     static_for<k + 1, N>([&](auto I) {
       constexpr int i = RFI_CI(I);
       v[i] = i == k + 1 ? 1.0f : A[Sym<N>::idx(i, k)] * iv0;
     });
+    A[Sym<N>::idx(k + 1, k)] = mu2;
     // p = beta A22 v, K = beta p.v / 2, w = p - K v
     float pv = 0.f;
     static_for<k + 1, N>([&](auto I) {
@@ -296,12 +295,16 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
       });
     });
   });
-  dg[N - 2] = A[Sym<N>::idx(N - 2, N - 2)];
-  dg[N - 1] = A[Sym<N>::idx(N - 1, N - 1)];
   {
     const float x = A[Sym<N>::idx(N - 1, N - 2)];
-    e2[N - 1] = x * x;
+    A[Sym<N>::idx(N - 1, N - 2)] = x * x;
   }
+  float dg[N], e2[N];
+  static_for<0, N>([&](auto I) {
+    constexpr int i = RFI_CI(I);
+    dg[i] = A[Sym<N>::idx(i, i)];
+    e2[i] = i > 0 ? A[Sym<N>::idx(i, i > 0 ? i - 1 : 0)] : 0.f;
+  });
 
   // Gershgorin bracket of T; lambda_1 (the largest: a correlation matrix is
   // positive semidefinite) is at least every diagonal entry
@@ -588,7 +591,7 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void eig_lane_tri(EigArgs g) {
+__global__ __launch_bounds__(256, 2) void eig_lane_tri(EigArgs g) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell < (int64_t)g.nsub * g.nchan) lanetri_cell<N>(g, cell);
 }
@@ -622,7 +625,7 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi_batch(const EigArgs* item
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void eig_lane_tri_batch(const EigArgs* items,
+__global__ __launch_bounds__(256, 2) void eig_lane_tri_batch(const EigArgs* items,
                                                           const int64_t* cell0, int nitem,
                                                           int64_t total) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
