@@ -388,6 +388,15 @@ typedef struct {
   int32_t device;        /* HIP device ordinal */
   int32_t max_inflight;  /* execution slots, 1..64 (0 = 8); 1 = one block at a time */
   int64_t hbm_budget;    /* bytes admitted at once (0 = 64 GiB) */
+  /* HOST table from rfi_tune_batch, or NULL (defaults). Copied at create;
+   * each stream takes the entry whose beam range holds its nbeam when it
+   * opens and uses its solver, sums tile, ring depth, XCD grouping and
+   * per-lane workgroup for every block. Results do not depend on it (the
+   * sums choices are bit-exact with the defaults; another solver gives the
+   * same masks with statistics within its accuracy, 1e-12 for the solvers
+   * rfi_tune_batch picks). Entries out of range fail rfi_stream_open with
+   * RFI_E_INVALID. */
+  const rfi_tune_table* tune;
 } rfi_session_config;
 
 typedef struct {

@@ -58,13 +58,6 @@ inline int shape_class(int nbeam) { return (nbeam + 1 + 15) / 16; }
 inline int class_lo(int sc) { return std::max(2, 16 * (sc - 1)); }
 inline int class_hi(int sc) { return 16 * sc - 1; }
 
-const rfi_tune_entry* find_tune(const rfi_tune_table* t, int nbeam) {
-  if (!t) return nullptr;
-  for (int i = 0; i < std::min<int>(t->n, RFI_TUNE_MAX); ++i)
-    if (t->e[i].nbeam_lo <= nbeam && nbeam <= t->e[i].nbeam_hi) return &t->e[i];
-  return nullptr;
-}
-
 struct BatchPlan {
   std::vector<ItemPlan> plans;
   rfi_eig_params eig;      // sweeps, precision (solver per item)
@@ -113,10 +106,7 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
     ip.nchan = it.blk->nchan;
     ip.ncell = (int64_t)it.nsub * it.blk->nchan;
     ip.ct = CcmTune{te ? te->ccm_tile : 0, te ? te->ccm_stages : 0, te ? te->ccm_group_bytes : 0};
-    if (te && (te->ccm_stages < 0 || te->ccm_stages > 4 || te->ccm_group_bytes < 0 ||
-               te->ccm_group_bytes > 16384 || te->ccm_tile < 0 ||
-               te->ccm_tile >= ccm_tile_variants(ip.nbeam)))
-      return fail(RFI_E_INVALID, "%s: item %d: tune entry out of range", who, i);
+    if ((st = check_tune_entry(te, ip.nbeam, who)) != RFI_OK) return st;
     if (ccm_class(ip.nbeam, &ip.cc, &ip.ct) != hipSuccess)
       return fail(RFI_E_INVALID, "%s: item %d: no sums instance for %d beams", who, i, ip.nbeam);
     ip.solver = res.solver;
@@ -126,8 +116,6 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
                   : res.solver == RFI_EIG_TRIDIAG ? eig_tri_class(ip.nbeam)
                                                   : 0;
     ip.wg = te && te->eig_wg ? te->eig_wg : 256;
-    if (ip.wg != 64 && ip.wg != 128 && ip.wg != 256)
-      return fail(RFI_E_INVALID, "%s: item %d: eig_wg %d not 64, 128 or 256", who, i, ip.wg);
     tab_bytes += (size_t)ip.nbeam * sizeof(void*);
     bpn->plans.push_back(ip);
   }
@@ -337,6 +325,24 @@ float time_ms(const std::function<hipError_t()>& fn, hipStream_t s, float cutoff
 }
 
 }  // namespace
+
+const rfi_tune_entry* find_tune(const rfi_tune_table* t, int nbeam) {
+  if (!t) return nullptr;
+  for (int i = 0; i < std::min<int>(t->n, RFI_TUNE_MAX); ++i)
+    if (t->e[i].nbeam_lo <= nbeam && nbeam <= t->e[i].nbeam_hi) return &t->e[i];
+  return nullptr;
+}
+
+rfi_status check_tune_entry(const rfi_tune_entry* te, int nbeam, const char* who) {
+  if (!te) return RFI_OK;
+  if (te->ccm_stages < 0 || te->ccm_stages > 4 || te->ccm_group_bytes < 0 ||
+      te->ccm_group_bytes > 16384 || te->ccm_tile < 0 || te->ccm_tile >= ccm_tile_variants(nbeam))
+    return fail(RFI_E_INVALID, "%s: tune entry for %d beams out of range", who, nbeam);
+  if (te->eig_wg != 0 && te->eig_wg != 64 && te->eig_wg != 128 && te->eig_wg != 256)
+    return fail(RFI_E_INVALID, "%s: tune entry eig_wg %d not 0, 64, 128 or 256", who, te->eig_wg);
+  return RFI_OK;
+}
+
 }  // namespace rfi
 
 struct rfi_batch_graph {

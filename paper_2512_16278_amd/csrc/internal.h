@@ -128,5 +128,10 @@ rfi_status validate_block(const rfi_block* blk, int64_t t0, int32_t L, int32_t n
                           const char* who, BeamPtrs* bp);
 // Eigen parameters with defaults applied and the solver resolved.
 rfi_status resolve_eig(int nbeam, const rfi_eig_params* p, rfi_eig_params* out, const char* who);
+// Entry of a tune table whose beam range holds nbeam (NULL if none or no table).
+const rfi_tune_entry* find_tune(const rfi_tune_table* t, int nbeam);
+// Range checks of one entry's launch choices for nbeam beams (not the solver,
+// which resolve_eig checks).
+rfi_status check_tune_entry(const rfi_tune_entry* te, int nbeam, const char* who);
 
 }  // namespace rfi

@@ -67,7 +67,7 @@ int shared_tile() {
 }  // namespace
 
 rfi_status resolve_process(int nbeam, int nchan, const rfi_process_params* p, ProcessPlan* pl,
-                           const char* who) {
+                           const char* who, const rfi_tune_entry* te) {
   if (!p) return fail(RFI_E_INVALID, "%s: params is NULL", who);
   if (nbeam < 2 || nbeam > RFI_MAX_BEAMS || nchan < 1)
     return fail(RFI_E_INVALID, "%s: bad nbeam %d / nchan %d", who, nbeam, nchan);
@@ -75,10 +75,13 @@ rfi_status resolve_process(int nbeam, int nchan, const rfi_process_params* p, Pr
   if (p->nsub < 0) return fail(RFI_E_INVALID, "%s: nsub %d < 0", who, p->nsub);
   if (!(p->kappa >= 0.0)) return fail(RFI_E_INVALID, "%s: kappa must be >= 0", who);
   if (p->max_iter < 0) return fail(RFI_E_INVALID, "%s: max_iter %d < 0", who, p->max_iter);
-  rfi_eig_params ep{p->eig_precision ? p->eig_precision : 32,
-                    p->max_sweeps ? p->max_sweeps : 12, 1, RFI_EIG_AUTO};
-  const rfi_status st = resolve_eig(nbeam, &ep, &pl->eig, who);
+  rfi_status st = check_tune_entry(te, nbeam, who);
   if (st != RFI_OK) return st;
+  rfi_eig_params ep{p->eig_precision ? p->eig_precision : 32,
+                    p->max_sweeps ? p->max_sweeps : 12, 1, te ? te->eig_solver : RFI_EIG_AUTO};
+  if ((st = resolve_eig(nbeam, &ep, &pl->eig, who)) != RFI_OK) return st;
+  pl->ct = te ? CcmTune{te->ccm_tile, te->ccm_stages, te->ccm_group_bytes} : CcmTune{};
+  pl->eig_wg = te ? te->eig_wg : 0;
   pl->nbeam = nbeam;
   pl->nchan = nchan;
   pl->nsub = p->nsub;
@@ -144,7 +147,7 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
     // the per-wave tridiagonal solver reads one cell record per wave
     const int layout = pl.eig.solver == RFI_EIG_TRIDIAG ? 1 : 0;
     e = launch_ccm_mfma(bp, pl.nbeam, pl.nchan, row_stride, t0 + (int64_t)k0 * L, L, ks, sx, sxy,
-                        cnt, 0, shared_tile(), s, nullptr, layout);
+                        cnt, 0, shared_tile(), s, &pl.ct, layout);
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ev.ccm[slot], s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(ev.aux, ev.ccm[slot], 0)) != hipSuccess) return e;
@@ -152,7 +155,7 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
     EigArgs a{pl.nbeam, ks, pl.nchan, sx, sxy, cnt, pl.eig.max_sweeps, 1,
               eigvals ? eigvals + off : nullptr, stat + off, v1 ? v1 + off : nullptr,
               status + off, out_stride, layout};
-    e = launch_eig(a, pl.eig, ev.aux, lane_wg());
+    e = launch_eig(a, pl.eig, ev.aux, pl.eig_wg ? pl.eig_wg : lane_wg());
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ev.eig[slot], ev.aux)) != hipSuccess) return e;
   }

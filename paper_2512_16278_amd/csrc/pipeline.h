@@ -18,13 +18,17 @@ struct ProcessPlan {
   int nbeam = 0, nchan = 0, nsub = 0, group = 1, nslot = 1, max_iter = 50;
   double kappa = 3.0;
   rfi_eig_params eig{32, 12, 1, RFI_EIG_AUTO};
+  CcmTune ct{};          // sums-engine choices (zeros = the engine's defaults)
+  int eig_wg = 0;        // per-lane solver workgroup (0 = default)
   size_t flag_ws = 0;    // bytes of the clip workspace (first in the workspace)
   size_t slot = 0;       // bytes of one ring slot of sums
   size_t ws_bytes = 0;   // total workspace
 };
 
+// te: tuned launch choices for this beam count (solver, sums tile, ring depth,
+// XCD grouping, per-lane workgroup), or NULL for the defaults.
 rfi_status resolve_process(int nbeam, int nchan, const rfi_process_params* p, ProcessPlan* pl,
-                           const char* who);
+                           const char* who, const rfi_tune_entry* te = nullptr);
 
 // Helper stream and the events that order the ring between the two streams.
 struct PipeEvents {

@@ -56,6 +56,9 @@ struct StreamCtx {
   hipEvent_t last = nullptr;         // completion of the stream's last admitted block
   bool has_last = false;
   int queued = 0, inflight = 0;
+  bool tuned = false;                // te holds the session's tune entry for nbeam
+  rfi_tune_entry te{};
+  const rfi_tune_entry* tune() const { return tuned ? &te : nullptr; }
   int32_t* carry_sx() const { return carry; }
   int32_t* carry_sxy() const { return carry + (size_t)cfg.nbeam * cfg.nchan; }
   int32_t* carry_cnt() const {
@@ -116,6 +119,8 @@ struct rfi_session {
   int device = 0;
   int max_slots = 8;
   int64_t budget = rfi::kDefaultBudget;
+  bool has_tune = false;  // session copy of the caller's tune table
+  rfi_tune_table tune{};
   std::mutex mu;
   std::condition_variable cv_work;   // new work / stop, for the scheduler
   std::condition_variable cv_done;   // a block finished, for waiters
@@ -193,7 +198,7 @@ rfi_status plan_block(const StreamCtx& st, int64_t nsamp, BlockPlan* b, const ch
   p.max_iter = st.cfg.max_iter;
   p.kappa = st.cfg.kappa;
   // the clip covers nsub rows; its workspace does not depend on the size
-  rfi_status s = resolve_process(st.cfg.nbeam, st.cfg.nchan, &p, &b->pl, who);
+  rfi_status s = resolve_process(st.cfg.nbeam, st.cfg.nchan, &p, &b->pl, who, st.tune());
   if (s != RFI_OK) return s;
   b->ws = b->pl.ws_bytes;
   const size_t ncell = (size_t)b->nsub * st.cfg.nchan;
@@ -244,13 +249,13 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
   // 1. complete (or extend) the carried sub-interval
   if (b.carry_add > 0) {
     e = launch_ccm_mfma(bp, n, F, stride, 0, (int)b.carry_add, 1, st.carry_sx(), st.carry_sxy(),
-                        st.carry_cnt(), 1, 0, s);
+                        st.carry_cnt(), 1, 0, s, &b.pl.ct);
     if (e != hipSuccess) return dev(e, "rfi_submit: carry sums");
   }
   if (b.carried) {
     EigArgs a{n, 1, F, st.carry_sx(), st.carry_sxy(), st.carry_cnt(), b.pl.eig.max_sweeps, 1,
               nullptr, r->stat, nullptr, r->cstat, (int64_t)b.nsub * F};
-    e = launch_eig(a, b.pl.eig, s);
+    e = launch_eig(a, b.pl.eig, s, b.pl.eig_wg ? b.pl.eig_wg : 256);
     if (e != hipSuccess) return dev(e, "rfi_submit: carry eigen stage");
   }
   // 2. full sub-intervals
@@ -265,7 +270,7 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
   // 3. new carry
   if (b.rem > 0) {
     e = launch_ccm_mfma(bp, n, F, stride, b.t_full + (int64_t)b.nfull * L, (int)b.rem, 1,
-                        st.carry_sx(), st.carry_sxy(), st.carry_cnt(), 0, 0, s);
+                        st.carry_sx(), st.carry_sxy(), st.carry_cnt(), 0, 0, s, &b.pl.ct);
     if (e != hipSuccess) return dev(e, "rfi_submit: new carry");
   }
   // 4. clip, pooled with the stream state (after the previous clip of any slot)
@@ -401,8 +406,10 @@ rfi_status rfi_session_create(const rfi_session_config* cfg, rfi_session** out) 
   const char* who = "rfi_session_create";
   if (!out) return fail(RFI_E_INVALID, "%s: out is NULL", who);
   *out = nullptr;
-  rfi_session_config c{0, 8, rfi::kDefaultBudget};
+  rfi_session_config c{0, 8, rfi::kDefaultBudget, nullptr};
   if (cfg) c = *cfg;
+  if (c.tune && (c.tune->n < 0 || c.tune->n > RFI_TUNE_MAX))
+    return fail(RFI_E_INVALID, "%s: tune table with %d entries", who, c.tune->n);
   if (c.max_inflight == 0) c.max_inflight = 8;
   if (c.hbm_budget == 0) c.hbm_budget = rfi::kDefaultBudget;
   if (c.max_inflight < 1 || c.max_inflight > rfi::kMaxSlots)
@@ -418,6 +425,10 @@ rfi_status rfi_session_create(const rfi_session_config* cfg, rfi_session** out) 
   s->device = c.device;
   s->max_slots = c.max_inflight;
   s->budget = c.hbm_budget;
+  if (c.tune) {
+    s->tune = *c.tune;
+    s->has_tune = true;
+  }
   s->t0 = rfi::Clock::now();
   rfi::DeviceGuard g(s->device);
   s->slots.resize(s->max_slots);
@@ -500,10 +511,15 @@ rfi_status rfi_stream_open(rfi_session* s, const rfi_stream_config* c, int32_t* 
   p.max_sweeps = cfg.max_sweeps;
   p.max_iter = cfg.max_iter;
   p.kappa = cfg.kappa;
-  rfi_status rs = rfi::resolve_process(cfg.nbeam, cfg.nchan, &p, &pl, who);
+  const rfi_tune_entry* te = s->has_tune ? rfi::find_tune(&s->tune, cfg.nbeam) : nullptr;
+  rfi_status rs = rfi::resolve_process(cfg.nbeam, cfg.nchan, &p, &pl, who, te);
   if (rs != RFI_OK) return rs;
   std::unique_ptr<rfi::StreamCtx> st(new rfi::StreamCtx);
   st->cfg = cfg;
+  if (te) {
+    st->tuned = true;
+    st->te = *te;
+  }
   st->cfg.protect_chan = nullptr;
   rfi::DeviceGuard g(s->device);
   hipError_t e;

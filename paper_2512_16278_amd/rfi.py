@@ -97,7 +97,8 @@ class rfi_batch_params(C.Structure):
 
 
 class rfi_session_config(C.Structure):
-    _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32), ("hbm_budget", C.c_int64)]
+    _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32), ("hbm_budget", C.c_int64),
+                ("tune", C.POINTER(rfi_tune_table))]
 
 
 class rfi_stream_config(C.Structure):
@@ -369,9 +370,11 @@ class BatchGraph:
 class Session:
     """Thin wrapper of an rfi_session (continuous batching of blocks)."""
 
-    def __init__(self, device=0, max_inflight=8, hbm_budget=0):
+    def __init__(self, device=0, max_inflight=8, hbm_budget=0,
+                 tune: "rfi_tune_table | None" = None):
         self.h = C.c_void_p()
-        cfg = rfi_session_config(int(device), int(max_inflight), int(hbm_budget))
+        cfg = rfi_session_config(int(device), int(max_inflight), int(hbm_budget),
+                                 C.pointer(tune) if tune is not None else None)
         _check(lib().rfi_session_create(C.byref(cfg), C.byref(self.h)))
 
     def close(self):

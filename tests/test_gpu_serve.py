@@ -194,3 +194,56 @@ def test_serve_errors_cancel_budget(dev):
         assert r.nsub == 1 and r.carried == 1 and r.carry_samples == 0
         s.close_stream(sid2)
         torch.cuda.synchronize()
+
+
+def _entry(lo, hi, tile=0, stages=0, group=0, solver=0, wg=0):
+    from paper_2512_16278_amd import rfi
+    return rfi.rfi_tune_entry(lo, hi, tile, stages, group, solver, wg, 0, 0.0, 0.0)
+
+
+def test_serve_tune_table(dev):
+    """A session given a tune table runs every stream with its entry's launch
+    choices: tile, ring depth and XCD grouping of the sums are bit-exact with
+    the defaults; another solver gives identical masks and statistics within
+    its accuracy (1e-12 for the per-lane Jacobi, whose FP64 refinement is
+    exact to rounding; 1e-10 for the FP32 wave Jacobi, whose lambda_1 is the
+    FP64 Rayleigh quotient of its FP32 vector, error quadratic in that
+    vector's). Entries outside the allowed ranges fail rfi_stream_open."""
+    from paper_2512_16278_amd import rfi
+    t = rfi.rfi_tune_table()
+    ents = [_entry(2, 15, stages=2, group=512, solver=rfi.RFI_EIG_LANE, wg=64),
+            _entry(16, 31, tile=2, stages=3, group=4096, solver=rfi.RFI_EIG_LANE_TRI, wg=128),
+            _entry(32, 47, group=256, solver=rfi.RFI_EIG_WAVE)]
+    t.n = len(ents)
+    for i, e in enumerate(ents):
+        t.e[i] = e
+    data = [_blocks(dev, spec, 80 + i) for i, spec in enumerate(STREAMS)]
+    res = []
+    for table in (None, t):
+        say("serve: tune table", table is not None)
+        with rfi.Session(max_inflight=4, tune=table) as s:
+            sids = [s.open_stream(nb, nc, L) for nb, nc, L, _ in STREAMS]
+            tickets = [_run(s, sid, bufs, spec[1])
+                       for sid, spec, (x, bufs) in zip(sids, STREAMS, data)]
+            res.append([_collect(s, tk) for tk in tickets])
+    for j, (nb, nc, L, _) in enumerate(STREAMS):
+        same_solver = nb >= 16 and nb <= 31      # LANE_TRI is the default there
+        for a, m in zip(res[0][j], res[1][j]):
+            assert a[:3] == m[:3], nb
+            sa, sm = a[3][0], m[3][0]
+            if same_solver:
+                assert np.array_equal(sa, sm), nb
+            else:
+                assert np.abs(sa - sm).max() <= (1e-12 if nb <= 20 else 1e-10), nb
+            assert np.array_equal(a[3][1], m[3][1]), nb
+            assert np.array_equal(a[3][2], m[3][2]), nb
+    # out-of-range entries are rejected when a stream of that shape opens
+    for bad in (_entry(2, 79, tile=1), _entry(2, 79, wg=96), _entry(2, 79, stages=5),
+                _entry(2, 79, solver=rfi.RFI_EIG_LANE)):
+        tb = rfi.rfi_tune_table()
+        tb.n = 1
+        tb.e[0] = bad
+        with rfi.Session(max_inflight=1, tune=tb) as s:
+            with pytest.raises(rfi.RfiError) as ei:
+                s.open_stream(36, 40, 300)
+            assert ei.value.code == rfi.RFI_E_INVALID
