@@ -23,6 +23,14 @@
 // (sigma - lambda_2) / (sigma - lambda_3), so a lambda_2 within the shift
 // distance of lambda_1 (where one vector of inverse iteration would stall and
 // its Rayleigh quotient miss lambda_1 by up to the gap) costs nothing.
+//
+// The kernels are bound by the latency of reading the cell's raw sums, not by
+// arithmetic: loads are unconditional (padding reads a clamped valid address
+// and is zeroed by its scale factor, so the compiler cannot sink a load into
+// a branch that waits for it alone) and issued in large groups, and the
+// Householder and refinement kernels run one wave per SIMD so that their
+// register overflow goes to AGPRs: a scratch reload would wait for every
+// load in flight.
 #include <float.h>
 #include <math.h>
 
@@ -52,6 +60,53 @@ struct Sym {
   }
 };
 
+// Rows of the strict upper triangle are read in groups of about G loads: row a
+// opens a group when the rows since the last group start hold >= G entries.
+// A fence at each group start bounds the raw sums in flight, while the loads
+// of one group overlap a single memory round trip.
+template <int N, int G>
+__device__ __forceinline__ constexpr bool row_group_start(int a) {
+  int acc = 0;
+  for (int k = 0; k < a; ++k) {
+    acc += N - 1 - k;
+    if (acc >= G) acc = 0;
+  }
+  return acc == 0;
+}
+constexpr int kRowGroup = 48;
+
+// Entry of this lane's cell in row `row` of a [rows][ncell] int32 array: a
+// wave-uniform row address plus the lane's 32-bit byte offset off4 = 4 cell,
+// which the load takes as a scalar base and one offset register (the launch
+// checks ncell <= 2^30). A 64-bit per-lane address would hold two more
+// registers for every load in flight.
+__device__ __forceinline__ int32_t lane_row(const int32_t* base, int64_t row, int64_t ncell,
+                                            uint32_t off4) {
+  return *(const int32_t*)((const char*)(base + row * ncell) + off4);
+}
+
+// Entry k of the strict upper triangle of an N x N matrix in row order:
+// (0,1), (0,2), ..., (0,N-1), (1,2), ...
+template <int N>
+struct UpperPair {
+  static constexpr int row(int k) {
+    int a = 0;
+    while (k >= N - 1 - a) {
+      k -= N - 1 - a;
+      ++a;
+    }
+    return a;
+  }
+  static constexpr int col(int k) {
+    int a = 0;
+    while (k >= N - 1 - a) {
+      k -= N - 1 - a;
+      ++a;
+    }
+    return a + 1 + k;
+  }
+};
+
 __device__ __forceinline__ int64_t pidx(int a, int b, int n) {
   return (int64_t)a * n - (int64_t)a * (a - 1) / 2 + (b - a);
 }
@@ -66,30 +121,33 @@ __device__ __forceinline__ void load_corr32(const EigArgs& g, int64_t ncell, int
   // N_ab = cnt S_ab - S_a S_b is formed exactly in FP64: cnt S_ab < 2^47 and
   // S_a S_b < 2^48 are integers held exactly, and the FMA's one rounding is
   // exact too (|N_ab| < 2^48 < 2^53) -- cheaper than int64 arithmetic.
-  double Sd[N];
+  int32_t S[N];
   float dinv[N];
   degenerate = false;
   const double cd = (double)cnt;
+  const uint32_t off4 = (uint32_t)cell * 4u;
   static_for<0, N>([&](auto Ai) {
     constexpr int a = RFI_CI(Ai);
     const int aa = a < n ? a : 0;                    // clamped: always a valid address
-    Sd[a] = (double)g.sum_x[aa * ncell + cell];
-    const double Saa = (double)g.sum_xy[pidx(aa, aa, n) * ncell + cell];
-    const double Naa = fma(cd, Saa, -Sd[a] * Sd[a]);
+    S[a] = lane_row(g.sum_x, aa, ncell, off4);
+    const double Sa = (double)S[a];
+    const double Saa = (double)lane_row(g.sum_xy, pidx(aa, aa, n), ncell, off4);
+    const double Naa = fma(cd, Saa, -Sa * Sa);
     dinv[a] = (a < n && Naa > 0.0) ? __builtin_amdgcn_rsqf((float)Naa) : 0.f;
     degenerate |= (a < n && Naa <= 0.0);
     A[Sym<N>::idx(a, a)] = 1.0f;
   });
-  // one row at a time, so that only a row's raw sums are in flight at once
   static_for<0, N>([&](auto Ai) {
     constexpr int a = RFI_CI(Ai);
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (row_group_start<N, kRowGroup>(a)) __builtin_amdgcn_sched_barrier(0);
     static_for<a + 1, N>([&](auto Bi) {
       constexpr int b = RFI_CI(Bi);
       const int64_t p = b < n ? pidx(a, b, n) : 0;   // b < n implies a < n
-      const double Sab = (double)g.sum_xy[p * ncell + cell];
-      const double Nab = fma(cd, Sab, -Sd[a] * Sd[b]);
-      A[Sym<N>::idx(a, b)] = b < n ? (float)Nab * dinv[a] * dinv[b] : 0.f;
+      const double Sab = (double)lane_row(g.sum_xy, p, ncell, off4);
+      const double Nab = fma(cd, Sab, -(double)S[a] * (double)S[b]);
+      // no select on b < n: padding has dinv[b] = 0, and + 0 turns its -0
+      // into +0, so the load stays unconditional and is issued with its group
+      A[Sym<N>::idx(a, b)] = (float)Nab * dinv[a] * dinv[b] + 0.0f;
     });
   });
 }
@@ -476,45 +534,62 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
   // span(v, u): H = [v u]^T C [v u] and the Gram matrix of (v, u)
   double f2 = 0.0, h11 = 0.0, h12 = 0.0, h22 = 0.0, gvv = 0.0, gvu = 0.0, guu = 0.0;
   {
-    int32_t S[N];
+    const uint32_t off4 = (uint32_t)cell * 4u;
+    // Branch-free, and the loads of each group are issued together before
+    // any is used: padding indices (>= n) read a clamped valid address and
+    // get d = 0 (v = u = 0 there too), which zeroes their terms. N_ab =
+    // cnt S_ab - S_a S_b is exact in FP64 (as in load_corr32).
+    const double cd = (double)cnt;
+    int32_t S[N], Sdg[N];
     double d[N], vd[N], ud[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-      S[a] = 0;
-      d[a] = 0.0;
+    static_for<0, N>([&](auto Ai) {
+      constexpr int a = RFI_CI(Ai);
+      const int aa = a < n ? a : 0;
+      S[a] = lane_row(g.sum_x, aa, ncell, off4);
+      Sdg[a] = lane_row(g.sum_xy, pidx(aa, aa, n), ncell, off4);
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    static_for<0, N>([&](auto Ai) {
+      constexpr int a = RFI_CI(Ai);
+      const double Sa = (double)S[a];
+      const double Naa = fma(cd, (double)Sdg[a], -Sa * Sa);
+      d[a] = (a < n && Naa > 0.0) ? 1.0 / sqrt(Naa) : 0.0;
       vd[a] = have_v ? (double)v[a] : 0.0;
       ud[a] = have_v ? (double)u[a] : 0.0;
-      if (a < n) {
-        S[a] = g.sum_x[a * ncell + cell];
-        const int64_t Saa = g.sum_xy[pidx(a, a, n) * ncell + cell];
-        const int64_t Naa = cnt * Saa - (int64_t)S[a] * S[a];
-        d[a] = Naa > 0 ? 1.0 / sqrt((double)Naa) : 0.0;
-        h11 += vd[a] * vd[a];
-        h12 += vd[a] * ud[a];
-        h22 += ud[a] * ud[a];
-        f2 += 1.0;
-      }
-    }
+      h11 += vd[a] * vd[a];
+      h12 += vd[a] * ud[a];
+      h22 += ud[a] * ud[a];
+      f2 += a < n ? 1.0 : 0.0;
+    });
     gvv = h11;
     gvu = h12;
     guu = h22;
     double off = 0.0, o11 = 0.0, o12 = 0.0, o22 = 0.0;
-    // one row at a time, so that only a row's raw sums are in flight at once
-    static_for<0, N>([&](auto Ai) {
-      constexpr int a = RFI_CI(Ai);
-      __builtin_amdgcn_sched_barrier(0);
-      static_for<a + 1, N>([&](auto Bi) {
-        constexpr int b = RFI_CI(Bi);
-        if (b < n) {
-          const int64_t Sab = g.sum_xy[pidx(a, b, n) * ncell + cell];
-          const int64_t Nab = cnt * Sab - (int64_t)S[a] * S[b];
-          const double r = (double)Nab * d[a] * d[b];
-          off += r * r;
-          o11 += r * (vd[a] * vd[b]);
-          o12 += r * (vd[a] * ud[b] + ud[a] * vd[b]);
-          o22 += r * (ud[a] * ud[b]);
-        }
+    // strict upper triangle in row order, in groups of kGroup entries
+    constexpr int kPairs = N * (N - 1) / 2;
+    constexpr int kGroup = kRowGroup;
+    static_for<0, (kPairs + kGroup - 1) / kGroup>([&](auto Ci) {
+      constexpr int k0 = RFI_CI(Ci) * kGroup;
+      constexpr int k1 = k0 + kGroup < kPairs ? k0 + kGroup : kPairs;
+      int32_t R[kGroup];
+      static_for<k0, k1>([&](auto Ki) {
+        constexpr int k = RFI_CI(Ki);
+        constexpr int a = UpperPair<N>::row(k), b = UpperPair<N>::col(k);
+        const int64_t p = b < n ? pidx(a, b, n) : 0;   // b < n implies a < n
+        R[k - k0] = lane_row(g.sum_xy, p, ncell, off4);
       });
+      __builtin_amdgcn_sched_barrier(0);
+      static_for<k0, k1>([&](auto Ki) {
+        constexpr int k = RFI_CI(Ki);
+        constexpr int a = UpperPair<N>::row(k), b = UpperPair<N>::col(k);
+        const double Nab = fma(cd, (double)R[k - k0], -(double)S[a] * (double)S[b]);
+        const double r = Nab * d[a] * d[b];
+        off += r * r;
+        o11 += r * (vd[a] * vd[b]);
+        o12 += r * (vd[a] * ud[b] + ud[a] * vd[b]);
+        o22 += r * (ud[a] * ud[b]);
+      });
+      __builtin_amdgcn_sched_barrier(0);
     });
     f2 += 2.0 * off;
     h11 += 2.0 * o11;
@@ -591,13 +666,13 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
 }
 
 template <int N>
-__global__ __launch_bounds__(256, 2) void eig_lane_tri(EigArgs g) {
+__global__ __launch_bounds__(256, 1) void eig_lane_tri(EigArgs g) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell < (int64_t)g.nsub * g.nchan) lanetri_cell<N>(g, cell);
 }
 
 template <int N>
-__global__ __launch_bounds__(256, 2) void eig_lane_refine(EigArgs g) {
+__global__ __launch_bounds__(256, 1) void eig_lane_refine(EigArgs g) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell < (int64_t)g.nsub * g.nchan) refine_cell<N>(g, cell);
 }
@@ -625,7 +700,7 @@ __global__ __launch_bounds__(256) void eig_lane_jacobi_batch(const EigArgs* item
 }
 
 template <int N>
-__global__ __launch_bounds__(256, 2) void eig_lane_tri_batch(const EigArgs* items,
+__global__ __launch_bounds__(256, 1) void eig_lane_tri_batch(const EigArgs* items,
                                                           const int64_t* cell0, int nitem,
                                                           int64_t total) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -636,7 +711,7 @@ __global__ __launch_bounds__(256, 2) void eig_lane_tri_batch(const EigArgs* item
 }
 
 template <int N>
-__global__ __launch_bounds__(256, 2) void eig_lane_refine_batch(const EigArgs* items,
+__global__ __launch_bounds__(256, 1) void eig_lane_refine_batch(const EigArgs* items,
                                                              const int64_t* cell0, int nitem,
                                                              int64_t total) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
