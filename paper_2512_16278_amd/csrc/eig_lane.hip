@@ -660,7 +660,7 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void eig_lane_jacobi(EigArgs g) {
+__global__ __launch_bounds__(256, 2) void eig_lane_jacobi(EigArgs g) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell < (int64_t)g.nsub * g.nchan) jacobi_cell<N>(g, cell);
 }
@@ -689,7 +689,7 @@ __device__ __forceinline__ int find_item(const int64_t* cell0, int nitem, int64_
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void eig_lane_jacobi_batch(const EigArgs* items,
+__global__ __launch_bounds__(256, 2) void eig_lane_jacobi_batch(const EigArgs* items,
                                                              const int64_t* cell0, int nitem,
                                                              int64_t total) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
