@@ -176,3 +176,100 @@ def test_injected_common_signal_population_eigenvalue():
     # sampling error of lambda_1 is O(sqrt(n / L)) relative; allow 4 %
     assert abs(w[0] - lam_pop) / lam_pop < 0.04
     assert w[0] > 1 + 0.5 * (n - 1) * (u * u).min()
+
+
+# ---------------------------------------------------------------------------
+# Pins of cell_eigen's dominant eigenvector v1 (Sec. 3.3: the eigenvector of
+# the dominant eigenvalue feeds the per-beam stage) against closed forms.
+
+def _unit_with_sign(v):
+    """Normalise v and apply the sign convention independently of the oracle:
+    sum > 0, or, for a zero sum, the first non-zero component > 0."""
+    v = np.asarray(v, dtype=np.float64) / np.linalg.norm(v)
+    tot = float(v.sum())
+    first = v[np.flatnonzero(v)[0]]
+    if tot < 0 or (tot == 0 and first < 0):
+        v = -v
+    return v
+
+
+def test_v1_2x2_closed_form():
+    # [[1, rho], [rho, 1]]: lambda_1 = 1 + |rho| with v1 = (1, sign rho) / sqrt 2
+    rhos = np.array([-0.9, -0.3, 0.25, 0.99])
+    C = np.stack([np.array([[1.0, r], [r, 1.0]]) for r in rhos])
+    w, v1 = eig.cell_eigen(C)
+    for i, r in enumerate(rhos):
+        exp = np.array([1.0, math.copysign(1.0, r)]) / math.sqrt(2.0)
+        np.testing.assert_allclose(v1[i], exp, atol=1e-15)
+        assert abs(w[i, 0] - (1 + abs(r))) < 1e-15
+
+
+@pytest.mark.parametrize("n,rho", [(3, 0.5), (19, 0.3), (36, 0.05), (72, 0.9)])
+def test_v1_equicorrelation_is_uniform(n, rho):
+    # (1 - rho) I + rho 11^T, rho > 0: v1 = 1 / sqrt(n) (simple eigenvalue)
+    C = (1 - rho) * np.eye(n) + rho * np.ones((n, n))
+    _, v1 = eig.cell_eigen(C)
+    np.testing.assert_allclose(v1, np.full(n, 1.0 / math.sqrt(n)), atol=1e-13)
+
+
+def _secular_root(u):
+    lo = max(1 - u * u) + 1e-15
+    hi = 1 + (u * u).sum() + 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if (u * u / (mid - 1 + u * u)).sum() > 1:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+@pytest.mark.parametrize("n", [4, 19, 36])
+def test_v1_diag_plus_rank_one(n):
+    """C = I - diag(u^2) + u u^T: (C - lambda I) v = 0 gives
+    v_b = u_b (u.v) / (lambda - 1 + u_b^2), so v1 is proportional to
+    u_b / (lambda_1 - 1 + u_b^2). Unequal, mixed-sign u makes V non-symmetric
+    (a row taken for a column fails) and exercises the sign convention."""
+    rng = np.random.default_rng(20 + n)
+    for trial in range(4):
+        u = rng.uniform(0.1, 0.8, size=n) * np.where(rng.uniform(size=n) < 0.4, -1.0, 1.0)
+        if trial == 0:
+            u = -np.abs(u)            # sum of v1 negative before the convention
+        C = np.eye(n) - np.diag(u * u) + np.outer(u, u)
+        lam = _secular_root(u)
+        exp = _unit_with_sign(u / (lam - 1 + u * u))
+        w, v1 = eig.cell_eigen(C[None])
+        assert abs(w[0, 0] - lam) < 1e-12
+        np.testing.assert_allclose(v1[0], exp, atol=1e-12)
+        assert v1[0].sum() > 0
+
+
+def test_v1_worked_3x3_against_cross_product():
+    """Independent route for a 3x3: v1 spans the null space of C - lambda_1 I,
+    i.e. the cross product of two of its rows; lambda_1 from Smith's closed form."""
+    with open(os.path.join(GOLD, "worked_3x3.json")) as f:
+        g = json.load(f)
+    x = np.array(g["x"], dtype=np.uint8)[:, :, None]
+    S, S2 = ccm.sums_loops(x, g["L"], 1)
+    r, _ = ccm.correlation(S, S2, g["L"])
+    C = r[0, 0]
+    lam = smith_3x3(C)[0]
+    M = C - lam * np.eye(3)
+    cands = [np.cross(M[0], M[1]), np.cross(M[0], M[2]), np.cross(M[1], M[2])]
+    v = max(cands, key=np.linalg.norm)
+    exp = _unit_with_sign(v)
+    _, v1 = eig.cell_eigen(C[None])
+    np.testing.assert_allclose(v1[0], exp, atol=1e-12)
+    np.testing.assert_allclose(C @ v1[0], lam * v1[0], atol=1e-13)
+
+
+def test_v1_sign_convention_ties():
+    # two beams anti-correlated: v1 = (1, -1)/sqrt 2 has a zero sum, so the
+    # first non-zero component is made positive
+    C = np.array([[[1.0, -0.5], [-0.5, 1.0]]])
+    _, v1 = eig.cell_eigen(C)
+    np.testing.assert_allclose(v1[0], [1 / math.sqrt(2), -1 / math.sqrt(2)], atol=1e-15)
+    # block structure: v1 lives on beams 1, 2 only (beam 0 uncorrelated)
+    C = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, -0.8], [0.0, -0.8, 1.0]])
+    _, v1 = eig.cell_eigen(C[None])
+    np.testing.assert_allclose(v1[0], [0.0, 1 / math.sqrt(2), -1 / math.sqrt(2)], atol=1e-15)
