@@ -179,23 +179,39 @@ typedef struct {
  * (Sec. 3.3; kappa of Sec. 4.5; preserved ranges of Sec. 4.3). Eligible
  * cells: status without RFI_CELL_DEGENERATE / RFI_CELL_BAD_COUNT and channel
  * not protected (protect_chan[j] != 0; NULL = none). On the statistic
- * quantised to q = rint(stat * 2^40): mu = Q1 / (N 2^40),
- * sigma^2 = (N Q2 - Q1^2) / (N^2 2^80) from exact integer sums over the
- * eligible unmasked cells (pooled with *state when state != NULL), mask
- * every such cell with q * 2^-40 > mu + kappa sigma, repeat until a fit masks
- * nothing new or max_iter fits. mask[cell] = 1 for masked cells, else 0. If
- * state != NULL the block's final unmasked sums are folded into it and the
- * fit appended to its history. out (nullable) receives the summary
- * (iterations = -1 if the grid-wide kernel's bounded barrier gave up).
- * workspace: device scratch of rfi_flag_workspace_size() bytes, owned by the
- * caller and used by one call at a time; NULL = the library takes it from
- * the stream-ordered allocator for this call.
- * Errors: RFI_E_INVALID for bad sizes, kappa < 0 or max_iter < 1. */
+ * quantised to q = rint(stat * 2^40): mu = Q1 / (N 2^40) and
+ * sigma^2 = (N Q2 - Q1^2) / (N^2 2^80), each the exact rational of the integer
+ * sums over the eligible unmasked cells (pooled with *state when state !=
+ * NULL) rounded once to FP64, sigma its correctly rounded square root,
+ * thr = mu + kappa sigma (FP64 product and sum, no fused multiply-add); mask
+ * every such cell with q * 2^-40 > thr, repeat until a fit masks nothing new
+ * or max_iter fits. mask[cell] = 1 for masked cells, else 0. If state != NULL
+ * the block's final unmasked sums are folded into it and the fit appended to
+ * its history. out (nullable) receives the summary.
+ * workspace: device scratch of rfi_flag_workspace_size(nsub, nchan) bytes,
+ * 256-byte aligned, owned by the caller and used by one call at a time (it
+ * holds per-workgroup partial sums and the list of tail cells; the library
+ * allocates nothing). nsub = 0 runs an empty clip (no fit; a history entry
+ * with iterations 0 is still appended to *state).
+ * Errors: RFI_E_INVALID for bad sizes, kappa < 0, max_iter < 1, or a NULL or
+ * misaligned workspace. */
 size_t rfi_flag_workspace_size(int32_t nsub, int32_t nchan);
 rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8_t* status,
                     const uint8_t* protect_chan, double kappa, int32_t max_iter,
                     rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
                     void* workspace, rfi_stream_t stream);
+
+/* The clip's moment fit on its own (Sec. 3.3 Gaussian fit; the arithmetic
+ * rfi_flag applies at every iteration), for checking its rounding: for each
+ * i < n, from N[i] > 0 and the 128-bit sums Q1 = (Q1[2i], Q1[2i+1]) and
+ * Q2 = (Q2[2i], Q2[2i+1]) (little-endian 64-bit limbs, N Q2 >= Q1^2):
+ * mu[i] = Q1 / (N 2^40) and var = (N Q2 - Q1^2) / (N^2 2^80) rounded once to
+ * FP64, sigma[i] = sqrt(var) correctly rounded, thr[i] = mu + kappa sigma.
+ * N[i] <= 0 gives NaN. All arrays are device arrays of n entries.
+ * Errors: RFI_E_INVALID for n < 0, NULL arrays or kappa < 0. */
+rfi_status rfi_clip_fit(int32_t n, const int64_t* N, const uint64_t* Q1, const uint64_t* Q2,
+                        double kappa, double* mu, double* sigma, double* thr,
+                        rfi_stream_t stream);
 
 /* Per-beam eigenvector stage (Sec. 3.3 last paragraph; kappa_v of Sec. 4.5):
  * for each beam b, mu_b and sigma_b (population) of |v1_b| over eligible

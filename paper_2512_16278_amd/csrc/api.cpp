@@ -120,13 +120,8 @@ rfi_status rfi_ccm_accumulate(const rfi_block* blk, int64_t t0, int32_t L, int32
   hipStream_t s = (hipStream_t)stream;
   hipError_t e;
   if (v == RFI_CCM_MFMA) {
-    // tuning knob: RFI_CCM_SHARED=1 selects the tile of the pipelined path
-    static const int shared = [] {
-      const char* e = getenv("RFI_CCM_SHARED");
-      return e && atoi(e) == 1 ? 1 : 0;
-    }();
     e = rfi::launch_ccm_mfma(bp, n, blk->nchan, blk->row_stride, t0, L, nsub, sum_x, sum_xy,
-                             count, accumulate ? 1 : 0, shared, s);
+                             count, accumulate ? 1 : 0, 0, s);
   } else if (v == RFI_CCM_VALU) {
     if (n > 20) return fail(RFI_E_INVALID, "rfi_ccm_accumulate: VALU variant needs nbeam <= 20");
     e = rfi::launch_ccm_valu(bp, n, blk->nchan, blk->row_stride, t0, L, nsub, sum_x, sum_xy,
@@ -160,17 +155,12 @@ rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan, const int
   rfi::EigArgs a{nbeam, nsub, nchan, sum_x, sum_xy, count, prm.max_sweeps, prm.refine ? 1 : 0,
                  eigvals, stat, v1, status, (int64_t)nsub * nchan};
   hipStream_t s = (hipStream_t)stream;
-  // tuning knob: RFI_EIG_WG = cells per workgroup of the per-lane solver
-  static const int wg = [] {
-    const char* e = getenv("RFI_EIG_WG");
-    const int v = e ? atoi(e) : 256;
-    return v == 64 || v == 128 ? v : 256;
-  }();
-  return check_hip(rfi::launch_eig(a, prm, s, wg), "rfi_eig_batched launch");
+  return check_hip(rfi::launch_eig(a, prm, s, 256), "rfi_eig_batched launch");
 }
 
 size_t rfi_flag_workspace_size(int32_t nsub, int32_t nchan) {
-  return rfi::flag_workspace_size(nsub, nchan);
+  if (nsub < 0 || nchan < 1) return 0;
+  return rfi::clip_workspace_size((int64_t)nsub * nchan);
 }
 
 rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8_t* status,
@@ -179,19 +169,30 @@ rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8
                     void* workspace, rfi_stream_t stream) {
   rfi::clear_error();
   if (nsub < 0 || nchan < 1) return fail(RFI_E_INVALID, "rfi_flag: bad nsub/nchan");
-  if (!stat || !status || !mask) return fail(RFI_E_INVALID, "rfi_flag: NULL input or output");
+  if ((int64_t)nsub * nchan > (int64_t)1 << 30)
+    return fail(RFI_E_INVALID, "rfi_flag: nsub * nchan exceeds 2^30 cells");
+  if (nsub > 0 && (!stat || !status || !mask))
+    return fail(RFI_E_INVALID, "rfi_flag: NULL input or output");
   if (!(kappa >= 0.0)) return fail(RFI_E_INVALID, "rfi_flag: kappa must be >= 0");
   if (max_iter < 1) return fail(RFI_E_INVALID, "rfi_flag: max_iter %d < 1", max_iter);
-  hipStream_t s = (hipStream_t)stream;
-  void* ws = workspace;
-  if (!ws) {
-    const hipError_t e = hipMallocAsync(&ws, rfi::flag_workspace_size(nsub, nchan), s);
-    if (e != hipSuccess) return fail(RFI_E_NOMEM, "rfi_flag: workspace: %s", hipGetErrorString(e));
-  }
-  const hipError_t e = rfi::launch_flag(nsub, nchan, stat, status, protect_chan, kappa, max_iter,
-                                        state, mask, out, ws, s);
-  if (!workspace) (void)hipFreeAsync(ws, s);
-  return check_hip(e, "rfi_flag launch");
+  if (!workspace) return fail(RFI_E_INVALID, "rfi_flag: workspace is NULL");
+  if ((uintptr_t)workspace % 256 != 0)
+    return fail(RFI_E_INVALID, "rfi_flag: workspace not 256-byte aligned");
+  const rfi::ClipJob j = rfi::make_clip_job(nsub, nchan, stat, status, protect_chan, kappa,
+                                            max_iter, state, mask, out, workspace);
+  return check_hip(rfi::launch_clip(j, (hipStream_t)stream), "rfi_flag launch");
+}
+
+rfi_status rfi_clip_fit(int32_t n, const int64_t* N, const uint64_t* Q1, const uint64_t* Q2,
+                        double kappa, double* mu, double* sigma, double* thr,
+                        rfi_stream_t stream) {
+  rfi::clear_error();
+  if (n < 0) return fail(RFI_E_INVALID, "rfi_clip_fit: n %d < 0", n);
+  if (n > 0 && (!N || !Q1 || !Q2 || !mu || !sigma || !thr))
+    return fail(RFI_E_INVALID, "rfi_clip_fit: NULL array");
+  if (!(kappa >= 0.0)) return fail(RFI_E_INVALID, "rfi_clip_fit: kappa must be >= 0");
+  return check_hip(rfi::launch_fit(n, N, Q1, Q2, kappa, mu, sigma, thr, (hipStream_t)stream),
+                   "rfi_clip_fit launch");
 }
 
 rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const float* v1,

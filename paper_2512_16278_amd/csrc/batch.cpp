@@ -5,7 +5,7 @@
 // Workspace layout: one descriptor area, uploaded by one host-to-device copy,
 // then the sums of every block (sum_x, sum_xy, count; 256-byte aligned):
 //   [beam pointer tables][CcmItem x nitem][EigArgs x nitem][cell0 x (nitem +
-//   nclass)][FlagItem x nitem] | sums of item 0 | sums of item 1 | ...
+//   nclass)][ClipJob x nitem] | sums and clip workspace of item 0 | of item 1 | ...
 // Items are ordered by sums class for the sums launches (each class a
 // contiguous run of CcmItem sorted by first workgroup) and by solver class
 // for the eigen launches (each a contiguous run of EigArgs with ascending
@@ -40,6 +40,7 @@ struct ItemPlan {
   int lane_cls;            // template class of the per-lane or per-wave tridiagonal solver
   int wg;                  // per-lane solver workgroup
   size_t sums_off;         // byte offset of the item's sums in the workspace
+  size_t clip_off;         // byte offset of the item's clip workspace
 };
 
 struct EigClass {
@@ -69,6 +70,7 @@ struct BatchPlan {
   std::vector<CcmLaunchClass> ccm_classes;
   std::vector<EigClass> eig_classes;
   std::vector<char> host;  // descriptor bytes (device addresses resolved for ws)
+  std::vector<ClipJob> clip_jobs;  // host copy of the clip descriptors (grid sizes)
 };
 
 rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_params* p,
@@ -120,6 +122,17 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
     bpn->plans.push_back(ip);
   }
   const int n = (int)bpn->plans.size();
+  // items that share a stream state would race in the batched clip (one
+  // workgroup per block reads and writes the state at the same time)
+  {
+    std::vector<const rfi_stream_state*> st;
+    for (const ItemPlan& ip : bpn->plans)
+      if (items[ip.idx].state) st.push_back(items[ip.idx].state);
+    std::sort(st.begin(), st.end());
+    if (std::adjacent_find(st.begin(), st.end()) != st.end())
+      return fail(RFI_E_INVALID, "%s: two items share one stream state; run consecutive blocks "
+                  "of a stream in separate batches", who);
+  }
   // classes
   std::map<long long, std::vector<int>> ccm;
   // (solver template class or 0, solver, precision, workgroup)
@@ -150,12 +163,14 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
   bpn->cell0_off = o;
   o = up(o + (size_t)(n + bpn->eig_classes.size()) * sizeof(int64_t));
   bpn->flag_off = o;
-  o = up(o + (size_t)n * sizeof(FlagItem));
+  o = up(o + (size_t)n * sizeof(ClipJob));
   bpn->desc_bytes = o;
   for (ItemPlan& ip : bpn->plans) {
     ip.sums_off = o;
     o += up((size_t)ip.nbeam * ip.ncell * 4) + up((size_t)npair_of(ip.nbeam) * ip.ncell * 4) +
          up((size_t)items[ip.idx].nsub * 4);
+    ip.clip_off = o;
+    o += up(clip_workspace_size(ip.ncell));
   }
   bpn->ws_bytes = std::max<size_t>(o, kAlign);
   return RFI_OK;
@@ -226,12 +241,14 @@ void fill_descriptors(const rfi_batch_item* items, BatchPlan* bpn, char* ws) {
     }
     c0[cpos++] = cell;      // total of the class
   }
-  FlagItem* fi = (FlagItem*)(h.data() + bpn->flag_off);
+  ClipJob* fi = (ClipJob*)(h.data() + bpn->flag_off);
+  bpn->clip_jobs.resize(bpn->plans.size());
   for (size_t k = 0; k < bpn->plans.size(); ++k) {
     const ItemPlan& ip = bpn->plans[k];
     const rfi_batch_item& it = items[ip.idx];
-    fi[k] = FlagItem{it.nsub, ip.nchan, bpn->max_iter, 0, bpn->kappa, it.stat, it.status,
-                     it.protect_chan, it.state, it.mask, it.out};
+    fi[k] = make_clip_job(it.nsub, ip.nchan, it.stat, it.status, it.protect_chan, bpn->kappa,
+                          bpn->max_iter, it.state, it.mask, it.out, dptr(ip.clip_off));
+    bpn->clip_jobs[k] = fi[k];
   }
 }
 
@@ -287,7 +304,7 @@ hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipSt
   if (e == hipSuccess) e = enqueue_ccm(bpn, desc, ws, s);
   if (e == hipSuccess) e = enqueue_eig(bpn, desc, ws, s);
   if (e != hipSuccess) return e;
-  return launch_flag_batch((const FlagItem*)(ws + bpn.flag_off), n, s);
+  return launch_clip_batch((const ClipJob*)(ws + bpn.flag_off), bpn.clip_jobs.data(), n, s);
 }
 
 // Median time (ms) of three runs of fn on s after one warm-up; -1 on a

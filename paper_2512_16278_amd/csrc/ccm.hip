@@ -127,14 +127,9 @@ __device__ __forceinline__ void wait_chunk(int ahead) {
 }
 
 // Tiles per XCD group: 1 KB of contiguous row bytes by default (measured best
-// for the 4 KB-row FAST layout); RFI_CCM_GROUP_BYTES overrides.
+// for the 4 KB-row FAST layout); a tune entry may choose another size.
 int group_tiles(int cw, int group_bytes_override = 0) {
-  static const int group_bytes = [] {
-    const char* v = getenv("RFI_CCM_GROUP_BYTES");
-    const int g = v ? atoi(v) : 1024;
-    return g < 16 ? 16 : g;
-  }();
-  const int gb = group_bytes_override > 0 ? group_bytes_override : group_bytes;
+  const int gb = group_bytes_override > 0 ? group_bytes_override : 1024;
   return gb / cw > 1 ? gb / cw : 1;
 }
 
@@ -477,11 +472,7 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
   if (e != hipSuccess) return e;
   const int64_t ntiles = (int64_t)nsub * nct;
   const int G = group_tiles(CW, group_bytes);
-  // tuning knob: RFI_CCM_PRIO=1 raises the streaming waves' issue priority
-  static const int prio = [] {
-    const char* v = getenv("RFI_CCM_PRIO");
-    return v && atoi(v) == 1 ? 1 : 0;
-  }();
+  const int prio = 0;   // raised issue priority of the streaming waves measured no gain
   hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), C::LDS, s, bp, nbeam, nchan,
                      row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate, G, nh, prio,
                      layout, (const CcmItem*)nullptr, 0);
@@ -529,10 +520,6 @@ hipError_t ccm_dispatch(int nbeam, int shared_cu, Op& op, const CcmTune* t = nul
   // tile shape per block count: (CW channels, CPW channels per wave). With
   // shared_cu the 19-beam tile is 32 channels on 8 waves of ~120 VGPRs.
   int cw, cpw;
-  static const int cpw2 = [] {
-    const char* e = getenv("RFI_CCM_CPW");
-    return e && atoi(e) == 4 ? 4 : 8;
-  }();
   const int tile = t ? t->tile : 0;
   if (tile < 0 || tile >= ccm_tile_variants(nbeam)) return hipErrorInvalidValue;
   switch (nb) {
@@ -540,19 +527,14 @@ hipError_t ccm_dispatch(int nbeam, int shared_cu, Op& op, const CcmTune* t = nul
     case 2:
       if (tile == 1) { cw = 64; cpw = 4; }
       else if (tile == 2 || shared_cu) { cw = 32; cpw = 4; }
-      else { cw = 64; cpw = cpw2; }
+      else { cw = 64; cpw = 8; }
       break;
     case 3: cw = 32; cpw = 4; break;
     case 4: case 5: cw = 16; cpw = 2; break;
     default: return hipErrorInvalidValue;
   }
-  // ring depth cap (tuning knob; default: the largest ring that fits)
-  static const int env_stages = [] {
-    const char* e = getenv("RFI_CCM_STAGES");
-    const int v = e ? atoi(e) : 4;
-    return v < 2 ? 2 : v;
-  }();
-  const int max_stages = t && t->stages >= 2 ? t->stages : env_stages;
+  // ring depth cap (a tune entry's choice; default: the largest ring that fits)
+  const int max_stages = t && t->stages >= 2 ? t->stages : 4;
   const int nwave = cw / cpw;
   const int units = nbeam * 32 * (cw / 16);        // 16-byte units per chunk
   const int ipw = (units + 64 * nwave - 1) / (64 * nwave);  // loads per wave per chunk

@@ -96,10 +96,11 @@ int eig_tri_class(int n);
 hipError_t launch_eig_tri_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
                                 int64_t total, hipStream_t s);
 
-size_t flag_workspace_size(int nsub, int nchan);
-// One block of a batched clip (device descriptor); one workgroup per block.
-struct FlagItem {
-  int32_t nsub, nchan, max_iter, pad;
+// One clip problem (device descriptor): the cells of one block, its outputs
+// and its workspace (clip_workspace_size bytes, 256-byte aligned, holding at
+// most tail_cap tail entries).
+struct ClipJob {
+  int32_t nsub, nchan, max_iter, nparts;
   double kappa;
   const double* stat;
   const uint8_t* status;
@@ -107,12 +108,29 @@ struct FlagItem {
   rfi_stream_state* state;
   uint8_t* mask;
   rfi_flag_stats* out;
+  void* ws;
+  int64_t tail_cap;
 };
-hipError_t launch_flag_batch(const FlagItem* items, int nitem, hipStream_t s);
-hipError_t launch_flag(int nsub, int nchan, const double* stat, const uint8_t* status,
-                       const uint8_t* protect_chan, double kappa, int max_iter,
-                       rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
-                       void* workspace, hipStream_t s);
+// Tail capacity the library gives a block of ncell cells, and the workspace
+// bytes for it (or for an explicit capacity).
+int64_t clip_tail_cap(int64_t ncell);
+size_t clip_workspace_size(int64_t ncell);
+size_t clip_workspace_size_for_cap(int64_t tail_cap);
+// Descriptor with the scan's workgroup count filled in (tail_cap 0: the
+// default capacity for the block).
+ClipJob make_clip_job(int nsub, int nchan, const double* stat, const uint8_t* status,
+                      const uint8_t* protect_chan, double kappa, int max_iter,
+                      rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out, void* ws,
+                      int64_t tail_cap = 0);
+// The clip of one block (four launches on s).
+hipError_t launch_clip(const ClipJob& j, hipStream_t s);
+// The clips of n blocks: jobs in device memory, host_jobs the same
+// descriptors on the host (grid sizes).
+hipError_t launch_clip_batch(const ClipJob* jobs, const ClipJob* host_jobs, int n, hipStream_t s);
+// The clip's exact fit for given moment sums (device arrays of n entries;
+// Q1, Q2 as little-endian 64-bit limb pairs).
+hipError_t launch_fit(int n, const int64_t* N, const uint64_t* Q1, const uint64_t* Q2,
+                      double kappa, double* mu, double* sigma, double* thr, hipStream_t s);
 hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float* v1,
                               const uint8_t* mask, const uint8_t* status,
                               const uint8_t* protect_chan, double kappa_v,

@@ -44,26 +44,6 @@ size_t slot_bytes(int nbeam, int nchan, int group) {
   return up(cells * nbeam * 4) + up(cells * npair_of(nbeam) * 4) + up((size_t)group * 4);
 }
 
-// tuning knobs: RFI_PIPE_EIG_WG = cells per workgroup of the per-lane solver;
-// RFI_PIPE_SHARED=1 selects the narrow CCM tile that leaves register room for
-// a solver wave on every SIMD (for experiments with overlapped groups).
-int lane_wg() {
-  static const int wg = [] {
-    const char* e = getenv("RFI_PIPE_EIG_WG");
-    const int v = e ? atoi(e) : 256;
-    return v == 64 || v == 128 ? v : 256;
-  }();
-  return wg;
-}
-
-int shared_tile() {
-  static const int v = [] {
-    const char* e = getenv("RFI_PIPE_SHARED");
-    return e && atoi(e) == 1 ? 1 : 0;
-  }();
-  return v;
-}
-
 }  // namespace
 
 rfi_status resolve_process(int nbeam, int nchan, const rfi_process_params* p, ProcessPlan* pl,
@@ -89,7 +69,7 @@ rfi_status resolve_process(int nbeam, int nchan, const rfi_process_params* p, Pr
                        : auto_group(nbeam, nchan, p->nsub);
   pl->max_iter = p->max_iter ? p->max_iter : 50;
   pl->kappa = p->kappa;
-  pl->flag_ws = up(flag_workspace_size(p->nsub, nchan));
+  pl->flag_ws = up(clip_workspace_size((int64_t)p->nsub * nchan));
   pl->slot = slot_bytes(nbeam, nchan, pl->group);
   const int ngroup = (p->nsub + pl->group - 1) / pl->group;
   pl->nslot = ngroup < kRing ? (ngroup < 1 ? 1 : ngroup) : kRing;
@@ -147,7 +127,7 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
     // the per-wave tridiagonal solver reads one cell record per wave
     const int layout = pl.eig.solver == RFI_EIG_TRIDIAG ? 1 : 0;
     e = launch_ccm_mfma(bp, pl.nbeam, pl.nchan, row_stride, t0 + (int64_t)k0 * L, L, ks, sx, sxy,
-                        cnt, 0, shared_tile(), s, &pl.ct, layout);
+                        cnt, 0, 0, s, &pl.ct, layout);
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ev.ccm[slot], s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(ev.aux, ev.ccm[slot], 0)) != hipSuccess) return e;
@@ -155,7 +135,7 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
     EigArgs a{pl.nbeam, ks, pl.nchan, sx, sxy, cnt, pl.eig.max_sweeps, 1,
               eigvals ? eigvals + off : nullptr, stat + off, v1 ? v1 + off : nullptr,
               status + off, out_stride, layout};
-    e = launch_eig(a, pl.eig, ev.aux, pl.eig_wg ? pl.eig_wg : lane_wg());
+    e = launch_eig(a, pl.eig, ev.aux, pl.eig_wg ? pl.eig_wg : 256);
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ev.eig[slot], ev.aux)) != hipSuccess) return e;
   }
@@ -215,8 +195,9 @@ rfi_status rfi_process_block(const rfi_block* blk, const rfi_process_params* p,
   e = rfi::enqueue_eig_groups(bp, blk->row_stride, p->t0, p->L, pl, stat, status, eigvals, v1,
                               ncell, (char*)workspace + pl.flag_ws, ev, s);
   if (e != hipSuccess) return rfi::check_hip(e, "rfi_process_block: sums / eigen launch");
-  e = rfi::launch_flag(pl.nsub, pl.nchan, stat, status, protect_chan, pl.kappa, pl.max_iter,
-                       state, mask, out, workspace, s);
+  const rfi::ClipJob cj = rfi::make_clip_job(pl.nsub, pl.nchan, stat, status, protect_chan,
+                                             pl.kappa, pl.max_iter, state, mask, out, workspace);
+  e = rfi::launch_clip(cj, s);
   return rfi::check_hip(e, "rfi_process_block: clip launch");
 }
 

@@ -136,12 +136,6 @@ struct rfi_session {
   int next_stream = 1;
   rfi::Clock::time_point t0;
   hipStream_t free_stream = nullptr;  // stream-ordered frees of released memory
-  // The clip kernel is grid-wide (all its workgroups co-resident, meeting at
-  // a grid barrier): two of them running at once could each hold part of the
-  // device and wait for the other. Clip launches of all slots are therefore
-  // chained through this event, in admission order.
-  hipEvent_t flag_chain = nullptr;
-  bool flag_chain_used = false;
 
   double now_us() const {
     return std::chrono::duration<double, std::micro>(rfi::Clock::now() - t0).count();
@@ -197,9 +191,11 @@ rfi_status plan_block(const StreamCtx& st, int64_t nsamp, BlockPlan* b, const ch
   p.max_sweeps = st.cfg.max_sweeps;
   p.max_iter = st.cfg.max_iter;
   p.kappa = st.cfg.kappa;
-  // the clip covers nsub rows; its workspace does not depend on the size
   rfi_status s = resolve_process(st.cfg.nbeam, st.cfg.nchan, &p, &b->pl, who, st.tune());
   if (s != RFI_OK) return s;
+  // the clip covers all nsub rows (the carried one included)
+  b->pl.flag_ws = up(clip_workspace_size((int64_t)b->nsub * st.cfg.nchan));
+  b->pl.ws_bytes = b->pl.flag_ws + (size_t)b->pl.nslot * b->pl.slot;
   b->ws = b->pl.ws_bytes;
   const size_t ncell = (size_t)b->nsub * st.cfg.nchan;
   b->res = ncell ? up(ncell * 8) + up(ncell) + up(ncell) : 0;
@@ -273,15 +269,12 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
                         st.carry_sx(), st.carry_sxy(), st.carry_cnt(), 0, 0, s, &b.pl.ct);
     if (e != hipSuccess) return dev(e, "rfi_submit: new carry");
   }
-  // 4. clip, pooled with the stream state (after the previous clip of any slot)
+  // 4. clip, pooled with the stream state
   if (b.nsub > 0) {
-    if (flag_chain_used && (e = hipStreamWaitEvent(s, flag_chain, 0)) != hipSuccess)
-      return dev(e, "rfi_submit: clip order");
-    e = launch_flag(b.nsub, F, r->stat, r->cstat, st.protect, st.cfg.kappa, b.pl.max_iter,
-                    st.state, r->mask, sl.dstats, sl.ws, s);
+    const ClipJob cj = make_clip_job(b.nsub, F, r->stat, r->cstat, st.protect, st.cfg.kappa,
+                                     b.pl.max_iter, st.state, r->mask, sl.dstats, sl.ws);
+    e = launch_clip(cj, s);
     if (e != hipSuccess) return dev(e, "rfi_submit: clip");
-    if ((e = hipEventRecord(flag_chain, s)) != hipSuccess) return dev(e, "rfi_submit: clip order");
-    flag_chain_used = true;
     if ((e = hipMemcpyAsync(sl.hstats, sl.dstats, sizeof(rfi_flag_stats), hipMemcpyDeviceToHost,
                             s)) != hipSuccess)
       return dev(e, "rfi_submit: clip summary");
@@ -441,8 +434,7 @@ rfi_status rfi_session_create(const rfi_session_config* cfg, rfi_session** out) 
       return rfi::check_hip(e, "rfi_session_create: slot");
     }
   }
-  if ((e = hipStreamCreateWithFlags(&s->free_stream, hipStreamNonBlocking)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&s->flag_chain, hipEventDisableTiming)) != hipSuccess) {
+  if ((e = hipStreamCreateWithFlags(&s->free_stream, hipStreamNonBlocking)) != hipSuccess) {
     rfi_session_destroy(s.release());
     return rfi::check_hip(e, "rfi_session_create: stream");
   }
@@ -487,7 +479,6 @@ void rfi_session_destroy(rfi_session* s) {
     if (sl.s) (void)hipStreamDestroy(sl.s);
   }
   if (s->free_stream) (void)hipStreamDestroy(s->free_stream);
-  if (s->flag_chain) (void)hipEventDestroy(s->flag_chain);
   delete s;
 }
 

@@ -153,6 +153,7 @@ def lib():
         L.rfi_flag.argtypes = [i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp]
         L.rfi_flag_workspace_size.argtypes = [i32, i32]
         L.rfi_flag_workspace_size.restype = C.c_size_t
+        L.rfi_clip_fit.argtypes = [i32, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.rfi_process_workspace_size.argtypes = [i32, i32, C.POINTER(rfi_process_params)]
         L.rfi_process_workspace_size.restype = C.c_size_t
@@ -186,7 +187,8 @@ def lib():
         L.rfi_batch_graph_destroy.restype = None
         L.rfi_stream_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
         L.rfi_stream_import.argtypes = [vp, i32, vp, C.c_size_t]
-        for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_eigvec_flag",
+        for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_clip_fit",
+                  "rfi_eigvec_flag",
                   "rfi_process_block", "rfi_session_create", "rfi_stream_open",
                   "rfi_stream_close", "rfi_submit", "rfi_poll", "rfi_wait", "rfi_cancel",
                   "rfi_result_release", "rfi_stream_export", "rfi_stream_import",
@@ -264,11 +266,30 @@ def rfi_flag_workspace_size(nsub, nchan):
     return int(lib().rfi_flag_workspace_size(int(nsub), int(nchan)))
 
 
+def flag_workspace(nsub, nchan, device="cuda"):
+    """A device buffer of rfi_flag_workspace_size bytes (torch's allocator
+    aligns it to 256 bytes)."""
+    import torch
+    return torch.empty(max(rfi_flag_workspace_size(nsub, nchan), 1), dtype=torch.uint8,
+                       device=device)
+
+
 def rfi_flag(nsub, nchan, stat, status, mask, protect_chan=None, kappa=3.0, max_iter=50,
              state=None, out=None, workspace=None, stream=None):
+    """rfi_flag; workspace=None takes a buffer from torch for this call (the
+    library itself allocates nothing)."""
+    if workspace is None:
+        workspace = flag_workspace(nsub, nchan, stat.device)
     _check(lib().rfi_flag(int(nsub), int(nchan), _ptr(stat), _ptr(status), _ptr(protect_chan),
                           float(kappa), int(max_iter), _ptr(state), _ptr(mask), _ptr(out),
                           _ptr(workspace), _stream(stream)))
+
+
+def rfi_clip_fit(N, Q1, Q2, mu, sigma, thr, kappa=3.0, stream=None):
+    """The clip's exact moment fit on device arrays (N int64 [n]; Q1, Q2
+    uint64-as-int64 [n, 2] limb pairs; mu, sigma, thr float64 [n])."""
+    _check(lib().rfi_clip_fit(int(N.numel()), _ptr(N), _ptr(Q1), _ptr(Q2), float(kappa), _ptr(mu),
+                              _ptr(sigma), _ptr(thr), _stream(stream)))
 
 
 def process_params(L, nsub, t0=0, group=0, eig_precision=32, max_sweeps=12, max_iter=50,

@@ -12,15 +12,16 @@ The oracle cannot process all 405,504 cells in a test, so:
 * over every cell, properties that hold at any size: the statistic lies in
   [1/n, 1]; the mask is exactly {eligible cells with q > thr} for the
   reported fit; the reported fit is the exact moment fit of the unmasked
-  eligible cells (recomputed here with Python integers); the clip reached
-  its fixed point.
+  eligible cells (recomputed here with Python integers, bit-equal); the clip
+  reached its fixed point; and the oracle's clip over all 405,504 GPU
+  statistics gives the same mask, fits and iteration count.
 """
 import math
 
 import numpy as np
 import pytest
 
-from oracle import ccm, pipeline
+from oracle import ccm, clip, pipeline
 from gpu_util import packed_oracle_sums, say
 
 pytestmark = pytest.mark.gpu
@@ -95,9 +96,14 @@ def test_fullsize_process_block(fast):
     assert fs["nfit"] == N
     mu = Q1 / (N << 40)
     var = (N * Q2 - Q1 * Q1) / ((N * N) << 80)
-    assert abs(fs["mu"] - mu) <= 1e-13 * mu
-    assert abs(fs["sigma"] - math.sqrt(var)) <= 1e-12 * math.sqrt(var)
-    assert abs(fs["thr"] - (mu + 3.0 * math.sqrt(var))) <= 1e-12 * fs["thr"]
+    assert fs["mu"] == mu and fs["sigma"] == math.sqrt(var)       # one rounding each
+    assert fs["thr"] == mu + 3.0 * math.sqrt(var)
+    # the oracle's clip over every cell's GPU statistic: the same mask and fits
+    say("full size: oracle clip over all cells")
+    ref = clip.clip_iterative(s.ravel(), elig.ravel(), 3.0, 50)
+    assert np.array_equal(m.ravel(), ref.mask)
+    assert (fs["mu"], fs["sigma"], fs["thr"], fs["iterations"], fs["nflag"]) == \
+        (ref.mu, ref.sigma, ref.thr, ref.iterations, ref.nflag)
     # fixed point: the last fit masks nothing new
     assert (q[elig & ~m] * 2.0 ** -40 <= fs["thr"]).all()
     # every injected common-mode channel is masked in most sub-intervals

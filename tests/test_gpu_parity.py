@@ -10,6 +10,8 @@ Tolerances (derived from the arithmetic of each step):
   FP64 Jacobi: 1e-12.
 * masks: identical (both sides decide s_q > thr in FP64).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -317,7 +319,80 @@ def test_flag_matches_oracle(dev, seed):
         assert st["iterations"] == ref.iterations and bool(st["converged"]) == ref.converged
         assert st["nflag"] == ref.nflag
         for k in ("mu", "sigma", "thr"):
-            assert abs(st[k] - getattr(ref, k)) <= 1e-13 * abs(getattr(ref, k)), k
+            assert st[k] == getattr(ref, k), k          # bit-equal: one rounding each
+
+
+def _same(a, b):
+    return a == b or (math.isnan(a) and math.isnan(b))
+
+
+def test_clip_fit_rounding(dev):
+    """The clip's fit, mu = Q1 / (N 2^40) and sigma = sqrt((N Q2 - Q1^2) /
+    (N^2 2^80)) each rounded once and thr = mu + kappa sigma, against the same
+    arithmetic on Python integers (exact rationals, one rounding each), on
+    random moment sums spanning N = 1 .. 2^40 and every exponent the clip
+    meets, plus hand-made ties and binade edges."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    rng = np.random.default_rng(77)
+    cases = []
+    for _ in range(4000):
+        N = int(2 ** rng.uniform(0, 40))
+        qmax = int(2 ** rng.uniform(1, 41))
+        Q1 = int(rng.integers(0, 2 ** 62)) * N % (N * qmax + 1)
+        lo = -(-Q1 * Q1 // N)                      # ceil(Q1^2 / N): N Q2 >= Q1^2
+        extra = int(2 ** rng.uniform(0, 80)) if rng.uniform() < 0.9 else 0
+        cases.append((N, Q1, lo + extra))
+    # exact small ratios, power-of-two boundaries, equal values (sigma 0)
+    cases += [(1, 0, 0), (1, 1 << 40, 1 << 80), (3, 1, 1), (2, 3, 5), (7, 7 << 39, 7 << 78),
+              (1 << 20, (1 << 20) * 12345, (1 << 20) * 12345 ** 2), (5, 2 ** 41 - 1, 2 ** 82),
+              (2, 0, 2 ** 81), (2, 0, 2 ** 83), (4, 4 << 38, 2 ** 80 + 8), (3, 2 ** 41 + 1, 2 ** 83)]
+    n = len(cases)
+    N = torch.tensor([c[0] for c in cases], dtype=torch.int64, device=dev)
+    limbs = lambda v: [v & (2 ** 64 - 1), v >> 64]
+    as_i64 = lambda a: np.array(a, dtype=np.uint64).view(np.int64)
+    Q1 = torch.from_numpy(as_i64([limbs(c[1]) for c in cases])).to(dev)
+    Q2 = torch.from_numpy(as_i64([limbs(c[2]) for c in cases])).to(dev)
+    mu = torch.empty(n, dtype=torch.float64, device=dev)
+    sg = torch.empty_like(mu)
+    th = torch.empty_like(mu)
+    say("clip fit", n)
+    for kappa in (3.0, 1.7):
+        rfi.rfi_clip_fit(N, Q1, Q2, mu, sg, th, kappa=kappa)
+        torch.cuda.synchronize()
+        gm, gs, gt = mu.cpu().numpy(), sg.cpu().numpy(), th.cpu().numpy()
+        for i, (a, b, c) in enumerate(cases):
+            m, s_ = clip.moments_from_sums(a, b, c)
+            t = m + kappa * s_
+            assert (gm[i], gs[i], gt[i]) == (m, s_, t), (i, a, b, c, kappa)
+
+
+def test_flag_fallback_and_large_tail(dev):
+    """Blocks where the sampled prediction of the final threshold is wrong
+    (the sampled cells run higher than the rest, so the exact iteration falls
+    below the predicted tail bound and takes its full passes), and where the
+    tail is too long for registers: both must equal the oracle exactly."""
+    rng = np.random.default_rng(500)
+    nsub, nchan = 40, 1500                         # 60000 cells > the 16384-cell sample
+    ncell = nsub * nchan
+    ns = 16384
+    sampled = (np.arange(ns, dtype=np.int64) * ncell) // ns
+    s = 0.070 + 0.002 * rng.standard_normal(ncell)
+    s[sampled] += 0.02                             # the sample sees a shifted population
+    s = np.clip(s, 1 / 19, 1.0)
+    status = np.zeros(ncell, np.uint8)
+    mask, st = _flag_case(dev, s, status, nsub, nchan)
+    ref = clip.clip_iterative(s, status == 0, 3.0, 50)
+    assert np.array_equal(mask, ref.mask)
+    assert (st["mu"], st["sigma"], st["thr"], st["iterations"]) == \
+        (ref.mu, ref.sigma, ref.thr, ref.iterations)
+    # a 45 % outlier population: the tail list outgrows the registers
+    s = _synthetic_stat(rng, 200000, 0.45)
+    mask, st = _flag_case(dev, s, np.zeros(s.size, np.uint8), 100, 2000)
+    ref = clip.clip_iterative(s, np.ones(s.size, bool), 3.0, 50)
+    assert np.array_equal(mask, ref.mask)
+    assert (st["mu"], st["sigma"], st["thr"], st["iterations"], st["nflag"]) == \
+        (ref.mu, ref.sigma, ref.thr, ref.iterations, ref.nflag)
 
 
 def test_flag_edge_cases(dev):
@@ -329,6 +404,11 @@ def test_flag_edge_cases(dev):
         ref = clip.clip_iterative(s, status == 0, 3.0)
         assert np.array_equal(mask, ref.mask)
         assert st["iterations"] == ref.iterations and st["nflag"] == ref.nflag
+        for k in ("mu", "sigma", "thr"):
+            assert _same(st[k], getattr(ref, k)), k
+    # an empty block (nsub = 0) runs no fit
+    mask, st = _flag_case(dev, np.zeros(0), np.zeros(0, np.uint8), 0, 7)
+    assert st["iterations"] == 0 and st["nflag"] == 0
 
 
 def test_flag_stream_state(dev):
@@ -344,13 +424,14 @@ def test_flag_stream_state(dev):
         mask, st = _flag_case(dev, s, status, nsub, nchan, state=state)
         ref = clip.clip_stream(ost, s, status == 0)
         assert np.array_equal(mask, ref.mask), i
-        assert abs(st["thr"] - ref.thr) <= 1e-13 * ref.thr
+        assert (st["mu"], st["sigma"], st["thr"]) == (ref.mu, ref.sigma, ref.thr), i
     gs = rfi.stream_state_from_bytes(state.cpu().numpy().tobytes())
     assert gs.n == ost.N and gs.nblocks == 3
     assert gs.q1[0] + (gs.q1[1] << 64) == ost.Q1
     assert gs.q2[0] + (gs.q2[1] << 64) == ost.Q2
     for i in range(3):
-        assert abs(gs.hist[i].thr - ost.history[i][2]) <= 1e-13 * ost.history[i][2]
+        h = gs.hist[i]
+        assert (h.mu, h.sigma, h.thr, h.iterations) == tuple(ost.history[i]), i
 
 
 def test_pipeline_tiny_end_to_end(dev, tiny):

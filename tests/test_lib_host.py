@@ -72,6 +72,14 @@ def test_argument_errors_are_synchronous():
     assert L.rfi_flag(1, 64, C.c_void_p(16), C.c_void_p(16), None, 3.0, 0, None,
                       C.c_void_p(16), None, None, None) == rfi.RFI_E_INVALID
     assert rfi.rfi_flag_workspace_size(99, 4096) > 0
+    # the clip needs a caller workspace (the library allocates nothing), 256-byte aligned
+    assert L.rfi_flag(1, 64, C.c_void_p(16), C.c_void_p(16), None, 3.0, 50, None,
+                      C.c_void_p(16), None, None, None) == rfi.RFI_E_INVALID
+    assert b"workspace" in L.rfi_last_error()
+    assert L.rfi_flag(1, 64, C.c_void_p(16), C.c_void_p(16), None, 3.0, 50, None,
+                      C.c_void_p(16), None, C.c_void_p(272), None) == rfi.RFI_E_INVALID
+    assert L.rfi_clip_fit(-1, None, None, None, 3.0, None, None, None, None) == rfi.RFI_E_INVALID
+    assert L.rfi_clip_fit(4, None, None, None, 3.0, None, None, None, None) == rfi.RFI_E_INVALID
 
 
 def test_struct_layouts_match_header():
@@ -151,6 +159,18 @@ def test_tune_arguments():
     assert L.rfi_batch_workspace_size(1, items, C.byref(p)) > 0
     t.n = 99
     assert L.rfi_batch_workspace_size(1, items, C.byref(p)) == 0
+    # two items on one stream state would race in the batched clip: refused
+    p2 = rfi.rfi_batch_params(32, 12, 50, 0, 3.0, None)
+    items2 = (rfi.rfi_batch_item * 2)()
+    for i in range(2):
+        items2[i].blk = C.pointer(blk)
+        items2[i].L, items2[i].nsub = 256, 2
+        items2[i].stat = items2[i].status = items2[i].mask = 256
+        items2[i].state = 4096
+    assert L.rfi_batch_workspace_size(2, items2, C.byref(p2)) == 0
+    assert b"stream state" in L.rfi_last_error()
+    items2[1].state = 8192
+    assert L.rfi_batch_workspace_size(2, items2, C.byref(p2)) > 0
     assert L.rfi_tune_batch(1, items, C.byref(p), None, None, None) == rfi.RFI_E_INVALID
     out = rfi.rfi_tune_table()
     assert L.rfi_tune_batch(1, items, C.byref(p), None, C.byref(out), None) == rfi.RFI_E_INVALID
