@@ -201,6 +201,22 @@ rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8
                     rfi_stream_state* state, uint8_t* mask, rfi_flag_stats* out,
                     void* workspace, rfi_stream_t stream);
 
+/* rfi_flag without a workspace argument, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Arguments, results and errors as rfi_flag; the workspace is a
+ * fixed array of about 8.1 MiB of device memory inside this library, one per
+ * GPU, set aside when the library loads and held until the process ends (its
+ * address is looked up on the first call on each device). Blocks of at most
+ * RFI_FLAG_NOALLOC_MAX_CELLS cells (nsub * nchan); larger ones return
+ * RFI_E_INVALID. The call allocates nothing. Every call on a GPU shares that
+ * GPU's array, so calls that overlap on one GPU (on different streams, or
+ * from different threads) race; calls in one stream order are safe. */
+#define RFI_FLAG_NOALLOC_MAX_CELLS 1048576
+rfi_status rfi_flag_noalloc(int32_t nsub, int32_t nchan, const double* stat,
+                            const uint8_t* status, const uint8_t* protect_chan, double kappa,
+                            int32_t max_iter, rfi_stream_state* state, uint8_t* mask,
+                            rfi_flag_stats* out, rfi_stream_t stream);
+
 /* The clip's moment fit on its own (Sec. 3.3 Gaussian fit; the arithmetic
  * rfi_flag applies at every iteration), for checking its rounding: for each
  * i < n, from N[i] > 0 and the 128-bit sums Q1 = (Q1[2i], Q1[2i+1]) and

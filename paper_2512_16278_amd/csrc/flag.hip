@@ -38,6 +38,8 @@
 // A batched form runs the same four launches over many blocks at once.
 #include <math.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace rfi {
@@ -1006,3 +1008,66 @@ hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float* v1,
 }
 
 }  // namespace rfi
+
+// ---------------------------------------------------------------------------
+// rfi_flag_noalloc: the clip with its workspace in a fixed device array of
+// this library, for callers that cannot allocate.
+namespace rfi {
+namespace {
+
+constexpr int64_t kNoAllocCells = (int64_t)1 << 20;
+constexpr size_t kNoAllocBytes = kTailOff + (size_t)kNoAllocCells * sizeof(int64_t);
+
+// One copy per GPU, alive until the process ends. Host code must not pass
+// this name to a kernel: it is a host-side stand-in, not a device address;
+// the device address comes from hipGetSymbolAddress, per device, below.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDev = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDev] = {};
+
+// Device address of this device's scratch array (looked up once per device,
+// with that device current).
+hipError_t scratch_for(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+}  // namespace rfi
+
+extern "C" rfi_status rfi_flag_noalloc(int32_t nsub, int32_t nchan, const double* stat,
+                                       const uint8_t* status, const uint8_t* protect_chan,
+                                       double kappa, int32_t max_iter, rfi_stream_state* state,
+                                       uint8_t* mask, rfi_flag_stats* out, rfi_stream_t stream) {
+  rfi::clear_error();
+  if (nsub < 0 || nchan < 1) return rfi::fail(RFI_E_INVALID, "rfi_flag_noalloc: bad nsub/nchan");
+  if ((int64_t)nsub * nchan > rfi::kNoAllocCells)
+    return rfi::fail(RFI_E_INVALID,
+                     "rfi_flag_noalloc: %lld cells exceed the fixed workspace's %lld "
+                     "(use rfi_flag with a caller workspace)",
+                     (long long)nsub * nchan, (long long)rfi::kNoAllocCells);
+  if (nsub > 0 && (!stat || !status || !mask))
+    return rfi::fail(RFI_E_INVALID, "rfi_flag_noalloc: NULL input or output");
+  if (!(kappa >= 0.0)) return rfi::fail(RFI_E_INVALID, "rfi_flag_noalloc: kappa must be >= 0");
+  if (max_iter < 1) return rfi::fail(RFI_E_INVALID, "rfi_flag_noalloc: max_iter %d < 1", max_iter);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return rfi::check_hip(e, "rfi_flag_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= rfi::kMaxDev)
+    return rfi::fail(RFI_E_DEVICE, "rfi_flag_noalloc: device %d out of range", dev);
+  void* ws = nullptr;
+  if ((e = rfi::scratch_for(dev, &ws)) != hipSuccess)
+    return rfi::check_hip(e, "rfi_flag_noalloc: scratch address");
+  const rfi::ClipJob j = rfi::make_clip_job(nsub, nchan, stat, status, protect_chan, kappa,
+                                            max_iter, state, mask, out, ws, rfi::kNoAllocCells);
+  return rfi::check_hip(rfi::launch_clip(j, (hipStream_t)stream), "rfi_flag_noalloc launch");
+}

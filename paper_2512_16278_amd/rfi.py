@@ -154,6 +154,7 @@ def lib():
         L.rfi_flag_workspace_size.argtypes = [i32, i32]
         L.rfi_flag_workspace_size.restype = C.c_size_t
         L.rfi_clip_fit.argtypes = [i32, vp, vp, vp, dbl, vp, vp, vp, vp]
+        L.rfi_flag_noalloc.argtypes = [i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
         L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.rfi_process_workspace_size.argtypes = [i32, i32, C.POINTER(rfi_process_params)]
         L.rfi_process_workspace_size.restype = C.c_size_t
@@ -188,6 +189,7 @@ def lib():
         L.rfi_stream_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
         L.rfi_stream_import.argtypes = [vp, i32, vp, C.c_size_t]
         for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_clip_fit",
+                  "rfi_flag_noalloc",
                   "rfi_eigvec_flag",
                   "rfi_process_block", "rfi_session_create", "rfi_stream_open",
                   "rfi_stream_close", "rfi_submit", "rfi_poll", "rfi_wait", "rfi_cancel",
@@ -283,6 +285,17 @@ def rfi_flag(nsub, nchan, stat, status, mask, protect_chan=None, kappa=3.0, max_
     _check(lib().rfi_flag(int(nsub), int(nchan), _ptr(stat), _ptr(status), _ptr(protect_chan),
                           float(kappa), int(max_iter), _ptr(state), _ptr(mask), _ptr(out),
                           _ptr(workspace), _stream(stream)))
+
+
+def rfi_flag_noalloc(nsub, nchan, stat, status, mask, protect_chan=None, kappa=3.0, max_iter=50,
+                     state=None, out=None, stream=None):
+    """rfi_flag on the library's fixed workspace (no allocation anywhere)."""
+    _check(lib().rfi_flag_noalloc(int(nsub), int(nchan), _ptr(stat), _ptr(status),
+                                  _ptr(protect_chan), float(kappa), int(max_iter), _ptr(state),
+                                  _ptr(mask), _ptr(out), _stream(stream)))
+
+
+RFI_FLAG_NOALLOC_MAX_CELLS = 1 << 20
 
 
 def rfi_clip_fit(N, Q1, Q2, mu, sigma, thr, kappa=3.0, stream=None):

@@ -80,6 +80,8 @@ def test_argument_errors_are_synchronous():
                       C.c_void_p(16), None, C.c_void_p(272), None) == rfi.RFI_E_INVALID
     assert L.rfi_clip_fit(-1, None, None, None, 3.0, None, None, None, None) == rfi.RFI_E_INVALID
     assert L.rfi_clip_fit(4, None, None, None, 3.0, None, None, None, None) == rfi.RFI_E_INVALID
+    assert L.rfi_flag_noalloc(1 << 11, 1 << 10, C.c_void_p(256), C.c_void_p(256), None, 3.0,
+                              50, None, C.c_void_p(256), None, None) == rfi.RFI_E_INVALID
 
 
 def test_struct_layouts_match_header():
