@@ -164,3 +164,63 @@ def test_fullsize_sums_sampled(fast):
         rx, rxy = packed_oracle_sums(S, S2)
         assert np.array_equal(gx[:, :, c], rx), c
         assert np.array_equal(gxy[:, :, c], rxy), c
+
+
+def test_fullsize_eigvec_stage(fast):
+    """The per-beam eigenvector stage (Sec. 3.3 last paragraph; kappa_v = 1)
+    on the whole FAST-shaped block, in the benchmark's launch configuration:
+    v1 of the whole-block call against the oracle on the sampled cells (up to
+    sign where sum(v1) ~ 0, where the gap lambda_1 - lambda_2 is clear), and
+    over every cell the per-beam fits and masks against the same moment fit
+    recomputed here in FP64 from the GPU's v1 and mask."""
+    import torch
+    from paper_2512_16278_amd import rfi, synth
+    spec, data, dev = fast
+    nb, nc, L = spec.nbeam, spec.nchan, spec.L
+    nsub = spec.nsamp // L
+    ncell = nsub * nc
+    blk = rfi.make_block(data, nc)
+    p = rfi.process_params(L, nsub)
+    ws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, p), dtype=torch.uint8, device=dev)
+    stat = torch.empty(ncell, dtype=torch.float64, device=dev)
+    status = torch.empty(ncell, dtype=torch.uint8, device=dev)
+    mask = torch.empty(ncell, dtype=torch.uint8, device=dev)
+    v1 = torch.empty((nb, ncell), dtype=torch.float32, device=dev)
+    bmask = torch.empty((nb, ncell), dtype=torch.uint8, device=dev)
+    bmu = torch.empty(nb, dtype=torch.float64, device=dev)
+    bsd = torch.empty(nb, dtype=torch.float64, device=dev)
+    say("full size: rfi_process_block with v1, then rfi_eigvec_flag")
+    rfi.rfi_process_block(blk, p, stat, status, mask, ws, v1=v1)
+    rfi.rfi_eigvec_flag(nb, nsub, nc, v1, mask, status, bmask, kappa_v=1.0, beam_mu=bmu,
+                        beam_sigma=bsd)
+    torch.cuda.synchronize()
+    g = v1.cpu().numpy().reshape(nb, nsub, nc)
+    m = mask.cpu().numpy().astype(bool)
+    bm = bmask.cpu().numpy().astype(bool)
+    assert np.allclose(np.linalg.norm(g, axis=0), 1.0, atol=1e-5)
+    # sampled cells against the oracle's v1
+    subs, chans = _sample_windows(spec)
+    for k in subs:
+        say(f"full size: oracle v1 on sub-interval {k}")
+        x = synth.generate(spec, k * L, (k + 1) * L, 0, 512)
+        cr = pipeline.cells(x, L, 1)
+        vo = cr.v1.reshape(512, nb)
+        w = cr.w.reshape(512, nb)
+        vg = g[:, k, :512].T.astype(np.float64)
+        clear = (w[:, 0] - w[:, 1]) / np.abs(w[:, 0]) > 0.05
+        tie = np.abs(vo.sum(axis=1)) < 1e-5
+        d = np.where(tie[:, None], np.minimum(np.abs(vg - vo), np.abs(vg + vo)), np.abs(vg - vo))
+        assert d.max(axis=1)[clear].max() < 1e-4, k
+    # every cell: the per-beam moment fit of |v1_b| over eligible unmasked cells
+    a = np.abs(g.reshape(nb, ncell).astype(np.float64))
+    clean = ~m
+    mu = a[:, clean].mean(axis=1)
+    sd = np.sqrt(((a[:, clean] - mu[:, None]) ** 2).mean(axis=1))
+    gmu, gsd = bmu.cpu().numpy(), bsd.cpu().numpy()
+    assert np.abs(gmu - mu).max() <= 1e-12 * mu.max()
+    assert np.abs(gsd - sd).max() <= 1e-10 * sd.max()
+    thr = (gmu + gsd)[:, None]
+    ref = m[None, :] & (a > thr)
+    assert np.array_equal(bm, ref)
+    assert not (bm & ~m[None, :]).any()
+    assert bm.any(axis=0)[m].mean() > 0.3       # most flagged cells name their beams

@@ -222,6 +222,43 @@ def test_eig_tridiag(dev, nbeam):
     assert (status == 0).all()
 
 
+def test_eig_tridiag_72_beams_many_cells(dev):
+    """The 72-beam class at the shape the uneven batch runs (L = 512) over
+    4200 cells, so that many workgroups and the XCD-contiguous cell order
+    are in play: the rows-layout call and the whole-block call (cell-record
+    layout) against the oracle, statistic within 1e-12, equal to each other
+    bit for bit, masks identical to the oracle's clip."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    rng = np.random.default_rng(472)
+    nb, L, nsub, nc = 72, 512, 2, 2100
+    x = 128 + 20 * rng.standard_normal((nb, nsub * L, nc))
+    t = np.arange(nsub * L)
+    for j in rng.choice(nc, size=60, replace=False):          # common-mode RFI channels
+        g = rng.uniform(0.3, 2.0, nb)
+        x[:, :, j] += 10 * g[:, None] * np.sin(2 * np.pi * t / rng.uniform(20, 200) + j)[None, :]
+    x = np.clip(np.rint(x), 0, 255).astype(np.uint8)
+    out = _eig_case(dev, x, L, nsub, 32, 3)
+    status, cr = _check_eig(x, L, nsub, out, 1e-6, 1e-12)
+    assert (status == 0).all()
+    buf = upload(x, dev)
+    blk = rfi.make_block(buf, nc)
+    p = rfi.process_params(L, nsub)
+    ws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, p), dtype=torch.uint8, device=dev)
+    ncell = nsub * nc
+    stat = torch.empty(ncell, dtype=torch.float64, device=dev)
+    st2 = torch.empty(ncell, dtype=torch.uint8, device=dev)
+    mask = torch.empty(ncell, dtype=torch.uint8, device=dev)
+    say("eig 72 beams: whole-block call")
+    rfi.rfi_process_block(blk, p, stat, st2, mask, ws)
+    torch.cuda.synchronize()
+    s_blk = stat.cpu().numpy()
+    assert np.array_equal(s_blk, out[0])                      # same arithmetic, either layout
+    ref = clip.clip_iterative(cr.stat.ravel(), np.ones(ncell, bool), 3.0, 50)
+    assert np.array_equal(mask.cpu().numpy().astype(bool), ref.mask)
+    assert ref.nflag > 60 * nsub // 2
+
+
 def _close_pair_block(seed=91, nb=19, L=1024, nsub=2, nc=16):
     """Two disjoint beam groups carrying two different Walsh sequences (exactly
     orthogonal, zero-mean +-1 patterns over every sub-interval) at amplitude
