@@ -134,3 +134,59 @@ def test_worked_3x3_frobenius():
     assert ccm.covariance_numerators(S, S2, g["L"])[0, 0].tolist() == g["N"]
     r, _ = ccm.correlation(S, S2, g["L"])
     assert abs(ccm.frobenius2(r)[0, 0] - g["frob2_num"] / g["frob2_den"]) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Long sub-intervals (Table 1 runs sub-intervals of 0.05 - 10 s; 10 s of
+# 49.152 us samples is L = 203,450): the sums leave int32 (255^2 L > 2^31 for
+# L > 33,025) and the routes must stay exact.
+
+@pytest.mark.parametrize("L", [40960, 203450])
+def test_long_cells_exact_against_brute_force(L):
+    rng = np.random.default_rng(L)
+    nb, nc = 2, 1
+    x = rng.integers(0, 256, size=(nb, L, nc), dtype=np.uint8)
+    x[0, :34000, 0] = 255                           # saturated: S_aa > 255^2 33025 > 2^31
+    # brute force with Python integers, written out independently of sums_loops
+    xa = [int(v) for v in x[0, :, 0]]
+    xb = [int(v) for v in x[1, :, 0]]
+    Sa, Sb = sum(xa), sum(xb)
+    Saa = sum(v * v for v in xa)
+    Sab = sum(u * v for u, v in zip(xa, xb))
+    Sbb = sum(v * v for v in xb)
+    for route in (ccm.sums_int64, ccm.sums_fp64):
+        S, S2 = route(x, L, 1)
+        assert S[0, 0].tolist() == [Sa, Sb]
+        assert S2[0, 0].tolist() == [[Saa, Sab], [Sab, Sbb]]
+    assert Saa > 2 ** 31                            # beyond the int32 range
+    N = ccm.covariance_numerators(S, S2, L)
+    assert N[0, 0, 0, 1] == L * Sab - Sa * Sb
+    assert N[0, 0, 0, 0] == L * Saa - Sa * Sa
+
+
+def test_long_cell_all_255_and_alternating():
+    # x = 255 everywhere: S_ab = 255^2 L; alternating 0 / 255: the largest
+    # variance; the two beams exactly anti-correlated give r = -1
+    L = 203450
+    x = np.zeros((3, L, 1), dtype=np.uint8)
+    x[0] = 255
+    x[1, ::2, 0] = 255
+    x[2, 1::2, 0] = 255
+    S, S2 = ccm.sums_fp64(x, L, 1)
+    assert S[0, 0, 0] == 255 * L and S2[0, 0, 0, 0] == 255 * 255 * L
+    assert S2[0, 0, 1, 2] == 0 and S2[0, 0, 1, 1] == 255 * 255 * (L // 2)
+    r, deg = ccm.correlation(S, S2, L)
+    assert deg[0, 0]                                # beam 0 is constant
+    assert r[0, 0, 1, 2] == -1.0 and r[0, 0, 0, 1] == 0.0
+
+
+def test_long_cell_correlation_equals_numpy_corrcoef():
+    rng = np.random.default_rng(9)
+    L = 81920
+    x = np.clip(np.rint(128 + 30 * rng.standard_normal((4, L, 2))), 0, 255).astype(np.uint8)
+    x[1] = np.clip(x[0].astype(np.int64) // 2 + x[1] // 2, 0, 255).astype(np.uint8)
+    S, S2 = ccm.sums_int64(x, L, 1)
+    r, _ = ccm.correlation(S, S2, L)
+    for j in range(2):
+        ref = np.corrcoef(x[:, :, j].astype(np.float64))
+        np.testing.assert_allclose(r[0, j], ref, atol=1e-13)
