@@ -61,8 +61,13 @@ enum {
 typedef void* rfi_stream_t;            /* hipStream_t */
 
 #define RFI_MAX_BEAMS 79
-/* Largest number of samples a cell may accumulate: 255^2 * count < 2^31. */
+/* Largest number of samples a cell may accumulate in the int32 sums:
+ * 255^2 * count < 2^31. */
 #define RFI_MAX_COUNT 33025
+/* Largest sub-interval of the int64 (long sub-interval) path: with
+ * count < 2^18 every covariance numerator count S_ab - S_a S_b stays below
+ * 2^50, exact in int64 and in FP64. 10 s of 49.152 us samples is 203,450. */
+#define RFI_MAX_COUNT_LONG 262143
 
 /* One observation block (Sec. 2 data layout): per beam, a time-major
  * filterbank of uint8 total power, channels contiguous within a time row.
@@ -96,6 +101,24 @@ rfi_status rfi_ccm_accumulate(const rfi_block* blk /* host */, int64_t t0, int32
                               int32_t nsub, int32_t* sum_x, int32_t* sum_xy,
                               int32_t* count, int32_t accumulate, int32_t variant,
                               rfi_stream_t stream);
+
+/* Sums of Eq. 1 (Sec. 3.2) for long sub-intervals, RFI_MAX_COUNT < L <=
+ * RFI_MAX_COUNT_LONG (Table 1 runs sub-intervals up to 10 s, 203,450 samples of
+ * 49.152 us; any L >= 1 is accepted): the same sums as rfi_ccm_accumulate, as
+ * exact int64 in one record per cell,
+ *     sums[cell * (nbeam + npair) + b]          = sum_t x_b(t)
+ *     sums[cell * (nbeam + npair) + nbeam + p]  = sum_t x_a(t) x_b(t), p = pair(a, b)
+ * and count[k] = L. Each sub-interval is summed in time chunks of at most
+ * RFI_MAX_COUNT samples by the int32 engine and the chunks are added exactly
+ * in int64. workspace: rfi_ccm_long_workspace_size(nbeam, nchan, nsub) bytes
+ * of device scratch, 256-byte aligned, caller-owned, one call at a time.
+ * Outputs are overwritten (no accumulate mode). Errors: as
+ * rfi_ccm_accumulate with the bound RFI_MAX_COUNT_LONG; RFI_E_INVALID for a
+ * NULL or misaligned workspace. */
+size_t rfi_ccm_long_workspace_size(int32_t nbeam, int32_t nchan, int32_t nsub);
+rfi_status rfi_ccm_accumulate_long(const rfi_block* blk /* host */, int64_t t0, int32_t L,
+                                   int32_t nsub, int64_t* sums, int32_t* count, void* workspace,
+                                   rfi_stream_t stream);
 
 /* Eigen solver selection:
  *  RFI_EIG_LANE    cyclic Jacobi, FP32, one cell per lane in registers, nbeam <= 20;
@@ -147,6 +170,15 @@ rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan,
                            const int32_t* count, const rfi_eig_params* p /* host */,
                            float* eigvals, double* stat, float* v1, uint8_t* status,
                            rfi_stream_t stream);
+
+/* The eigen stage of rfi_eig_batched (Sec. 3.2-3.3, Eq. 2) on the int64 sums
+ * of rfi_ccm_accumulate_long (count[k] <= RFI_MAX_COUNT_LONG): the FP64
+ * Householder-tridiagonal solver (RFI_EIG_TRIDIAG) for every beam count, the
+ * covariance numerators formed exactly in int64. Outputs as rfi_eig_batched
+ * (eigvals and v1 nullable). */
+rfi_status rfi_eig_batched_long(int32_t nbeam, int32_t nsub, int32_t nchan, const int64_t* sums,
+                                const int32_t* count, float* eigvals, double* stat, float* v1,
+                                uint8_t* status, rfi_stream_t stream);
 
 /* Clip summary written by rfi_flag (device struct). */
 typedef struct {
@@ -266,7 +298,10 @@ rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const flo
  * RFI_E_INVALID if workspace is NULL or misaligned, or group < 0. */
 typedef struct {
   int64_t t0;            /* first sample of the first sub-interval */
-  int32_t L;             /* samples per sub-interval, 1..RFI_MAX_COUNT */
+  int32_t L;             /* samples per sub-interval, 1..RFI_MAX_COUNT_LONG; above
+                            RFI_MAX_COUNT the sums are int64 (as
+                            rfi_ccm_accumulate_long) and the eigen stage is the
+                            FP64 tridiagonal solver */
   int32_t nsub;          /* full sub-intervals to process */
   int32_t group;         /* sub-intervals per pipeline group; 0 = automatic */
   int32_t eig_precision; /* 32 (default) or 64 */

@@ -34,7 +34,7 @@ rfi_status check_hip(hipError_t e, const char* what) {
 }
 
 rfi_status validate_block(const rfi_block* blk, int64_t t0, int32_t L, int32_t nsub,
-                          const char* who, BeamPtrs* bp) {
+                          const char* who, BeamPtrs* bp, int32_t max_L) {
   if (!blk) return fail(RFI_E_INVALID, "%s: blk is NULL", who);
   const int n = blk->nbeam;
   if (n < 2 || n > RFI_MAX_BEAMS)
@@ -44,9 +44,9 @@ rfi_status validate_block(const rfi_block* blk, int64_t t0, int32_t L, int32_t n
     return fail(RFI_E_INVALID, "%s: row_stride %lld must be >= nchan and a multiple of 16", who,
                 (long long)blk->row_stride);
   if (L < 1) return fail(RFI_E_INVALID, "%s: L %d < 1", who, L);
-  if (L > RFI_MAX_COUNT)
-    return fail(RFI_E_OVERFLOW, "%s: L %d exceeds the exact int32 bound %d", who, L,
-                RFI_MAX_COUNT);
+  if (L > max_L)
+    return fail(RFI_E_OVERFLOW, "%s: L %d exceeds the exact bound %d of this path", who, L,
+                max_L);
   if (nsub < 0) return fail(RFI_E_INVALID, "%s: nsub %d < 0", who, nsub);
   if (t0 < 0 || t0 + (int64_t)nsub * L > blk->nsamp)
     return fail(RFI_E_INVALID, "%s: samples [%lld, %lld) outside the block of %lld", who,
@@ -156,6 +156,45 @@ rfi_status rfi_eig_batched(int32_t nbeam, int32_t nsub, int32_t nchan, const int
                  eigvals, stat, v1, status, (int64_t)nsub * nchan};
   hipStream_t s = (hipStream_t)stream;
   return check_hip(rfi::launch_eig(a, prm, s, 256), "rfi_eig_batched launch");
+}
+
+size_t rfi_ccm_long_workspace_size(int32_t nbeam, int32_t nchan, int32_t nsub) {
+  if (nbeam < 2 || nbeam > RFI_MAX_BEAMS || nchan < 1 || nsub < 0) return 0;
+  return rfi::ccm_long_tmp_bytes(nbeam, nchan, nsub);
+}
+
+rfi_status rfi_ccm_accumulate_long(const rfi_block* blk, int64_t t0, int32_t L, int32_t nsub,
+                                   int64_t* sums, int32_t* count, void* workspace,
+                                   rfi_stream_t stream) {
+  rfi::clear_error();
+  const char* who = "rfi_ccm_accumulate_long";
+  rfi::BeamPtrs bp;
+  const rfi_status st = rfi::validate_block(blk, t0, L, nsub, who, &bp, RFI_MAX_COUNT_LONG);
+  if (st != RFI_OK) return st;
+  if (nsub == 0) return RFI_OK;
+  if (!sums || !count) return fail(RFI_E_INVALID, "%s: NULL output", who);
+  if (!workspace || (uintptr_t)workspace % 256 != 0)
+    return fail(RFI_E_INVALID, "%s: workspace NULL or not 256-byte aligned", who);
+  return check_hip(rfi::launch_ccm_long(bp, blk->nbeam, blk->nchan, blk->row_stride, t0, L, nsub,
+                                        sums, count, workspace, (hipStream_t)stream),
+                   "rfi_ccm_accumulate_long launch");
+}
+
+rfi_status rfi_eig_batched_long(int32_t nbeam, int32_t nsub, int32_t nchan, const int64_t* sums,
+                                const int32_t* count, float* eigvals, double* stat, float* v1,
+                                uint8_t* status, rfi_stream_t stream) {
+  rfi::clear_error();
+  const char* who = "rfi_eig_batched_long";
+  if (nbeam < 2 || nbeam > RFI_MAX_BEAMS)
+    return fail(RFI_E_INVALID, "%s: nbeam %d outside 2..%d", who, nbeam, RFI_MAX_BEAMS);
+  if (nsub < 0 || nchan < 1) return fail(RFI_E_INVALID, "%s: bad nsub/nchan", who);
+  if ((int64_t)nsub * nchan > (int64_t)1 << 30)
+    return fail(RFI_E_INVALID, "%s: nsub * nchan exceeds 2^30 cells", who);
+  if (nsub == 0) return RFI_OK;
+  if (!sums || !count || !stat || !status) return fail(RFI_E_INVALID, "%s: NULL input or output", who);
+  rfi::EigArgs a{nbeam, nsub, nchan, (const int32_t*)sums, nullptr, count, 12, 1,
+                 eigvals, stat, v1, status, (int64_t)nsub * nchan, 2};
+  return check_hip(rfi::launch_eig_tri(a, (hipStream_t)stream), "rfi_eig_batched_long launch");
 }
 
 size_t rfi_flag_workspace_size(int32_t nsub, int32_t nchan) {

@@ -196,15 +196,20 @@ __device__ __forceinline__ int find_item_t(const int64_t* cell0, int nitem, int6
 // when v1 is requested; 0 in launches that never ask for v1).
 // Two waves per SIMD up to NL = 9 (72 beams: a few spilled registers cost less
 // than the latency one wave per SIMD leaves exposed); one beyond.
-template <int NL>
-__global__ __launch_bounds__(64, NL <= 9 ? 2 : 1) void eig_tri_kernel(EigArgs g,
+// W: the sums are int64 cell records (sub-intervals longer than the int32
+// bound, summed in time chunks and widened); such cells read n L >= 66,050
+// bytes each, so their eigen stage is never the bound and one wave per SIMD
+// (room for the wider LDS copy of the sums) costs nothing.
+template <int NL, bool W = false>
+__global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(EigArgs g,
                                                                       const EigArgs* items,
                                                                       const int64_t* cell0,
                                                                       int nitem, int vcap) {
   constexpr int NN = 8 * NL;
+  using ST = std::conditional_t<W, int64_t, int32_t>;
   __shared__ double X[NN], P[NN], alpha[NN], offd[NN], tau[NN], dinv[NN], z[NN];
   __shared__ double2 ae[NN];
-  __shared__ int32_t S[NN], SP[NN * (NN + 1) / 2];
+  __shared__ ST S[NN], SP[NN * (NN + 1) / 2];
   extern __shared__ __attribute__((aligned(16))) double vst[];
   int64_t cell = xcd_order(blockIdx.x, gridDim.x);
   if (items) {
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(64, NL <= 9 ? 2 : 1) void eig_tri_kernel(EigArgs g,
   const int lane = threadIdx.x, r = lane >> 3, c = lane & 7;
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
   const int64_t cnt = g.count[cell / g.nchan];
-  if (cnt < 2 || cnt > RFI_MAX_COUNT) {
+  if (cnt < 2 || cnt > (W ? RFI_MAX_COUNT_LONG : RFI_MAX_COUNT)) {
     for (int i = lane; i < n; i += 64) {
       if (g.eigvals) g.eigvals[i * g.out_stride + cell] = 0.f;
       if (g.v1) g.v1[i * g.out_stride + cell] = 0.f;
@@ -232,7 +237,12 @@ __global__ __launch_bounds__(64, NL <= 9 ? 2 : 1) void eig_tri_kernel(EigArgs g,
   // correlation matrix in FP64 and ||C||_F^2 (the cell's sums first go to
   // LDS, one pair per lane)
   const int np = n * (n + 1) / 2;
-  if (g.layout) {
+  if constexpr (W) {
+    // one contiguous int64 record per cell
+    const int64_t* rec = (const int64_t*)g.sum_x + cell * (int64_t)(n + np);
+    for (int q = lane; q < np; q += 64) SP[q] = rec[n + q];
+    for (int a = lane; a < n; a += 64) S[a] = rec[a];
+  } else if (g.layout) {
     // one contiguous record per cell: coalesced
     const int32_t* rec = g.sum_x + cell * (int64_t)(n + np);
     for (int q = lane; q < np; q += 64) SP[q] = rec[n + q];
@@ -487,29 +497,30 @@ __global__ __launch_bounds__(64, NL <= 9 ? 2 : 1) void eig_tri_kernel(EigArgs g,
   }
 }
 
-template <int NL>
+template <int NL, bool W>
 hipError_t launch_nl(int nbeam, const EigArgs& a, const EigArgs* items, const int64_t* cell0,
                      int nitem, int64_t total, bool v1, hipStream_t s) {
   const int vcap = v1 ? (nbeam - 1) * 8 * NL : 0;
   const size_t shm = (size_t)vcap * sizeof(double);
   if (shm > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)eig_tri_kernel<NL>,
+    hipError_t e = hipFuncSetAttribute((const void*)eig_tri_kernel<NL, W>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(eig_tri_kernel<NL>, dim3((unsigned)total), dim3(64), shm, s, a, items,
+  hipLaunchKernelGGL((eig_tri_kernel<NL, W>), dim3((unsigned)total), dim3(64), shm, s, a, items,
                      cell0, nitem, vcap);
   return hipGetLastError();
 }
 
+template <bool W>
 hipError_t launch_cls(int cls, int nbeam, const EigArgs& a, const EigArgs* items,
                       const int64_t* cell0, int nitem, int64_t total, bool v1, hipStream_t s) {
   switch (cls) {
-    case 3: return launch_nl<3>(nbeam, a, items, cell0, nitem, total, v1, s);
-    case 5: return launch_nl<5>(nbeam, a, items, cell0, nitem, total, v1, s);
-    case 8: return launch_nl<8>(nbeam, a, items, cell0, nitem, total, v1, s);
-    case 9: return launch_nl<9>(nbeam, a, items, cell0, nitem, total, v1, s);
-    case 10: return launch_nl<10>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 3: return launch_nl<3, W>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 5: return launch_nl<5, W>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 8: return launch_nl<8, W>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 9: return launch_nl<9, W>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 10: return launch_nl<10, W>(nbeam, a, items, cell0, nitem, total, v1, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -529,15 +540,18 @@ int eig_tri_class(int n) {
 hipError_t launch_eig_tri(const EigArgs& a, hipStream_t s) {
   const int64_t ncell = (int64_t)a.nsub * a.nchan;
   if (ncell == 0) return hipSuccess;
-  return launch_cls(eig_tri_class(a.nbeam), a.nbeam, a, nullptr, nullptr, 0, ncell,
-                    a.v1 != nullptr, s);
+  if (a.layout == 2)
+    return launch_cls<true>(eig_tri_class(a.nbeam), a.nbeam, a, nullptr, nullptr, 0, ncell,
+                            a.v1 != nullptr, s);
+  return launch_cls<false>(eig_tri_class(a.nbeam), a.nbeam, a, nullptr, nullptr, 0, ncell,
+                           a.v1 != nullptr, s);
 }
 
 hipError_t launch_eig_tri_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
                                 int64_t total, hipStream_t s) {
   if (total == 0) return hipSuccess;
   EigArgs none{};
-  return launch_cls(cls, 0, none, items, cell0, nitem, total, false, s);
+  return launch_cls<false>(cls, 0, none, items, cell0, nitem, total, false, s);
 }
 
 }  // namespace rfi

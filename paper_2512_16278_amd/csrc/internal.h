@@ -47,10 +47,12 @@ hipError_t launch_ccm_batch(int nbeam_of_class, const CcmTune* t, const CcmItem*
                             int nitem, int total_wg, hipStream_t s);
 
 // Kernel launchers (return a HIP error code; arguments already validated).
+// kstride: samples from the start of one sub-interval to the next (0 = L:
+// back to back; longer strides sum one time chunk of long sub-intervals).
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, int shared_cu, hipStream_t s,
-                           const CcmTune* t = nullptr, int layout = 0);
+                           const CcmTune* t = nullptr, int layout = 0, int64_t kstride = 0);
 // Sums layouts: 0 = the C ABI's rows (sum_x[b][cell], sum_xy[pair][cell]);
 // 1 = one record per cell, sum_x[cell * (nbeam + npair) + row] with rows b
 // then nbeam + pair (sum_xy unused): what a one-cell-per-wave consumer reads
@@ -58,6 +60,14 @@ hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
 hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, hipStream_t s);
+
+// Sums of sub-intervals longer than RFI_MAX_COUNT (up to RFI_MAX_COUNT_LONG):
+// int64 cell records rec[cell * (nbeam + npair) + row] (rows b, then nbeam +
+// pair), count[k] = L; tmp: ccm_long_tmp_bytes of device scratch.
+size_t ccm_long_tmp_bytes(int nbeam, int nchan, int nsub);
+hipError_t launch_ccm_long(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
+                           int64_t t0, int L, int nsub, int64_t* rec, int32_t* count, void* tmp,
+                           hipStream_t s, const CcmTune* t = nullptr);
 
 struct EigArgs {
   int nbeam, nsub, nchan;
@@ -70,7 +80,8 @@ struct EigArgs {
   float* v1;
   uint8_t* status;
   int64_t out_stride;  // cell stride of the eigvals / v1 rows (>= nsub * nchan)
-  int layout;          // sums layout (1: cell records; the tridiagonal solver only)
+  int layout;          // sums layout (1: cell records; 2: int64 cell records of long
+                       // sub-intervals, in sum_x; the tridiagonal solver only)
 };
 // FP32, nbeam <= 20; wg = lanes (cells) per workgroup: 64, 128 or 256; tri
 // = Householder + Sturm instead of Jacobi for the first kernel
@@ -142,8 +153,10 @@ void clear_error();
 rfi_status fail(rfi_status code, const char* fmt, ...);
 rfi_status check_hip(hipError_t e, const char* what);
 // Argument checks shared by the entry points; fill bp on success.
+// max_L: the longest sub-interval the caller's path takes (RFI_MAX_COUNT, or
+// RFI_MAX_COUNT_LONG where int64 sums are used).
 rfi_status validate_block(const rfi_block* blk, int64_t t0, int32_t L, int32_t nsub,
-                          const char* who, BeamPtrs* bp);
+                          const char* who, BeamPtrs* bp, int32_t max_L = RFI_MAX_COUNT);
 // Eigen parameters with defaults applied and the solver resolved.
 rfi_status resolve_eig(int nbeam, const rfi_eig_params* p, rfi_eig_params* out, const char* who);
 // Entry of a tune table whose beam range holds nbeam (NULL if none or no table).

@@ -23,7 +23,7 @@ namespace {
 constexpr size_t kAlign = 256;
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-size_t slot_bytes(int nbeam, int nchan, int group);
+size_t slot_bytes(int nbeam, int nchan, int group, bool longL = false);
 
 // Sub-intervals per group when the caller leaves it to the library: the whole
 // block while its sums fit in kAutoSums bytes, else the largest group whose
@@ -32,15 +32,18 @@ size_t slot_bytes(int nbeam, int nchan, int group);
 // after the other over the whole block (both are then limited by the same
 // vector ALU issue), so groups serve to bound the workspace, not to overlap.
 constexpr size_t kAutoSums = (size_t)1 << 30;
-int auto_group(int nbeam, int nchan, int nsub) {
+int auto_group(int nbeam, int nchan, int nsub, bool longL) {
   if (nsub <= 1) return 1;
-  if (slot_bytes(nbeam, nchan, nsub) <= kAutoSums) return nsub;
-  int g = (int)(kAutoSums / kRing / slot_bytes(nbeam, nchan, 1));
+  if (slot_bytes(nbeam, nchan, nsub, longL) <= kAutoSums) return nsub;
+  int g = (int)(kAutoSums / kRing / slot_bytes(nbeam, nchan, 1, longL));
   return g < 1 ? 1 : (g > nsub ? nsub : g);
 }
 
-size_t slot_bytes(int nbeam, int nchan, int group) {
+size_t slot_bytes(int nbeam, int nchan, int group, bool longL) {
   const size_t cells = (size_t)group * nchan;
+  if (longL)   // int64 records, the int32 chunk scratch, counts
+    return up(cells * (nbeam + npair_of(nbeam)) * 8) + up(ccm_long_tmp_bytes(nbeam, nchan, group)) +
+           up((size_t)group * 4);
   return up(cells * nbeam * 4) + up(cells * npair_of(nbeam) * 4) + up((size_t)group * 4);
 }
 
@@ -60,17 +63,22 @@ rfi_status resolve_process(int nbeam, int nchan, const rfi_process_params* p, Pr
   rfi_eig_params ep{p->eig_precision ? p->eig_precision : 32,
                     p->max_sweeps ? p->max_sweeps : 12, 1, te ? te->eig_solver : RFI_EIG_AUTO};
   if ((st = resolve_eig(nbeam, &ep, &pl->eig, who)) != RFI_OK) return st;
+  pl->L = p->L;
+  pl->longL = p->L > RFI_MAX_COUNT;
+  // long sub-intervals: the FP64 tridiagonal solver on the int64 sums (their
+  // cells read n L > 66,050 bytes each: the eigen stage is never the bound)
+  if (pl->longL) pl->eig.solver = RFI_EIG_TRIDIAG;
   pl->ct = te ? CcmTune{te->ccm_tile, te->ccm_stages, te->ccm_group_bytes} : CcmTune{};
   pl->eig_wg = te ? te->eig_wg : 0;
   pl->nbeam = nbeam;
   pl->nchan = nchan;
   pl->nsub = p->nsub;
   pl->group = p->group ? (p->group < p->nsub ? p->group : (p->nsub < 1 ? 1 : p->nsub))
-                       : auto_group(nbeam, nchan, p->nsub);
+                       : auto_group(nbeam, nchan, p->nsub, pl->longL);
   pl->max_iter = p->max_iter ? p->max_iter : 50;
   pl->kappa = p->kappa;
   pl->flag_ws = up(clip_workspace_size((int64_t)p->nsub * nchan));
-  pl->slot = slot_bytes(nbeam, nchan, pl->group);
+  pl->slot = slot_bytes(nbeam, nchan, pl->group, pl->longL);
   const int ngroup = (p->nsub + pl->group - 1) / pl->group;
   pl->nslot = ngroup < kRing ? (ngroup < 1 ? 1 : ngroup) : kRing;
   pl->ws_bytes = pl->flag_ws + (size_t)pl->nslot * pl->slot;
@@ -118,6 +126,26 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
     const int k0 = g * pl.group;
     const int ks = pl.nsub - k0 < pl.group ? pl.nsub - k0 : pl.group;
     char* base = (char*)ring + (size_t)slot * pl.slot;
+    const int64_t off = (int64_t)k0 * pl.nchan;
+    if (pl.longL) {
+      // the slot is free once the eigen stage of its previous group has run
+      if (g >= pl.nslot && (e = hipStreamWaitEvent(s, ev.eig[slot], 0)) != hipSuccess) return e;
+      const int nrow = pl.nbeam + npair_of(pl.nbeam);
+      int64_t* rec = (int64_t*)base;
+      char* tmp = base + up(cells_cap * nrow * 8);
+      int32_t* cnt = (int32_t*)(tmp + up(ccm_long_tmp_bytes(pl.nbeam, pl.nchan, pl.group)));
+      e = launch_ccm_long(bp, pl.nbeam, pl.nchan, row_stride, t0 + (int64_t)k0 * L, L, ks, rec,
+                          cnt, tmp, s, &pl.ct);
+      if (e != hipSuccess) return e;
+      if ((e = hipEventRecord(ev.ccm[slot], s)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(ev.aux, ev.ccm[slot], 0)) != hipSuccess) return e;
+      EigArgs a{pl.nbeam, ks, pl.nchan, (const int32_t*)rec, nullptr, cnt, pl.eig.max_sweeps, 1,
+                eigvals ? eigvals + off : nullptr, stat + off, v1 ? v1 + off : nullptr,
+                status + off, out_stride, 2};
+      if ((e = launch_eig(a, pl.eig, ev.aux)) != hipSuccess) return e;
+      if ((e = hipEventRecord(ev.eig[slot], ev.aux)) != hipSuccess) return e;
+      continue;
+    }
     int32_t* sx = (int32_t*)base;
     int32_t* sxy = (int32_t*)(base + up(cells_cap * pl.nbeam * 4));
     int32_t* cnt = (int32_t*)(base + up(cells_cap * pl.nbeam * 4) +
@@ -131,7 +159,6 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
     if (e != hipSuccess) return e;
     if ((e = hipEventRecord(ev.ccm[slot], s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(ev.aux, ev.ccm[slot], 0)) != hipSuccess) return e;
-    const int64_t off = (int64_t)k0 * pl.nchan;
     EigArgs a{pl.nbeam, ks, pl.nchan, sx, sxy, cnt, pl.eig.max_sweeps, 1,
               eigvals ? eigvals + off : nullptr, stat + off, v1 ? v1 + off : nullptr,
               status + off, out_stride, layout};
@@ -174,7 +201,7 @@ rfi_status rfi_process_block(const rfi_block* blk, const rfi_process_params* p,
   const char* who = "rfi_process_block";
   if (!p) return fail(RFI_E_INVALID, "%s: params is NULL", who);
   rfi::BeamPtrs bp;
-  rfi_status st = rfi::validate_block(blk, p->t0, p->L, p->nsub, who, &bp);
+  rfi_status st = rfi::validate_block(blk, p->t0, p->L, p->nsub, who, &bp, RFI_MAX_COUNT_LONG);
   if (st != RFI_OK) return st;
   rfi::ProcessPlan pl;
   if ((st = rfi::resolve_process(blk->nbeam, blk->nchan, p, &pl, who)) != RFI_OK) return st;

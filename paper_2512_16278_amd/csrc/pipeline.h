@@ -16,6 +16,8 @@ constexpr int kRing = 3;   // sum slots in flight between the two streams
 // Sizes and settings of one whole-block call, defaults applied.
 struct ProcessPlan {
   int nbeam = 0, nchan = 0, nsub = 0, group = 1, nslot = 1, max_iter = 50;
+  int L = 0;
+  bool longL = false;    // L > RFI_MAX_COUNT: int64 sums in time chunks, FP64 tridiagonal solver
   double kappa = 3.0;
   rfi_eig_params eig{32, 12, 1, RFI_EIG_AUTO};
   CcmTune ct{};          // sums-engine choices (zeros = the engine's defaults)

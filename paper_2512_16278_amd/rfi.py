@@ -21,6 +21,7 @@ RFI_CELL_DEGENERATE, RFI_CELL_NOT_CONVERGED, RFI_CELL_PROTECTED = 1, 2, 4
 RFI_CELL_REFINE_FAILED, RFI_CELL_BAD_COUNT = 8, 16
 RFI_MAX_BEAMS = 79
 RFI_MAX_COUNT = 33025
+RFI_MAX_COUNT_LONG = 262143
 RFI_HIST_CAP = 1024
 RFI_CCM_AUTO, RFI_CCM_MFMA, RFI_CCM_VALU = 0, 1, 2
 RFI_EIG_AUTO, RFI_EIG_LANE, RFI_EIG_WAVE, RFI_EIG_TRIDIAG, RFI_EIG_LANE_TRI = 0, 1, 2, 3, 4
@@ -154,6 +155,10 @@ def lib():
         L.rfi_flag_workspace_size.argtypes = [i32, i32]
         L.rfi_flag_workspace_size.restype = C.c_size_t
         L.rfi_clip_fit.argtypes = [i32, vp, vp, vp, dbl, vp, vp, vp, vp]
+        L.rfi_ccm_long_workspace_size.argtypes = [i32, i32, i32]
+        L.rfi_ccm_long_workspace_size.restype = C.c_size_t
+        L.rfi_ccm_accumulate_long.argtypes = [C.POINTER(rfi_block), i64, i32, i32, vp, vp, vp, vp]
+        L.rfi_eig_batched_long.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.rfi_flag_noalloc.argtypes = [i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
         L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.rfi_process_workspace_size.argtypes = [i32, i32, C.POINTER(rfi_process_params)]
@@ -188,7 +193,8 @@ def lib():
         L.rfi_batch_graph_destroy.restype = None
         L.rfi_stream_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
         L.rfi_stream_import.argtypes = [vp, i32, vp, C.c_size_t]
-        for f in ("rfi_ccm_accumulate", "rfi_eig_batched", "rfi_flag", "rfi_clip_fit",
+        for f in ("rfi_ccm_accumulate", "rfi_ccm_accumulate_long", "rfi_eig_batched_long",
+                  "rfi_eig_batched", "rfi_flag", "rfi_clip_fit",
                   "rfi_flag_noalloc",
                   "rfi_eigvec_flag",
                   "rfi_process_block", "rfi_session_create", "rfi_stream_open",
@@ -253,6 +259,23 @@ def rfi_ccm_accumulate(blk: rfi_block, t0, L, nsub, sum_x, sum_xy, count, accumu
     _check(lib().rfi_ccm_accumulate(C.byref(blk), int(t0), int(L), int(nsub), _ptr(sum_x),
                                     _ptr(sum_xy), _ptr(count), int(accumulate), int(variant),
                                     _stream(stream)))
+
+
+def rfi_ccm_long_workspace_size(nbeam, nchan, nsub):
+    return int(lib().rfi_ccm_long_workspace_size(int(nbeam), int(nchan), int(nsub)))
+
+
+def rfi_ccm_accumulate_long(blk: rfi_block, t0, L, nsub, sums, count, workspace, stream=None):
+    """int64 cell-record sums of long sub-intervals (L <= RFI_MAX_COUNT_LONG)."""
+    _check(lib().rfi_ccm_accumulate_long(C.byref(blk), int(t0), int(L), int(nsub), _ptr(sums),
+                                         _ptr(count), _ptr(workspace), _stream(stream)))
+
+
+def rfi_eig_batched_long(nbeam, nsub, nchan, sums, count, stat, status, eigvals=None, v1=None,
+                         stream=None):
+    _check(lib().rfi_eig_batched_long(int(nbeam), int(nsub), int(nchan), _ptr(sums), _ptr(count),
+                                      _ptr(eigvals), _ptr(stat), _ptr(v1), _ptr(status),
+                                      _stream(stream)))
 
 
 def rfi_eig_batched(nbeam, nsub, nchan, sum_x, sum_xy, count, stat, status, eigvals=None,

@@ -224,3 +224,40 @@ def test_fullsize_eigvec_stage(fast):
     assert np.array_equal(bm, ref)
     assert not (bm & ~m[None, :]).any()
     assert bm.any(axis=0)[m].mean() > 0.3       # most flagged cells name their beams
+
+
+def test_fullsize_one_10s_sub_interval(fast):
+    """Table 1's longest sub-interval: the whole 10 s FAST-shaped block as one
+    sub-interval of L = 203,450 samples (int64 sums in time chunks), 4096
+    cells: sampled channels against the oracle (statistic within 1e-12) and
+    the clip against the oracle's clip of the same statistic (bit-equal)."""
+    import torch
+    from paper_2512_16278_amd import rfi, synth
+    spec, data, dev = fast
+    nb, nc = spec.nbeam, spec.nchan
+    L = spec.nsamp
+    blk = rfi.make_block(data, nc)
+    p = rfi.process_params(L, 1)
+    ws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, p), dtype=torch.uint8, device=dev)
+    stat = torch.empty(nc, dtype=torch.float64, device=dev)
+    status = torch.empty(nc, dtype=torch.uint8, device=dev)
+    mask = torch.empty(nc, dtype=torch.uint8, device=dev)
+    out = torch.zeros(48, dtype=torch.uint8, device=dev)
+    say(f"full size: one sub-interval of {L} samples")
+    rfi.rfi_process_block(blk, p, stat, status, mask, ws, out=out)
+    torch.cuda.synchronize()
+    s = stat.cpu().numpy()
+    m = mask.cpu().numpy().astype(bool)
+    fs = rfi.flag_stats_from_bytes(out.cpu().numpy().tobytes())
+    ref = clip.clip_iterative(s, (status.cpu().numpy() & 17) == 0, 3.0, 50)
+    assert np.array_equal(m, ref.mask)
+    assert (fs["mu"], fs["sigma"], fs["thr"], fs["iterations"]) == \
+        (ref.mu, ref.sigma, ref.thr, ref.iterations)
+    _, chans = _sample_windows(spec)
+    for c in chans:
+        say(f"full size: oracle on channel {c}, L = {L}")
+        x = synth.generate(spec, 0, L, c, c + 1)
+        cr = pipeline.cells(x, L, 1)
+        assert abs(s[c] - cr.stat[0, 0]) <= 1e-12, c
+    for sn in spec.sinusoids[:8]:
+        assert m[sn.chan], sn.chan                      # persistent common-mode channels

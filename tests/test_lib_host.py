@@ -72,6 +72,19 @@ def test_argument_errors_are_synchronous():
     assert L.rfi_flag(1, 64, C.c_void_p(16), C.c_void_p(16), None, 3.0, 0, None,
                       C.c_void_p(16), None, None, None) == rfi.RFI_E_INVALID
     assert rfi.rfi_flag_workspace_size(99, 4096) > 0
+    # long sub-intervals: int64 path up to RFI_MAX_COUNT_LONG
+    assert rfi.rfi_ccm_long_workspace_size(19, 4096, 1) > 0
+    assert rfi.rfi_ccm_long_workspace_size(1, 4096, 1) == 0
+    blk.nbeam, blk.nsamp = 19, 300000
+    assert L.rfi_ccm_accumulate_long(C.byref(blk), 0, rfi.RFI_MAX_COUNT_LONG + 1, 1, C.c_void_p(256),
+                                     C.c_void_p(256), C.c_void_p(256), None) == rfi.RFI_E_OVERFLOW
+    assert L.rfi_ccm_accumulate_long(C.byref(blk), 0, 203450, 1, C.c_void_p(256), C.c_void_p(256),
+                                     None, None) == rfi.RFI_E_INVALID
+    assert L.rfi_ccm_accumulate(C.byref(blk), 0, 203450, 1, C.c_void_p(256), C.c_void_p(256),
+                                C.c_void_p(256), 0, 0, None) == rfi.RFI_E_OVERFLOW
+    assert L.rfi_eig_batched_long(1, 1, 64, None, None, None, None, None, None, None) == rfi.RFI_E_INVALID
+    assert rfi.rfi_process_workspace_size(19, 4096, rfi.process_params(203450, 1)) > 0
+    blk.nsamp = 1024
     # the clip needs a caller workspace (the library allocates nothing), 256-byte aligned
     assert L.rfi_flag(1, 64, C.c_void_p(16), C.c_void_p(16), None, 3.0, 50, None,
                       C.c_void_p(16), None, None, None) == rfi.RFI_E_INVALID
