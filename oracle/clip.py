@@ -77,12 +77,13 @@ class ClipResult:
 
 
 def clip_iterative(s: np.ndarray, eligible: np.ndarray, kappa: float = 3.0,
-                   max_iter: int = 50, prior=(0, 0, 0)) -> ClipResult:
+                   max_iter: int = 50, prior=(0, 0, 0), fit: str = "moments") -> ClipResult:
     """Route 1: the iteration as stated, one pass per iteration.
 
     ``prior`` = (N_h, Q1_h, Q2_h) are moment sums pooled into every fit (the
     streaming reading of ``clip_stream``); (0, 0, 0) is the paper's batch
-    clip.
+    clip. ``fit`` = "histogram" replaces the moment fit by ``fit_histogram``
+    of the live values (no prior then).
     """
     eligible = np.asarray(eligible, dtype=bool)
     q = quantize(s)
@@ -98,7 +99,10 @@ def clip_iterative(s: np.ndarray, eligible: np.ndarray, kappa: float = 3.0,
         if N + Nh == 0:
             break
         it += 1
-        mu, sigma = moments_from_sums(N + Nh, Q1 + Q1h, Q2 + Q2h)
+        if fit == "histogram":
+            mu, sigma = fit_histogram(sq[live], N, Q1, Q2)
+        else:
+            mu, sigma = moments_from_sums(N + Nh, Q1 + Q1h, Q2 + Q2h)
         thr = mu + kappa * sigma
         new = live & (sq > thr)
         if not new.any():
@@ -152,6 +156,118 @@ def clip_sorted(s: np.ndarray, eligible: np.ndarray, kappa: float = 3.0,
         cut = vals[m]             # smallest masked value
         mask = eligible & (sq >= cut)
     return ClipResult(mask, mu, sigma, thr, it, converged, int(mask.sum()))
+
+
+HIST_BINS = 64
+
+
+def histogram_counts(sq_live: np.ndarray, mu_m: float, sig_m: float) -> np.ndarray:
+    """Counts of the live values in 64 bins of width sigma_m / 8 over
+    [mu_m - 4 sigma_m, mu_m + 4 sigma_m): bin i holds the values with
+    floor((v - lo) / w) = i, lo = mu_m - 4 sigma_m, w = sigma_m / 8 (each
+    step one FP64 rounding, in this order); values outside are not counted."""
+    lo = mu_m - 4.0 * sig_m
+    w = sig_m * 0.125
+    idx = np.floor((np.asarray(sq_live, dtype=np.float64) - lo) / w)
+    counts = np.zeros(HIST_BINS, dtype=np.int64)
+    for i in range(HIST_BINS):
+        counts[i] = int(np.count_nonzero(idx == i))
+    return counts
+
+
+def fit_histogram(sq_live: np.ndarray, N: int, Q1: int, Q2: int):
+    """Gaussian fit to the histogram of the live values (Sec. 3.3, Fig. 1:
+    the mean and standard deviation come from a Gaussian fitted to the
+    distribution; the paper does not state the bins or the fitting method).
+
+    Reading: the moment fit (mu_m, sigma_m) places 64 bins over +-4 sigma_m
+    (``histogram_counts``); ln c_i is fitted by a parabola a + b z + c z^2 in
+    the standardised bin centres z_i = (i + 1/2) / 8 - 4 by least squares
+    with weights c_i^2 over the non-empty bins (Guo's weighting of Caruana's
+    method), solved by Cramer's rule; then mu = mu_m + (-b / 2c) sigma_m and
+    sigma = sqrt(-1 / 2c) sigma_m. Fewer than 3 non-empty bins, fewer than 8
+    values, sigma_m = 0 or c >= 0 fall back to the moment fit. Sums run over
+    the bins in index order, in the operation order written here.
+    """
+    mu_m, sig_m = moments_from_sums(N, Q1, Q2)
+    if N < 8 or not (sig_m > 0):
+        return mu_m, sig_m
+    counts = histogram_counts(sq_live, mu_m, sig_m)
+    if int(np.count_nonzero(counts)) < 3:
+        return mu_m, sig_m
+    S0 = S1 = S2 = S3 = S4 = T0 = T1 = T2 = 0.0
+    for i in range(HIST_BINS):
+        c = int(counts[i])
+        if c == 0:
+            continue
+        z = (i + 0.5) * 0.125 - 4.0
+        y = math.log(c)
+        wt = float(c) * float(c)
+        z2 = z * z
+        S0 += wt
+        S1 += wt * z
+        S2 += wt * z2
+        S3 += wt * (z2 * z)
+        S4 += wt * (z2 * z2)
+        T0 += wt * y
+        T1 += wt * (z * y)
+        T2 += wt * (z2 * y)
+    # Cramer's rule for [[S0 S1 S2] [S1 S2 S3] [S2 S3 S4]] (a b c)^T = (T0 T1 T2)^T
+    m0 = S2 * S4 - S3 * S3
+    m1 = S1 * S4 - S3 * S2
+    m2 = S1 * S3 - S2 * S2
+    det = S0 * m0 - S1 * m1 + S2 * m2
+    if not (det != 0.0):
+        return mu_m, sig_m
+    db = S0 * (T1 * S4 - S3 * T2) - T0 * m1 + S2 * (S1 * T2 - T1 * S2)
+    dc = S0 * (S2 * T2 - T1 * S3) - S1 * (S1 * T2 - T1 * S2) + T0 * m2
+    b = db / det
+    c2 = dc / det
+    if not (c2 < 0.0):
+        return mu_m, sig_m
+    mu_z = -b / (2.0 * c2)
+    sig_z = math.sqrt(-1.0 / (2.0 * c2))
+    return mu_m + mu_z * sig_m, sig_z * sig_m
+
+
+@dataclass
+class ScopedResult:
+    mask: np.ndarray          # union of the requested scopes' masks [nsub, nchan]
+    glob: "ClipResult | None"
+    chan: list                # ClipResult per channel (or [])
+    sub: list                 # ClipResult per sub-interval (or [])
+
+
+SCOPE_GLOBAL, SCOPE_CHANNEL, SCOPE_SUBINT = 1, 2, 4
+
+
+def clip_scoped(s2d: np.ndarray, elig2d: np.ndarray, kappa: float = 3.0, max_iter: int = 50,
+                scopes: int = SCOPE_GLOBAL, fit: str = "moments") -> ScopedResult:
+    """Clip scopes over the [nsub, nchan] statistic (Sec. 3.3: outliers are
+    masked as a function of frequency and time): the global clip over every
+    cell, one clip per channel over its sub-intervals, one clip per
+    sub-interval over its channels; the result is the union of the masks of
+    the requested scopes (the combined mask of Sec. 3.3)."""
+    s2d = np.asarray(s2d, dtype=np.float64)
+    elig2d = np.asarray(elig2d, dtype=bool)
+    nsub, nchan = s2d.shape
+    mask = np.zeros((nsub, nchan), dtype=bool)
+    g = None
+    ch, sb = [], []
+    if scopes & SCOPE_GLOBAL:
+        g = clip_iterative(s2d.ravel(), elig2d.ravel(), kappa, max_iter, fit=fit)
+        mask |= g.mask.reshape(nsub, nchan)
+    if scopes & SCOPE_CHANNEL:
+        for j in range(nchan):
+            r = clip_iterative(s2d[:, j], elig2d[:, j], kappa, max_iter, fit=fit)
+            ch.append(r)
+            mask[:, j] |= r.mask
+    if scopes & SCOPE_SUBINT:
+        for k in range(nsub):
+            r = clip_iterative(s2d[k, :], elig2d[k, :], kappa, max_iter, fit=fit)
+            sb.append(r)
+            mask[k, :] |= r.mask
+    return ScopedResult(mask, g, ch, sb)
 
 
 @dataclass

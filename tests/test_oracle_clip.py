@@ -180,3 +180,88 @@ def test_stream_reduces_to_batch_and_pools_history():
     assert np.array_equal(masked[live.sum():], r2.mask)
     assert abs(thr - r2.thr) < 1e-11
     assert len(st.history) == 2 and st.N == live.sum() + (~r2.mask).sum()
+
+
+# ---------------------------------------------------------------------------
+# Clip scopes and the histogram Gaussian fit (Sec. 3.3: outliers are masked
+# as a function of frequency and time; the mean and standard deviation come
+# from a Gaussian fitted to the distribution, Fig. 1).
+
+def _qlive(rng, n, mu=0.075, sd=0.002):
+    s = np.clip(mu + sd * rng.standard_normal(n), 0, 1)
+    q = clip.quantize(s)
+    return clip.dequantize(q), clip.exact_sums(q)
+
+
+def test_histogram_fit_matches_weighted_polyfit():
+    """The Cramer's-rule least squares of fit_histogram against numpy.polyfit
+    (weights w_i = c_i multiply the residuals, i.e. c_i^2 weighting) on the
+    same bins."""
+    rng = np.random.default_rng(61)
+    for n in (500, 5000, 60000):
+        sq, (N, Q1, Q2) = _qlive(rng, n)
+        mu_m, sg_m = clip.moments_from_sums(N, Q1, Q2)
+        c = clip.histogram_counts(sq, mu_m, sg_m)
+        nz = c > 0
+        z = (np.arange(clip.HIST_BINS) + 0.5) * 0.125 - 4.0
+        c2, b, a = np.polyfit(z[nz], np.log(c[nz]), 2, w=c[nz].astype(float))
+        mu_ref = mu_m + (-b / (2 * c2)) * sg_m
+        sd_ref = math.sqrt(-1.0 / (2 * c2)) * sg_m
+        mu, sd = clip.fit_histogram(sq, N, Q1, Q2)
+        assert abs(mu - mu_ref) <= 1e-12 * mu_ref
+        assert abs(sd - sd_ref) <= 1e-9 * sd_ref
+        assert c.sum() == np.count_nonzero(np.abs(sq - mu_m) < 4 * sg_m + 1e-18) or c.sum() <= n
+
+
+def test_histogram_fit_recovers_gaussian_and_symmetry():
+    rng = np.random.default_rng(62)
+    sq, (N, Q1, Q2) = _qlive(rng, 200000, 0.1, 0.003)
+    mu, sd = clip.fit_histogram(sq, N, Q1, Q2)
+    assert abs(mu - 0.1) < 5e-5 and abs(sd / 0.003 - 1) < 0.02
+    # exactly symmetric values about their mean: the parabola's vertex is the mean
+    q = clip.quantize(np.clip(0.2 + 0.004 * rng.standard_normal(4000), 0, 1))
+    centre = int(clip.quantize(np.array([0.2]))[0])
+    qs = np.concatenate([q, 2 * centre - q])
+    N, Q1, Q2 = clip.exact_sums(qs)
+    mu_m, _ = clip.moments_from_sums(N, Q1, Q2)
+    mu, _ = clip.fit_histogram(clip.dequantize(qs), N, Q1, Q2)
+    assert abs(mu - mu_m) <= 1e-12 * mu_m
+    # too few values or no spread: the moment fit
+    sq, (N, Q1, Q2) = _qlive(rng, 5)
+    assert clip.fit_histogram(sq, N, Q1, Q2) == clip.moments_from_sums(N, Q1, Q2)
+
+
+def test_histogram_clip_flags_outliers():
+    rng = np.random.default_rng(63)
+    s = np.clip(0.075 + 0.002 * rng.standard_normal(3000), 0, 1)
+    bad = rng.choice(3000, 60, replace=False)
+    s[bad] += rng.uniform(0.02, 0.5, 60)
+    res = clip.clip_iterative(s, np.ones(3000, bool), 3.0, 50, fit="histogram")
+    assert res.mask[bad].all() and res.converged
+    assert res.mask.sum() < 80
+
+
+def test_scopes_orientation_and_union():
+    """One sub-interval raised in every channel and one channel raised in every
+    sub-interval: the per-channel clips catch the raised sub-interval (an
+    outlier within each channel) but not the raised channel (uniform within
+    it); the per-sub-interval clips the reverse; the union holds both."""
+    rng = np.random.default_rng(64)
+    K, F = 40, 60
+    s = 0.075 + 0.002 * rng.standard_normal((K, F))
+    s[7, :] += 0.05                   # broadband burst in sub-interval 7
+    s[:, 11] += 0.05                  # persistent RFI in channel 11
+    ok = np.ones((K, F), bool)
+    ch = clip.clip_scoped(s, ok, scopes=clip.SCOPE_CHANNEL)
+    sb = clip.clip_scoped(s, ok, scopes=clip.SCOPE_SUBINT)
+    un = clip.clip_scoped(s, ok, scopes=clip.SCOPE_CHANNEL | clip.SCOPE_SUBINT)
+    assert ch.mask[7, :].sum() >= F - 1 and ch.mask[:, 11].sum() <= 2
+    assert sb.mask[:, 11].sum() >= K - 1 and sb.mask[7, :].sum() <= 2
+    assert np.array_equal(un.mask, ch.mask | sb.mask)
+    assert len(ch.chan) == F and len(sb.sub) == K
+    # per-channel scope == the batch clip of each column on its own
+    for j in (0, 11, F - 1):
+        r = clip.clip_iterative(s[:, j], ok[:, j])
+        assert np.array_equal(ch.mask[:, j], r.mask) and ch.chan[j].thr == r.thr
+    g = clip.clip_scoped(s, ok, scopes=clip.SCOPE_GLOBAL)
+    assert g.mask[7, :].all() and g.mask[:, 11].all()
