@@ -249,6 +249,36 @@ rfi_status rfi_flag_noalloc(int32_t nsub, int32_t nchan, const double* stat,
                             int32_t max_iter, rfi_stream_state* state, uint8_t* mask,
                             rfi_flag_stats* out, rfi_stream_t stream);
 
+/* Clip scopes and fits (Sec. 3.3: outliers are masked as a function of
+ * frequency and time; the mean and standard deviation come from a Gaussian
+ * fitted to the distribution, Fig. 1). scopes is a bit set:
+ *   RFI_SCOPE_GLOBAL   one clip over every cell (as rfi_flag, state-free);
+ *   RFI_SCOPE_CHANNEL  one clip per channel over its nsub sub-intervals;
+ *   RFI_SCOPE_SUBINT   one clip per sub-interval over its nchan channels;
+ * mask[cell] = 1 where any requested scope masks the cell (the combined
+ * mask). Each clip iterates as rfi_flag (same eligibility, kappa, max_iter,
+ * quantised statistic). fit: RFI_FIT_MOMENTS is rfi_flag's exact moment fit
+ * (every reported fit bit-equal to it); RFI_FIT_HISTOGRAM fits a Gaussian to
+ * the histogram of the live values: 64 bins of width sigma_m / 8 over
+ * mu_m +- 4 sigma_m of the exact moment fit, then a least-squares parabola
+ * a + b z + c z^2 through ln(count) at the standardised bin centres
+ * z = (i + 1/2) / 8 - 4 with weights count^2 over the non-empty bins
+ * (Cramer's rule), mu = mu_m - b / (2c) sigma_m, sigma = sqrt(-1 / (2c))
+ * sigma_m; fewer than 8 live values, sigma_m = 0, fewer than 3 non-empty
+ * bins or c >= 0 keep the moment fit. Summaries (nullable): out for the
+ * global scope, chan_out[nchan] per channel, sub_out[nsub] per sub-interval.
+ * workspace: rfi_flag_workspace_size bytes (256-byte aligned) when the global
+ * scope uses the moment fit, else unused (may be NULL).
+ * Errors: RFI_E_INVALID for bad sizes, scopes outside 1..7, an unknown fit,
+ * kappa < 0, max_iter < 1 or a missing workspace. */
+enum { RFI_SCOPE_GLOBAL = 1, RFI_SCOPE_CHANNEL = 2, RFI_SCOPE_SUBINT = 4 };
+enum { RFI_FIT_MOMENTS = 0, RFI_FIT_HISTOGRAM = 1 };
+rfi_status rfi_flag_scoped(int32_t nsub, int32_t nchan, const double* stat, const uint8_t* status,
+                           const uint8_t* protect_chan, double kappa, int32_t max_iter,
+                           int32_t scopes, int32_t fit, uint8_t* mask, rfi_flag_stats* out,
+                           rfi_flag_stats* chan_out, rfi_flag_stats* sub_out, void* workspace,
+                           rfi_stream_t stream);
+
 /* The clip's moment fit on its own (Sec. 3.3 Gaussian fit; the arithmetic
  * rfi_flag applies at every iteration), for checking its rounding: for each
  * i < n, from N[i] > 0 and the 128-bit sums Q1 = (Q1[2i], Q1[2i+1]) and

@@ -222,6 +222,32 @@ rfi_status rfi_flag(int32_t nsub, int32_t nchan, const double* stat, const uint8
   return check_hip(rfi::launch_clip(j, (hipStream_t)stream), "rfi_flag launch");
 }
 
+rfi_status rfi_flag_scoped(int32_t nsub, int32_t nchan, const double* stat, const uint8_t* status,
+                           const uint8_t* protect_chan, double kappa, int32_t max_iter,
+                           int32_t scopes, int32_t fit, uint8_t* mask, rfi_flag_stats* out,
+                           rfi_flag_stats* chan_out, rfi_flag_stats* sub_out, void* workspace,
+                           rfi_stream_t stream) {
+  rfi::clear_error();
+  const char* who = "rfi_flag_scoped";
+  if (nsub < 0 || nchan < 1) return fail(RFI_E_INVALID, "%s: bad nsub/nchan", who);
+  if ((int64_t)nsub * nchan > (int64_t)1 << 30)
+    return fail(RFI_E_INVALID, "%s: nsub * nchan exceeds 2^30 cells", who);
+  if (nsub > 0 && (!stat || !status || !mask))
+    return fail(RFI_E_INVALID, "%s: NULL input or output", who);
+  if (!(kappa >= 0.0)) return fail(RFI_E_INVALID, "%s: kappa must be >= 0", who);
+  if (max_iter < 1) return fail(RFI_E_INVALID, "%s: max_iter %d < 1", who, max_iter);
+  if (scopes < 1 || scopes > 7) return fail(RFI_E_INVALID, "%s: scopes %d not in 1..7", who, scopes);
+  if (fit != RFI_FIT_MOMENTS && fit != RFI_FIT_HISTOGRAM)
+    return fail(RFI_E_INVALID, "%s: unknown fit %d", who, fit);
+  if ((scopes & RFI_SCOPE_GLOBAL) && fit == RFI_FIT_MOMENTS &&
+      (!workspace || (uintptr_t)workspace % 256 != 0))
+    return fail(RFI_E_INVALID, "%s: workspace NULL or not 256-byte aligned", who);
+  const rfi::ClipJob j = rfi::make_clip_job(nsub, nchan, stat, status, protect_chan, kappa,
+                                            max_iter, nullptr, mask, out, workspace);
+  return check_hip(rfi::launch_clip_scoped(j, scopes, fit, chan_out, sub_out, (hipStream_t)stream),
+                   "rfi_flag_scoped launch");
+}
+
 rfi_status rfi_clip_fit(int32_t n, const int64_t* N, const uint64_t* Q1, const uint64_t* Q2,
                         double kappa, double* mu, double* sigma, double* thr,
                         rfi_stream_t stream) {

@@ -38,6 +38,7 @@
 // A batched form runs the same four launches over many blocks at once.
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "internal.h"
@@ -831,6 +832,213 @@ __global__ __launch_bounds__(kGridThreads) void clip_mask_kernel(ClipJob job0, c
   }
 }
 
+// ---------------------------------------------------------------------------
+// Clip scopes (Sec. 3.3: outliers are masked as a function of frequency and
+// time): one workgroup clips one segment of cells -- a channel over its
+// sub-intervals, a sub-interval over its channels, or the whole block -- with
+// the same exact iteration, re-reading its cells every pass; the masks of the
+// requested scopes are OR-ed into one. The fit is the exact moment fit, or the
+// histogram Gaussian fit: 64 bins of width sigma_m / 8 over +-4 sigma_m of
+// the exact moment fit, a least-squares parabola through the log counts with
+// weights c^2 (one thread, bins in index order, the operation order of the
+// definition, no fused multiply-add), falling back to the moments where the
+// parabola is undefined.
+constexpr int kSegThreads = 256;
+constexpr int kBins = 64;
+
+struct SegArgs {
+  int nsub, nchan, max_iter, fit;
+  double kappa;
+  const double* stat;
+  const uint8_t* status;
+  const uint8_t* protect;
+  uint8_t* mask;
+  rfi_flag_stats* out;   // [segments] or NULL
+  int write;             // 1: store the mask, 0: OR it in
+};
+
+// the segment's i-th cell (MODE 0: channel blockIdx.x over sub-intervals;
+// 1: sub-interval blockIdx.x over channels; 2: every cell)
+template <int MODE>
+__device__ __forceinline__ int64_t seg_cell(const SegArgs& a, int64_t i) {
+  if constexpr (MODE == 0) return i * a.nchan + blockIdx.x;
+  else if constexpr (MODE == 1) return (int64_t)blockIdx.x * a.nchan + i;
+  else return i;
+}
+
+// mu, sigma of the histogram fit (thread 0; cnt: the 64 bin counts)
+__device__ void hist_fit(const unsigned* cnt, int64_t N, double mu_m, double sg_m, double& mu,
+                         double& sg) {
+#pragma clang fp contract(off)
+  mu = mu_m;
+  sg = sg_m;
+  if (N < 8 || !(sg_m > 0.0)) return;
+  int nz = 0;
+  double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0, T0 = 0.0, T1 = 0.0, T2 = 0.0;
+  for (int i = 0; i < kBins; ++i) {
+    const unsigned c = cnt[i];
+    if (c == 0) continue;
+    ++nz;
+    const double z = ((double)i + 0.5) * 0.125 - 4.0;
+    const double y = log((double)c);
+    const double wt = (double)c * (double)c;
+    const double z2 = z * z;
+    S0 += wt;
+    S1 += wt * z;
+    S2 += wt * z2;
+    S3 += wt * (z2 * z);
+    S4 += wt * (z2 * z2);
+    T0 += wt * y;
+    T1 += wt * (z * y);
+    T2 += wt * (z2 * y);
+  }
+  if (nz < 3) return;
+  const double m0 = S2 * S4 - S3 * S3;
+  const double m1 = S1 * S4 - S3 * S2;
+  const double m2 = S1 * S3 - S2 * S2;
+  const double det = S0 * m0 - S1 * m1 + S2 * m2;
+  if (!(det != 0.0)) return;
+  const double db = S0 * (T1 * S4 - S3 * T2) - T0 * m1 + S2 * (S1 * T2 - T1 * S2);
+  const double dc = S0 * (S2 * T2 - T1 * S3) - S1 * (S1 * T2 - T1 * S2) + T0 * m2;
+  const double b = db / det;
+  const double c2 = dc / det;
+  if (!(c2 < 0.0)) return;
+  const double mu_z = -b / (2.0 * c2);
+  const double sg_z = sqrt(-1.0 / (2.0 * c2));
+  mu = mu_m + mu_z * sg_m;
+  sg = sg_z * sg_m;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kSegThreads) void segclip_kernel(SegArgs a) {
+  __shared__ Red3<kSegThreads> red;
+  __shared__ unsigned hcnt[kBins];
+  __shared__ int64_t sT;
+  __shared__ double sfit[3];
+  const int64_t m = MODE == 0 ? a.nsub : (MODE == 1 ? a.nchan : (int64_t)a.nsub * a.nchan);
+  const ClipJob J{a.nsub, a.nchan, a.max_iter, 0, a.kappa, a.stat, a.status, a.protect,
+                  nullptr, a.mask, nullptr, nullptr, 0};
+  const int64_t ncell = (int64_t)a.nsub * a.nchan;
+  if (threadIdx.x == 0) sT = INT64_MAX;
+  int64_t prevN = -1, N = 0, Nelig = -1;
+  u128 Q1 = 0, Q2 = 0;
+  int it = 0, converged = 1;
+  bool last_exact = true;
+  int64_t Nl = 0;                        // sums of the last fit
+  u128 Q1l = 0, Q2l = 0;
+  double mu = NAN, sigma = NAN, thr = NAN;
+  for (int guard = 0; guard <= a.max_iter + 1; ++guard) {
+    __syncthreads();
+    const int64_t T = sT;
+    __syncthreads();
+    int64_t n = 0;
+    u128 q1 = 0, q2 = 0;
+    for (int64_t i = threadIdx.x; i < m; i += kSegThreads) {
+      const CellLd x = load_cell(J, seg_cell<MODE>(a, i), ncell);
+      if (!elig(x)) continue;
+      const int64_t q = quant(x.s);
+      if (q <= T) acc(q, n, q1, q2);
+    }
+    block_sum3<kSegThreads>(n, q1, q2, red);
+    N = n; Q1 = q1; Q2 = q2;
+    if (Nelig < 0) Nelig = N;
+    if (it > 0 && N == prevN) break;
+    if (it > 0 && it >= a.max_iter) { converged = 0; break; }
+    if (N == 0) break;
+    Nl = N; Q1l = Q1; Q2l = Q2;
+    int64_t Tn;
+    if (a.fit == 0) {
+      bool ok;
+      Tn = fit_T_fast(N, Q1, Q2, a.kappa, ok);
+      last_exact = !ok;
+      if (!ok) {
+        if (threadIdx.x < 64) {
+          double m_, s_, t_;
+          fit_wave(N, Q1, Q2, a.kappa, m_, s_, t_);
+          if (threadIdx.x == 0) { sfit[0] = m_; sfit[1] = s_; sfit[2] = t_; }
+        }
+        __syncthreads();
+        mu = sfit[0]; sigma = sfit[1]; thr = sfit[2];
+        Tn = thr_to_T(thr);
+      }
+    } else {
+      // histogram fit: exact moments, the 64 bin counts of the live values, the parabola
+      if (threadIdx.x < 64) {
+        double m_, s_, t_;
+        fit_wave(N, Q1, Q2, a.kappa, m_, s_, t_);
+        if (threadIdx.x == 0) { sfit[0] = m_; sfit[1] = s_; }
+      }
+      for (int i = threadIdx.x; i < kBins; i += kSegThreads) hcnt[i] = 0;
+      __syncthreads();
+      const double mu_m = sfit[0], sg_m = sfit[1];
+      {
+#pragma clang fp contract(off)
+        const double lo = mu_m - 4.0 * sg_m;
+        const double w = sg_m * 0.125;
+        for (int64_t i = threadIdx.x; i < m; i += kSegThreads) {
+          const CellLd x = load_cell(J, seg_cell<MODE>(a, i), ncell);
+          if (!elig(x)) continue;
+          const int64_t q = quant(x.s);
+          if (q > T) continue;
+          const double v = (double)q / TWO40;
+          const double f = floor((v - lo) / w);
+          if (f >= 0.0 && f < (double)kBins) atomicAdd(&hcnt[(int)f], 1u);
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+#pragma clang fp contract(off)
+        double hm, hs;
+        hist_fit(hcnt, N, mu_m, sg_m, hm, hs);
+        const double ks = a.kappa * hs;
+        sfit[0] = hm; sfit[1] = hs; sfit[2] = hm + ks;
+      }
+      __syncthreads();
+      mu = sfit[0]; sigma = sfit[1]; thr = sfit[2];
+      Tn = thr_to_T(thr);
+      last_exact = true;
+    }
+    if (threadIdx.x == 0 && Tn < sT) sT = Tn;
+    ++it;
+    prevN = N;
+  }
+  if (a.fit == 0 && it > 0 && !last_exact) {
+    // the reported fit is the exact one, from the last fit's sums
+    if (threadIdx.x < 64) {
+      double m_, s_, t_;
+      fit_wave(Nl, Q1l, Q2l, a.kappa, m_, s_, t_);
+      if (threadIdx.x == 0) { sfit[0] = m_; sfit[1] = s_; sfit[2] = t_; }
+    }
+    __syncthreads();
+    mu = sfit[0]; sigma = sfit[1]; thr = sfit[2];
+  }
+  __syncthreads();
+  const int64_t T = sT;
+  for (int64_t i = threadIdx.x; i < m; i += kSegThreads) {
+    const int64_t c = seg_cell<MODE>(a, i);
+    const CellLd x = load_cell(J, c, ncell);
+    const uint8_t hit = (elig(x) && quant(x.s) > T) ? 1 : 0;
+    if (a.write) a.mask[c] = hit;
+    else if (hit) a.mask[c] = 1;
+  }
+  if (threadIdx.x == 0 && a.out) {
+    rfi_flag_stats& o = a.out[blockIdx.x];
+    o.mu = mu;
+    o.sigma = sigma;
+    o.thr = thr;
+    o.iterations = it;
+    o.converged = converged;
+    o.nflag = (Nelig < 0 ? 0 : Nelig) - N;
+    o.nfit = N;
+  }
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
 // Exact fit of given moment sums (the clip's arithmetic, for checking it):
 // one wavefront per entry.
 __global__ __launch_bounds__(256) void fit_kernel(int n, const int64_t* N, const uint64_t* Q1,
@@ -986,6 +1194,36 @@ hipError_t launch_clip_batch(const ClipJob* jobs, const ClipJob* host_jobs, int 
   if (nmask > 0)
     hipLaunchKernelGGL(clip_mask_kernel<true>, dim3(nmask, (unsigned)n), dim3(kGridThreads), 0, s,
                        none, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_clip_scoped(const ClipJob& g, int scopes, int fit, rfi_flag_stats* chan_out,
+                              rfi_flag_stats* sub_out, hipStream_t s) {
+  const int64_t ncell = (int64_t)g.nsub * g.nchan;
+  SegArgs a{g.nsub, g.nchan, g.max_iter, fit, g.kappa, g.stat, g.status, g.protect, g.mask,
+            nullptr, 0};
+  if (scopes & 1) {
+    if (fit == 0) {
+      hipError_t e = launch_clip(g, s);
+      if (e != hipSuccess) return e;
+    } else {
+      a.out = g.out;
+      a.write = 1;
+      hipLaunchKernelGGL(segclip_kernel<2>, dim3(1), dim3(kSegThreads), 0, s, a);
+    }
+  } else if (ncell > 0) {
+    const unsigned grid = (unsigned)std::min<int64_t>((ncell + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(grid), dim3(256), 0, s, g.mask, ncell);
+  }
+  a.write = 0;
+  if ((scopes & 2) && g.nsub > 0) {
+    a.out = chan_out;
+    hipLaunchKernelGGL(segclip_kernel<0>, dim3((unsigned)g.nchan), dim3(kSegThreads), 0, s, a);
+  }
+  if ((scopes & 4) && g.nsub > 0) {
+    a.out = sub_out;
+    hipLaunchKernelGGL(segclip_kernel<1>, dim3((unsigned)g.nsub), dim3(kSegThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -138,6 +138,12 @@ hipError_t launch_clip(const ClipJob& j, hipStream_t s);
 // The clips of n blocks: jobs in device memory, host_jobs the same
 // descriptors on the host (grid sizes).
 hipError_t launch_clip_batch(const ClipJob* jobs, const ClipJob* host_jobs, int n, hipStream_t s);
+// Clip scopes: scopes bit 1 = the global clip of g (the four-launch clip for
+// fit 0, a one-workgroup clip for the histogram fit 1), bit 2 = one clip per
+// channel, bit 4 = one clip per sub-interval; g.mask gets the union (zeroed
+// first when bit 1 is absent); chan_out [nchan] / sub_out [nsub] nullable.
+hipError_t launch_clip_scoped(const ClipJob& g, int scopes, int fit, rfi_flag_stats* chan_out,
+                              rfi_flag_stats* sub_out, hipStream_t s);
 // The clip's exact fit for given moment sums (device arrays of n entries;
 // Q1, Q2 as little-endian 64-bit limb pairs).
 hipError_t launch_fit(int n, const int64_t* N, const uint64_t* Q1, const uint64_t* Q2,

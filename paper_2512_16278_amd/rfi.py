@@ -25,6 +25,8 @@ RFI_MAX_COUNT_LONG = 262143
 RFI_HIST_CAP = 1024
 RFI_CCM_AUTO, RFI_CCM_MFMA, RFI_CCM_VALU = 0, 1, 2
 RFI_EIG_AUTO, RFI_EIG_LANE, RFI_EIG_WAVE, RFI_EIG_TRIDIAG, RFI_EIG_LANE_TRI = 0, 1, 2, 3, 4
+RFI_SCOPE_GLOBAL, RFI_SCOPE_CHANNEL, RFI_SCOPE_SUBINT = 1, 2, 4
+RFI_FIT_MOMENTS, RFI_FIT_HISTOGRAM = 0, 1
 
 
 class RfiError(RuntimeError):
@@ -155,6 +157,8 @@ def lib():
         L.rfi_flag_workspace_size.argtypes = [i32, i32]
         L.rfi_flag_workspace_size.restype = C.c_size_t
         L.rfi_clip_fit.argtypes = [i32, vp, vp, vp, dbl, vp, vp, vp, vp]
+        L.rfi_flag_scoped.argtypes = [i32, i32, vp, vp, vp, dbl, i32, i32, i32, vp, vp, vp, vp, vp,
+                                      vp]
         L.rfi_ccm_long_workspace_size.argtypes = [i32, i32, i32]
         L.rfi_ccm_long_workspace_size.restype = C.c_size_t
         L.rfi_ccm_accumulate_long.argtypes = [C.POINTER(rfi_block), i64, i32, i32, vp, vp, vp, vp]
@@ -194,6 +198,7 @@ def lib():
         L.rfi_stream_export.argtypes = [vp, i32, vp, C.POINTER(C.c_size_t)]
         L.rfi_stream_import.argtypes = [vp, i32, vp, C.c_size_t]
         for f in ("rfi_ccm_accumulate", "rfi_ccm_accumulate_long", "rfi_eig_batched_long",
+                  "rfi_flag_scoped",
                   "rfi_eig_batched", "rfi_flag", "rfi_clip_fit",
                   "rfi_flag_noalloc",
                   "rfi_eigvec_flag",
@@ -319,6 +324,19 @@ def rfi_flag_noalloc(nsub, nchan, stat, status, mask, protect_chan=None, kappa=3
 
 
 RFI_FLAG_NOALLOC_MAX_CELLS = 1 << 20
+
+
+def rfi_flag_scoped(nsub, nchan, stat, status, mask, scopes=RFI_SCOPE_GLOBAL,
+                    fit=RFI_FIT_MOMENTS, protect_chan=None, kappa=3.0, max_iter=50, out=None,
+                    chan_out=None, sub_out=None, workspace=None, stream=None):
+    """rfi_flag_scoped; workspace=None takes a buffer from torch when the
+    global moment clip needs one."""
+    if workspace is None and (scopes & RFI_SCOPE_GLOBAL) and fit == RFI_FIT_MOMENTS:
+        workspace = flag_workspace(nsub, nchan, stat.device)
+    _check(lib().rfi_flag_scoped(int(nsub), int(nchan), _ptr(stat), _ptr(status),
+                                 _ptr(protect_chan), float(kappa), int(max_iter), int(scopes),
+                                 int(fit), _ptr(mask), _ptr(out), _ptr(chan_out), _ptr(sub_out),
+                                 _ptr(workspace), _stream(stream)))
 
 
 def rfi_clip_fit(N, Q1, Q2, mu, sigma, thr, kappa=3.0, stream=None):
