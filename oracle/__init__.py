@@ -20,6 +20,8 @@ Modules (each function cites the passage of the paper it follows):
 * ``clip``     -- iterative one-sided Gaussian clipping of the statistic into
                   the combined mask (Sec. 3.3, Sec. 4.5 eigenvalue threshold),
                   batch and pooled-stream forms.
+* ``bandpass`` -- ArPLS bandpass (Sec. 3.1) and the non-centred CCM of the
+                  bandpass-subtracted power (the raw second-moment reading).
 * ``eigvec``   -- per-beam eigenvector threshold (Sec. 3.3 last paragraph,
                   Sec. 4.5 eigenvector threshold).
 * ``pipeline`` -- the whole per-block path composed from the above.
