@@ -180,6 +180,42 @@ rfi_status rfi_eig_batched_long(int32_t nbeam, int32_t nsub, int32_t nchan, cons
                                 const int32_t* count, float* eigvals, double* stat, float* v1,
                                 uint8_t* status, rfi_stream_t stream);
 
+/* ArPLS bandpass (Sec. 3.1; lam, ratio, itermax of Sec. 4.5): for every beam
+ * b and sub-interval k, the channel means y_j = sum_x[b][k nchan + j] /
+ * count[k] are fitted by asymmetrically reweighted penalised least squares
+ * (Baek et al. 2015): with D the second-difference operator over channels,
+ * solve (W + lam D^T D) z = W y (W = diag(w), w = 1 at first), d = y - z,
+ * m and s the mean and sample standard deviation (ddof 1) of the negative d,
+ * w' = 1 / (1 + exp(2 (d - (2 s - m)) / s)); stop when ||w - w'|| / ||w|| <
+ * ratio (keeping this pass's z), when fewer than two residuals are negative
+ * or s = 0, or after itermax passes. z[b][k nchan + j] (FP64) receives the
+ * baseline, the bandpass to subtract from every sample of the channel;
+ * passes[k nbeam + b] (nullable) the passes taken. Inputs in the rows layout
+ * of rfi_ccm_accumulate. workspace: rfi_bandpass_workspace_size bytes
+ * (caller-owned, one call at a time). One thread per (beam, sub-interval):
+ * the solve is sequential over the channels.
+ * Errors: RFI_E_INVALID for bad sizes, lam <= 0, ratio < 0, itermax < 1 or
+ * NULL pointers. */
+size_t rfi_bandpass_workspace_size(int32_t nbeam, int32_t nchan, int32_t nsub);
+rfi_status rfi_bandpass_arpls(int32_t nbeam, int32_t nsub, int32_t nchan, const int32_t* sum_x,
+                              const int32_t* count, double lam, double ratio, int32_t itermax,
+                              double* z, int32_t* passes, void* workspace, rfi_stream_t stream);
+
+/* The non-centred reading of Eq. 1's <B_a B_b> (Sec. 3.2) on the
+ * bandpass-subtracted power of Sec. 3.1: per cell the raw second-moment
+ * matrix
+ *     M_ab = (S_ab - z_b S_a - z_a S_b + count z_a z_b) / count
+ * of x - z (z[b][cell] from rfi_bandpass_arpls, or NULL for z = 0), each
+ * entry formed in FP64 in that order, then its eigenvalues by the FP64
+ * Householder-tridiagonal solver and stat = lambda_1^2 / ||M||_F^2 (Sec. 3.3).
+ * Sums in the rows layout of rfi_ccm_accumulate; outputs as rfi_eig_batched
+ * (eigvals, v1 nullable; status RFI_CELL_DEGENERATE where M = 0,
+ * RFI_CELL_BAD_COUNT where count < 2). */
+rfi_status rfi_eig_noncentred(int32_t nbeam, int32_t nsub, int32_t nchan, const int32_t* sum_x,
+                              const int32_t* sum_xy, const int32_t* count, const double* z,
+                              float* eigvals, double* stat, float* v1, uint8_t* status,
+                              rfi_stream_t stream);
+
 /* Clip summary written by rfi_flag (device struct). */
 typedef struct {
   double mu, sigma, thr;   /* last fit: mean, population sigma, mu + kappa sigma */

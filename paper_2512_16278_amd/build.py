@@ -1,7 +1,7 @@
 """Build the HIP libraries in-tree for gfx950 (hipcc cross-compiles; no GPU needed).
 
 librfi.so       -- the method (csrc/api.cpp, pipeline.cpp, ccm.hip, ccm_long.hip, eig_lane.hip,
-                   eig_wave.hip, eig_tri.hip, flag.hip, serve.cpp, batch.cpp)
+                   eig_wave.hip, eig_tri.hip, flag.hip, bandpass.hip, serve.cpp, batch.cpp)
 librfi_synth.so -- the GPU input generator (csrc/synth.hip) and the streaming-read
                    reference of the HBM roofline (csrc/stream_read.hip)
 
@@ -31,7 +31,7 @@ COMMON = [
 
 LIBS = {
     "librfi.so": ["api.cpp", "pipeline.cpp", "ccm.hip", "ccm_long.hip", "eig_lane.hip", "eig_wave.hip",
-                  "eig_tri.hip", "flag.hip", "serve.cpp", "batch.cpp"],
+                  "eig_tri.hip", "flag.hip", "bandpass.hip", "serve.cpp", "batch.cpp"],
     "librfi_synth.so": ["synth.hip", "stream_read.hip"],
 }
 

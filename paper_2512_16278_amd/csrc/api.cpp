@@ -197,6 +197,49 @@ rfi_status rfi_eig_batched_long(int32_t nbeam, int32_t nsub, int32_t nchan, cons
   return check_hip(rfi::launch_eig_tri(a, (hipStream_t)stream), "rfi_eig_batched_long launch");
 }
 
+size_t rfi_bandpass_workspace_size(int32_t nbeam, int32_t nchan, int32_t nsub) {
+  if (nbeam < 2 || nbeam > RFI_MAX_BEAMS || nchan < 1 || nsub < 0) return 0;
+  return rfi::bandpass_workspace_size(nbeam, nchan, nsub);
+}
+
+rfi_status rfi_bandpass_arpls(int32_t nbeam, int32_t nsub, int32_t nchan, const int32_t* sum_x,
+                              const int32_t* count, double lam, double ratio, int32_t itermax,
+                              double* z, int32_t* passes, void* workspace, rfi_stream_t stream) {
+  rfi::clear_error();
+  const char* who = "rfi_bandpass_arpls";
+  if (nbeam < 2 || nbeam > RFI_MAX_BEAMS || nsub < 0 || nchan < 1)
+    return fail(RFI_E_INVALID, "%s: bad sizes", who);
+  if ((int64_t)nsub * nchan > (int64_t)1 << 30 || (int64_t)nsub * nbeam > (int64_t)1 << 30)
+    return fail(RFI_E_INVALID, "%s: nsub * nchan or nsub * nbeam exceeds 2^30", who);
+  if (!(lam > 0.0) || !(ratio >= 0.0) || itermax < 1)
+    return fail(RFI_E_INVALID, "%s: lam must be > 0, ratio >= 0, itermax >= 1", who);
+  if (nsub == 0) return RFI_OK;
+  if (!sum_x || !count || !z || !workspace)
+    return fail(RFI_E_INVALID, "%s: NULL input, output or workspace", who);
+  return check_hip(rfi::launch_arpls(nbeam, nsub, nchan, sum_x, count, lam, ratio, itermax, z,
+                                     passes, workspace, (hipStream_t)stream),
+                   "rfi_bandpass_arpls launch");
+}
+
+rfi_status rfi_eig_noncentred(int32_t nbeam, int32_t nsub, int32_t nchan, const int32_t* sum_x,
+                              const int32_t* sum_xy, const int32_t* count, const double* z,
+                              float* eigvals, double* stat, float* v1, uint8_t* status,
+                              rfi_stream_t stream) {
+  rfi::clear_error();
+  const char* who = "rfi_eig_noncentred";
+  if (nbeam < 2 || nbeam > RFI_MAX_BEAMS)
+    return fail(RFI_E_INVALID, "%s: nbeam %d outside 2..%d", who, nbeam, RFI_MAX_BEAMS);
+  if (nsub < 0 || nchan < 1) return fail(RFI_E_INVALID, "%s: bad nsub/nchan", who);
+  if ((int64_t)nsub * nchan > (int64_t)1 << 30)
+    return fail(RFI_E_INVALID, "%s: nsub * nchan exceeds 2^30 cells", who);
+  if (nsub == 0) return RFI_OK;
+  if (!sum_x || !sum_xy || !count || !stat || !status)
+    return fail(RFI_E_INVALID, "%s: NULL input or output", who);
+  rfi::EigArgs a{nbeam, nsub, nchan, sum_x, sum_xy, count, 12, 1, eigvals, stat, v1, status,
+                 (int64_t)nsub * nchan, 0};
+  return check_hip(rfi::launch_eig_tri_nc(a, z, (hipStream_t)stream), "rfi_eig_noncentred launch");
+}
+
 size_t rfi_flag_workspace_size(int32_t nsub, int32_t nchan) {
   if (nsub < 0 || nchan < 1) return 0;
   return rfi::clip_workspace_size((int64_t)nsub * nchan);

@@ -200,11 +200,15 @@ __device__ __forceinline__ int find_item_t(const int64_t* cell0, int nitem, int6
 // bound, summed in time chunks and widened); such cells read n L >= 66,050
 // bytes each, so their eigen stage is never the bound and one wave per SIMD
 // (room for the wider LDS copy of the sums) costs nothing.
-template <int NL, bool W = false>
-__global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(EigArgs g,
-                                                                      const EigArgs* items,
-                                                                      const int64_t* cell0,
-                                                                      int nitem, int vcap) {
+// NC: the non-centred matrix of the bandpass-subtracted power instead of the
+// correlation matrix: M_ab = (S_ab - z_b S_a - z_a S_b + L z_a z_b) / L from
+// the exact sums and the baseline zb [nbeam][ncell] (NULL: 0), every entry
+// formed in that operation order (no fused multiply-add), ||M||_F^2 over all
+// entries.
+template <int NL, bool W = false, bool NC = false>
+__global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_kernel(
+    EigArgs g, const EigArgs* items, const int64_t* cell0, int nitem, int vcap,
+    const double* zb) {
   constexpr int NN = 8 * NL;
   using ST = std::conditional_t<W, int64_t, int32_t>;
   __shared__ double X[NN], P[NN], alpha[NN], offd[NN], tau[NN], dinv[NN], z[NN];
@@ -254,11 +258,15 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(Ei
   __syncthreads();
   int dead = 0;
   for (int a = lane; a < n; a += 64) {
-    const int64_t Naa = cnt * (int64_t)SP[pidx(a, a, n)] - (int64_t)S[a] * S[a];
-    dinv[a] = Naa > 0 ? 1.0 / sqrt((double)Naa) : 0.0;
-    dead |= Naa <= 0;
+    if constexpr (NC) {
+      dinv[a] = zb ? zb[(int64_t)a * ncell + cell] : 0.0;     // the baseline z_a
+    } else {
+      const int64_t Naa = cnt * (int64_t)SP[pidx(a, a, n)] - (int64_t)S[a] * S[a];
+      dinv[a] = Naa > 0 ? 1.0 / sqrt((double)Naa) : 0.0;
+      dead |= Naa <= 0;
+    }
   }
-  const int degenerate = __syncthreads_or(dead);
+  int degenerate = __syncthreads_or(dead);
   double A[NL][NL];
   double offsq = 0.0;
   static_for<0, NL>([&](auto II) {
@@ -267,7 +275,16 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(Ei
       constexpr int jj = RFI_CI(JJ);
       const int gi = r + 8 * ii, gj = c + 8 * jj;
       double val = 0.0;
-      if (gi < n && gj < n) {
+      if constexpr (NC) {
+        if (gi < n && gj < n) {
+#pragma clang fp contract(off)
+          const int a = gi < gj ? gi : gj, b = gi < gj ? gj : gi;
+          const double Lc = (double)cnt, za = dinv[a], zbv = dinv[b];
+          const double Sa = (double)S[a], Sb = (double)S[b];
+          val = ((((double)SP[pidx(a, b, n)] - zbv * Sa) - za * Sb) + (Lc * za) * zbv) / Lc;
+          offsq += gi == gj ? val * val : (gi < gj ? 2.0 * val * val : 0.0);
+        }
+      } else if (gi < n && gj < n) {
         if (gi == gj) {
           val = 1.0;
         } else {
@@ -280,7 +297,8 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(Ei
       A[ii][jj] = val;
     });
   });
-  const double frob2 = (double)n + 2.0 * wave_sum(offsq);
+  const double frob2 = NC ? wave_sum(offsq) : (double)n + 2.0 * wave_sum(offsq);
+  if constexpr (NC) degenerate = !(frob2 > 0.0);
 
   // Householder reduction: steps k = 0 .. n - 2 (the last one only records
   // the final sub-diagonal entry)
@@ -408,8 +426,11 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(Ei
   // The bracket stops at 2e-14 relative width, the order of the backward
   // error of the FP64 reduction itself.
   constexpr int NP = 1;
+  // a correlation matrix has lambda_1 >= 1; the non-centred matrix has the
+  // scale of the data, so its stop is relative only
+  constexpr double kFloor = NC ? 1e-300 : 1.0;
   double lo = fmax(glo, lb - 1e-12 * span), hi = ghi;
-  for (int it = 0; it < 16 && hi - lo > 2e-14 * fmax(fabs(hi), 1.0); ++it) {
+  for (int it = 0; it < 16 && hi - lo > 2e-14 * fmax(fabs(hi), kFloor); ++it) {
     const double h = (hi - lo) * (1.0 / (64 * NP + 1));
     double xs[NP];
     int cn[NP];
@@ -431,7 +452,7 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(Ei
   const double lam1 = 0.5 * (lo + hi);
 
   if (lane == 0) {
-    g.stat[cell] = lam1 * lam1 / frob2;
+    g.stat[cell] = (NC && degenerate) ? 0.0 : lam1 * lam1 / frob2;
     g.status[cell] = degenerate ? RFI_CELL_DEGENERATE : 0;
   }
 
@@ -441,7 +462,7 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(Ei
     // is index n - 1 - i
     for (int i = lane; i < n; i += 64) {
       double a = glo, b = ghi;
-      for (int it = 0; it < 64 && b - a > 2e-16 * fmax(fabs(b), 1.0); ++it) {
+      for (int it = 0; it < 64 && b - a > 2e-16 * fmax(fabs(b), kFloor); ++it) {
         const double mid = 0.5 * (a + b);
         if (sturm_below(ae, n, mid) > i) b = mid; else a = mid;
       }
@@ -471,7 +492,7 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(Ei
     // Gaussian elimination with partial pivoting of the tridiagonal into
     // U = (ud, ue, uf) (diagonal and two upper diagonals), then back
     // substitution; three iterations from the all-ones vector
-    if (lane == 0) tri_inverse_iteration(alpha, offd, n, lam1 + 1e-13 * fmax(fabs(lam1), 1.0),
+    if (lane == 0) tri_inverse_iteration(alpha, offd, n, lam1 + 1e-13 * fmax(fabs(lam1), kFloor),
                                          X, P, dinv, z);
     __syncthreads();
     // back-transform: v1 = H_0 H_1 ... H_{n-3} z, applied from the last
@@ -497,30 +518,31 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W) ? 2 : 1) void eig_tri_kernel(Ei
   }
 }
 
-template <int NL, bool W>
+template <int NL, bool W, bool NC>
 hipError_t launch_nl(int nbeam, const EigArgs& a, const EigArgs* items, const int64_t* cell0,
-                     int nitem, int64_t total, bool v1, hipStream_t s) {
+                     int nitem, int64_t total, bool v1, const double* zb, hipStream_t s) {
   const int vcap = v1 ? (nbeam - 1) * 8 * NL : 0;
   const size_t shm = (size_t)vcap * sizeof(double);
   if (shm > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)eig_tri_kernel<NL, W>,
+    hipError_t e = hipFuncSetAttribute((const void*)eig_tri_kernel<NL, W, NC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((eig_tri_kernel<NL, W>), dim3((unsigned)total), dim3(64), shm, s, a, items,
-                     cell0, nitem, vcap);
+  hipLaunchKernelGGL((eig_tri_kernel<NL, W, NC>), dim3((unsigned)total), dim3(64), shm, s, a,
+                     items, cell0, nitem, vcap, zb);
   return hipGetLastError();
 }
 
-template <bool W>
+template <bool W, bool NC = false>
 hipError_t launch_cls(int cls, int nbeam, const EigArgs& a, const EigArgs* items,
-                      const int64_t* cell0, int nitem, int64_t total, bool v1, hipStream_t s) {
+                      const int64_t* cell0, int nitem, int64_t total, bool v1, hipStream_t s,
+                      const double* zb = nullptr) {
   switch (cls) {
-    case 3: return launch_nl<3, W>(nbeam, a, items, cell0, nitem, total, v1, s);
-    case 5: return launch_nl<5, W>(nbeam, a, items, cell0, nitem, total, v1, s);
-    case 8: return launch_nl<8, W>(nbeam, a, items, cell0, nitem, total, v1, s);
-    case 9: return launch_nl<9, W>(nbeam, a, items, cell0, nitem, total, v1, s);
-    case 10: return launch_nl<10, W>(nbeam, a, items, cell0, nitem, total, v1, s);
+    case 3: return launch_nl<3, W, NC>(nbeam, a, items, cell0, nitem, total, v1, zb, s);
+    case 5: return launch_nl<5, W, NC>(nbeam, a, items, cell0, nitem, total, v1, zb, s);
+    case 8: return launch_nl<8, W, NC>(nbeam, a, items, cell0, nitem, total, v1, zb, s);
+    case 9: return launch_nl<9, W, NC>(nbeam, a, items, cell0, nitem, total, v1, zb, s);
+    case 10: return launch_nl<10, W, NC>(nbeam, a, items, cell0, nitem, total, v1, zb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -545,6 +567,13 @@ hipError_t launch_eig_tri(const EigArgs& a, hipStream_t s) {
                             a.v1 != nullptr, s);
   return launch_cls<false>(eig_tri_class(a.nbeam), a.nbeam, a, nullptr, nullptr, 0, ncell,
                            a.v1 != nullptr, s);
+}
+
+hipError_t launch_eig_tri_nc(const EigArgs& a, const double* zb, hipStream_t s) {
+  const int64_t ncell = (int64_t)a.nsub * a.nchan;
+  if (ncell == 0) return hipSuccess;
+  return launch_cls<false, true>(eig_tri_class(a.nbeam), a.nbeam, a, nullptr, nullptr, 0, ncell,
+                                 a.v1 != nullptr, s, zb);
 }
 
 hipError_t launch_eig_tri_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,

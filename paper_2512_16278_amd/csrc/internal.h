@@ -107,6 +107,17 @@ int eig_tri_class(int n);
 hipError_t launch_eig_tri_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
                                 int64_t total, hipStream_t s);
 
+// ArPLS bandpass of every (beam, sub-interval) from the channel sums (rows
+// layout sum_x[b][cell]); z [nbeam][ncell] FP64; passes [nsub][nbeam] or NULL;
+// ws: bandpass_workspace_size bytes.
+size_t bandpass_workspace_size(int nbeam, int nchan, int nsub);
+hipError_t launch_arpls(int nbeam, int nsub, int nchan, const int32_t* sum_x,
+                        const int32_t* count, double lam, double ratio, int itermax, double* z,
+                        int32_t* passes, void* ws, hipStream_t s);
+// The FP64 tridiagonal solver on the non-centred matrix of the bandpass-
+// subtracted power (zb [nbeam][ncell] or NULL), sums in the rows layout.
+hipError_t launch_eig_tri_nc(const EigArgs& a, const double* zb, hipStream_t s);
+
 // One clip problem (device descriptor): the cells of one block, its outputs
 // and its workspace (clip_workspace_size bytes, 256-byte aligned, holding at
 // most tail_cap tail entries).

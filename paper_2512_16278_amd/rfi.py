@@ -164,6 +164,10 @@ def lib():
         L.rfi_ccm_accumulate_long.argtypes = [C.POINTER(rfi_block), i64, i32, i32, vp, vp, vp, vp]
         L.rfi_eig_batched_long.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.rfi_flag_noalloc.argtypes = [i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp]
+        L.rfi_bandpass_workspace_size.argtypes = [i32, i32, i32]
+        L.rfi_bandpass_workspace_size.restype = C.c_size_t
+        L.rfi_bandpass_arpls.argtypes = [i32, i32, i32, vp, vp, dbl, dbl, i32, vp, vp, vp, vp]
+        L.rfi_eig_noncentred.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.rfi_process_workspace_size.argtypes = [i32, i32, C.POINTER(rfi_process_params)]
         L.rfi_process_workspace_size.restype = C.c_size_t
@@ -200,7 +204,7 @@ def lib():
         for f in ("rfi_ccm_accumulate", "rfi_ccm_accumulate_long", "rfi_eig_batched_long",
                   "rfi_flag_scoped",
                   "rfi_eig_batched", "rfi_flag", "rfi_clip_fit",
-                  "rfi_flag_noalloc",
+                  "rfi_flag_noalloc", "rfi_bandpass_arpls", "rfi_eig_noncentred",
                   "rfi_eigvec_flag",
                   "rfi_process_block", "rfi_session_create", "rfi_stream_open",
                   "rfi_stream_close", "rfi_submit", "rfi_poll", "rfi_wait", "rfi_cancel",
@@ -290,6 +294,30 @@ def rfi_eig_batched(nbeam, nsub, nchan, sum_x, sum_xy, count, stat, status, eigv
     _check(lib().rfi_eig_batched(int(nbeam), int(nsub), int(nchan), _ptr(sum_x), _ptr(sum_xy),
                                  _ptr(count), C.byref(p), _ptr(eigvals), _ptr(stat), _ptr(v1),
                                  _ptr(status), _stream(stream)))
+
+
+def rfi_bandpass_workspace_size(nbeam, nchan, nsub):
+    return int(lib().rfi_bandpass_workspace_size(int(nbeam), int(nchan), int(nsub)))
+
+
+def rfi_bandpass_arpls(nbeam, nsub, nchan, sum_x, count, z, workspace=None, passes=None,
+                       lam=1e5, ratio=0.05, itermax=100, stream=None):
+    """ArPLS baselines z [nbeam, nsub * nchan] (FP64) from the channel sums;
+    the workspace is allocated with torch when not given."""
+    if workspace is None:
+        import torch
+        workspace = torch.empty(max(rfi_bandpass_workspace_size(nbeam, nchan, nsub), 1),
+                                dtype=torch.uint8, device=z.device)
+    _check(lib().rfi_bandpass_arpls(int(nbeam), int(nsub), int(nchan), _ptr(sum_x), _ptr(count),
+                                    float(lam), float(ratio), int(itermax), _ptr(z), _ptr(passes),
+                                    _ptr(workspace), _stream(stream)))
+
+
+def rfi_eig_noncentred(nbeam, nsub, nchan, sum_x, sum_xy, count, z, stat, status, eigvals=None,
+                       v1=None, stream=None):
+    _check(lib().rfi_eig_noncentred(int(nbeam), int(nsub), int(nchan), _ptr(sum_x), _ptr(sum_xy),
+                                    _ptr(count), _ptr(z), _ptr(eigvals), _ptr(stat), _ptr(v1),
+                                    _ptr(status), _stream(stream)))
 
 
 def rfi_flag_workspace_size(nsub, nchan):

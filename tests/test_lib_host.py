@@ -95,6 +95,17 @@ def test_argument_errors_are_synchronous():
     assert L.rfi_clip_fit(4, None, None, None, 3.0, None, None, None, None) == rfi.RFI_E_INVALID
     assert L.rfi_flag_noalloc(1 << 11, 1 << 10, C.c_void_p(256), C.c_void_p(256), None, 3.0,
                               50, None, C.c_void_p(256), None, None) == rfi.RFI_E_INVALID
+    # ArPLS bandpass and the non-centred matrix: argument checks before any launch
+    assert rfi.rfi_bandpass_workspace_size(19, 4096, 1) == 6 * 19 * 4096 * 8
+    assert rfi.rfi_bandpass_workspace_size(1, 4096, 1) == 0
+    v = C.c_void_p(256)
+    assert L.rfi_bandpass_arpls(19, 1, 64, v, v, 0.0, 0.05, 100, v, None, v, None) == rfi.RFI_E_INVALID
+    assert L.rfi_bandpass_arpls(19, 1, 64, v, v, 1e5, -0.1, 100, v, None, v, None) == rfi.RFI_E_INVALID
+    assert L.rfi_bandpass_arpls(19, 1, 64, v, v, 1e5, 0.05, 0, v, None, v, None) == rfi.RFI_E_INVALID
+    assert L.rfi_bandpass_arpls(19, 1, 64, v, v, 1e5, 0.05, 100, v, None, None, None) == rfi.RFI_E_INVALID
+    assert L.rfi_bandpass_arpls(19, 0, 64, None, None, 1e5, 0.05, 100, None, None, None, None) == rfi.RFI_OK
+    assert L.rfi_eig_noncentred(80, 1, 64, v, v, v, None, None, v, None, v, None) == rfi.RFI_E_INVALID
+    assert L.rfi_eig_noncentred(19, 1, 64, v, None, v, None, None, v, None, v, None) == rfi.RFI_E_INVALID
 
 
 def test_struct_layouts_match_header():
