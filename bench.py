@@ -5,18 +5,22 @@ Workload: FAST-shaped block, 19 beams x 4096 channels of uint8 total power,
 49.152 us samples, 10 s of data (203,450 samples), 2048-sample sub-intervals
 (99 full sub-intervals; the 698-sample tail is not a full cell), synthetic
 (seeded, generated on the GPU, device-resident before timing). One step is
-one pass of the whole path over the block, by default the single call
-
-    rfi_process_block   (sums -> eigen -> clip, sub-interval groups pipelined)
-
-or, with --path stages, the three calls
+one pass of the whole path over the block, by default the three calls
 
     rfi_ccm_accumulate -> rfi_eig_batched -> rfi_flag
 
+with HIP events recorded between them on the launch stream in every timed
+step, or, with --path fused, the single call rfi_process_block (the same
+kernels behind one entry point; also timed below the main figure).
+
 Metric: beam-sample GB/s = nbeam * nchan * nsub * L bytes / step time.
-The roofline object is for the dominant kernel, timed with HIP events around
-its own launches in the three-call path (one launch per step over the whole
-block). Prints one JSON line (see the keys below).
+The roofline object is for the dominant kernel (the sums kernel, one launch
+per step over the whole block): achieved = its algorithmic bytes per launch
+(n L input bytes per cell x nsub * nchan cells; the int32 sums it writes are
+intermediate, reported apart) / its mean launch time from the events of the
+timed steps. The CPU baseline times the FP64 oracle on a bounded sample, on
+one thread and on all host cores (one worker process per channel strip).
+Prints one JSON line (see the keys below).
 """
 from __future__ import annotations
 
@@ -39,33 +43,87 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(spec, nsub_sample: int, nchan_sample: int):
-    """The FP64 oracle, as it stands, on a bounded sample: the first
-    nchan_sample channels of the first nsub_sample sub-intervals (bytes
-    regenerated on the CPU)."""
+def _oracle_strip(task):
+    """Worker of the all-core CPU baseline: regenerate channels [c_lo, c_hi)
+    of the first nsub sub-intervals (not timed), then run the oracle's
+    per-cell part on them (BLAS limited to one thread by the environment)."""
+    seconds, nsub, c_lo, c_hi = task
     from oracle import pipeline
     from paper_2512_16278_amd import synth
+    spec = synth.fast_spec(seconds=seconds)
+    x = synth.generate(spec, 0, nsub * spec.L, c_lo, c_hi)
+    t0 = time.time()
+    cr = pipeline.cells(x, spec.L, nsub)
+    t1 = time.time()
+    return c_lo, cr.stat, cr.degenerate, t0, t1, int(x.size)
+
+
+def cpu_baseline(spec, seconds: float, nsub_sample: int, nchan_single: int, nchan_all: int):
+    """The FP64 oracle, as it stands, on bounded samples of the same block
+    (bytes regenerated on the CPU, generation not timed):
+
+    * one thread (BLAS pools limited to 1): the whole path -- sums,
+      correlation, eigen, statistic, clip -- on channels 0..nchan_single-1 of
+      the first nsub_sample sub-intervals;
+    * all host cores: one worker process per channel strip of channels
+      0..nchan_all-1 (BLAS 1 thread each) runs the per-cell part, the parent
+      clips the gathered statistic; wall time from the first worker's start
+      to the last one's end, plus the clip.
+    """
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import threadpoolctl
+    from oracle import clip, pipeline
+    from paper_2512_16278_amd import synth
     L = spec.L
+    host = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    x = synth.generate(spec, 0, nsub_sample * L, 0, nchan_sample)
-    tgen = time.perf_counter() - t0
-    log(f"cpu baseline: sample generated in {tgen:.1f} s; running the oracle")
-    t0 = time.perf_counter()
-    cr, res, _ = pipeline.block(x, L, nsub_sample)
-    dt = time.perf_counter() - t0
-    nbytes = x.size
+    x = synth.generate(spec, 0, nsub_sample * L, 0, nchan_single)
+    log(f"cpu baseline: sample generated in {time.perf_counter() - t0:.1f} s; "
+        f"one thread on {x.size / 1e6:.0f} MB")
+    with threadpoolctl.threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        pipeline.block(x, L, nsub_sample)
+        dt1 = time.perf_counter() - t0
+    single = {"value": x.size / dt1 / 1e9, "unit": "GB/s", "cores": 1, "seconds": round(dt1, 2),
+              "sample": f"channels 0..{nchan_single - 1} x {nsub_sample} sub-int(s) of {L} "
+                        f"samples x {spec.nbeam} beams ({x.size / 1e6:.0f} MB)"}
+    del x
+    workers = max(1, min(host, 16))
+    edges = np.linspace(0, nchan_all, workers + 1).astype(int)
+    tasks = [(seconds, nsub_sample, int(edges[i]), int(edges[i + 1])) for i in range(workers)
+             if edges[i + 1] > edges[i]]
+    env_keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in env_keys}
+    for k in env_keys:
+        os.environ[k] = "1"
     try:
-        import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        cores = max([i.get("num_threads", 1) for i in info] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+        # a worker that dies raises here instead of being replaced
+        with ProcessPoolExecutor(len(tasks), mp_context=mp.get_context("spawn")) as pool:
+            parts = list(pool.map(_oracle_strip, tasks))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    parts.sort(key=lambda p: p[0])
+    stat = np.concatenate([p[1] for p in parts], axis=1)
+    deg = np.concatenate([p[2] for p in parts], axis=1)
+    with threadpoolctl.threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        clip.clip_iterative(stat, pipeline.eligible_cells(deg), 3.0, 50)
+        dclip = time.perf_counter() - t0
+    wall = max(p[4] for p in parts) - min(p[3] for p in parts) + dclip
+    nbytes = sum(p[5] for p in parts)
     return {
-        "value": nbytes / dt / 1e9, "unit": "GB/s", "cores": int(cores), "kind": "oracle",
-        "sample": f"channels 0..{nchan_sample - 1} x {nsub_sample} sub-int(s) of {L} samples x "
-                  f"{spec.nbeam} beams ({nbytes / 1e6:.0f} MB, {nsub_sample * nchan_sample} cells); "
-                  f"oracle {dt:.2f} s, input generation {tgen:.1f} s not timed",
-        "seconds": dt,
+        "value": nbytes / wall / 1e9, "unit": "GB/s", "cores": len(tasks), "kind": "oracle",
+        "sample": f"channels 0..{nchan_all - 1} x {nsub_sample} sub-int(s) of {L} samples x "
+                  f"{spec.nbeam} beams ({nbytes / 1e6:.0f} MB, {nsub_sample * nchan_all} cells) "
+                  f"in {len(tasks)} channel strips, one worker process each, BLAS 1 thread; "
+                  f"the parent clips the gathered statistic",
+        "seconds": round(wall, 2), "host_cores": host, "single_thread": single,
     }
 
 
@@ -346,10 +404,13 @@ def main():
     ap.add_argument("--variant", default="mfma", choices=["mfma", "valu"])
     ap.add_argument("--precision", type=int, default=32, choices=[32, 64])
     ap.add_argument("--cpu-sample-subints", type=int, default=1)
-    ap.add_argument("--cpu-sample-chans", type=int, default=1024)
+    ap.add_argument("--cpu-sample-chans", type=int, default=1024,
+                    help="channels of the one-thread oracle sample")
+    ap.add_argument("--cpu-sample-chans-all", type=int, default=4096,
+                    help="channels of the all-core oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seconds", type=float, default=10.0)
-    ap.add_argument("--path", default="fused", choices=["fused", "stages"])
+    ap.add_argument("--path", default="stages", choices=["fused", "stages"])
     ap.add_argument("--group", type=int, default=0, help="sub-intervals per pipeline group")
     ap.add_argument("--serve-rates", default="200,2000",
                     help="arrival rates (blocks/s) of the serving run; empty = skip it")
@@ -430,26 +491,24 @@ def main():
     variant = rfi.RFI_CCM_MFMA if args.variant == "mfma" else rfi.RFI_CCM_VALU
     stream = torch.cuda.current_stream()
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     pp = rfi.process_params(L, nsub, group=args.group, eig_precision=args.precision)
     pws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, pp), dtype=torch.uint8, device=dev)
 
-    def step_stages(timed=None):
-        if timed is not None:
-            ev[0].record(stream)
+    def step_stages(evs=None):
+        # evs: four events recorded on the launch stream around the three calls
+        if evs is not None:
+            evs[0].record(stream)
         rfi.rfi_ccm_accumulate(blk, 0, L, nsub, sx, sxy, cnt, variant=variant)
-        if timed is not None:
-            ev[1].record(stream)
+        if evs is not None:
+            evs[1].record(stream)
         rfi.rfi_eig_batched(nb, nsub, nc, sx, sxy, cnt, stat, status, precision=args.precision)
-        if timed is not None:
-            ev[2].record(stream)
+        if evs is not None:
+            evs[2].record(stream)
         rfi.rfi_flag(nsub, nc, stat, status, mask, out=fstats, workspace=fws)
-        if timed is not None:
-            ev[3].record(stream)
-            torch.cuda.synchronize()
-            timed.append([ev[i].elapsed_time(ev[i + 1]) for i in range(3)])
+        if evs is not None:
+            evs[3].record(stream)
 
-    def step_fused():
+    def step_fused(evs=None):
         rfi.rfi_process_block(blk, pp, stat, status, mask, pws, out=fstats)
 
     step = step_fused if args.path == "fused" else step_stages
@@ -464,13 +523,16 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
-    # whole-step timing: K steps back to back between two synchronisations
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
+    # timed region: K steps back to back between two synchronisations; in the
+    # three-call path every step also records events between its calls (on
+    # the launch stream), which time the dominant kernel live
+    mk = lambda: torch.cuda.Event(enable_timing=True)          # noqa: E731
+    sev = [[mk() for _ in range(4)] for _ in range(args.steps)]
+    t_start, t_end = mk(), mk()
     torch.cuda.synchronize()
     t_start.record(stream)
-    for _ in range(args.steps):
-        step()
+    for i in range(args.steps):
+        step(sev[i] if args.path == "stages" else None)
     t_end.record(stream)
     torch.cuda.synchronize()
     ms_total = t_start.elapsed_time(t_end)
@@ -486,7 +548,7 @@ def main():
 
     # block latency: each step alone, from an event before it to one after it
     lat = []
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = mk(), mk()
     for _ in range(max(10, min(args.steps, 30))):
         e0.record(stream)
         step()
@@ -495,22 +557,36 @@ def main():
         lat.append(e0.elapsed_time(e1))
     lat = np.array(lat)
 
-    # per-kernel timing in the three-call path (events between the calls)
-    stages = []
-    for _ in range(max(3, min(args.steps, 10))):
-        step_stages(stages)
-    st = np.array(stages)
-    ms_ccm, ms_eig, ms_flag = np.median(st, axis=0)
-    log(f"stages (median ms): ccm {ms_ccm:.3f}  eig {ms_eig:.3f}  flag {ms_flag:.3f}")
+    # per-call times: from the timed steps themselves in the three-call path,
+    # else from separate three-call steps
+    if args.path != "stages":
+        sev = [[mk() for _ in range(4)] for _ in range(max(3, min(args.steps, 10)))]
+        for evs in sev:
+            step_stages(evs)
+        torch.cuda.synchronize()
+    st = np.array([[evs[i].elapsed_time(evs[i + 1]) for i in range(3)] for evs in sev])
+    ms_ccm, ms_eig, ms_flag = st.mean(axis=0)
+    med = np.median(st, axis=0)
+    log(f"calls (mean ms): ccm {ms_ccm:.3f}  eig {ms_eig:.3f}  flag {ms_flag:.3f}")
+    # the other entry point over the same block, for comparison
+    other = step_fused if args.path == "stages" else step_stages
+    for _ in range(2):
+        other()
+    torch.cuda.synchronize()
+    o0, o1 = mk(), mk()
+    o0.record(stream)
+    for _ in range(args.steps):
+        other()
+    o1.record(stream)
+    torch.cuda.synchronize()
+    ms_other = o0.elapsed_time(o1) / args.steps
     # the timed path's own outputs, for the summary
     step()
     torch.cuda.synchronize()
 
     nbytes_in = nb * nc * nsub * L
     value = nbytes_in / (ms_step / 1e3) / 1e9
-    # dominant kernel and its roofline
-    ccm_bytes = nbytes_in + 4 * (nb + npair) * ncell          # bytes in + sums out
-    ccm_gbs = ccm_bytes / (ms_ccm / 1e3) / 1e9
+    sums_bytes = 4 * (nb + npair) * ncell
     flags = rfi.flag_stats_from_bytes(fstats.cpu().numpy().tobytes())
     # HBM bytes of the sums kernel from the committed counter summary, while
     # the kernel's source is the one those counters were taken on
@@ -522,11 +598,16 @@ def main():
         if rec.get("source_sha256") == prof_summary.source_hash() and rec.get("traffic_bytes"):
             traffic = int(rec["traffic_bytes"])
     if ms_ccm >= ms_eig:
-        roof = {"kernel": "ccm_mfma_kernel (64-channel tile, one launch per block)"
+        ccm_gbs = nbytes_in / (ms_ccm / 1e3) / 1e9
+        roof = {"kernel": "ccm_mfma_kernel (64-channel tiles, one launch per block)"
                           if variant == rfi.RFI_CCM_MFMA else "ccm_valu_kernel",
                 "bound": "hbm", "achieved": round(ccm_gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ccm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "ms": round(float(ms_ccm), 4)}
+                "ms": round(float(ms_ccm), 4), "algorithmic_bytes": nbytes_in,
+                "sums_write_bytes": sums_bytes,
+                "derivation": f"{nb} beams x {L} samples = {nb * L} input bytes per cell x "
+                              f"{ncell} cells per launch / mean launch time over the "
+                              f"{len(sev)} event-timed steps / {HBM_PEAK_GBS:.0f} GB/s"}
     else:
         # algorithmic FP32 flops of the Jacobi: per sweep n(n-1)/2 rotations of
         # 6(n-2) + 12 flops; 6 sweeps (the typical count on noise-dominated cells)
@@ -571,14 +652,17 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(spec, args.cpu_sample_subints, args.cpu_sample_chans)
-        log(f"cpu baseline: {cpu['value'] * 1e3:.2f} MB/s on {cpu['cores']} threads")
+        cpu = cpu_baseline(spec, args.seconds, args.cpu_sample_subints, args.cpu_sample_chans,
+                           args.cpu_sample_chans_all)
+        log(f"cpu baseline: {cpu['value'] * 1e3:.2f} MB/s on {cpu['cores']} workers, "
+            f"{cpu['single_thread']['value'] * 1e3:.2f} MB/s on one thread")
 
     out = {
         "metric": "beam-sample GB/s through CCM+eigen+flag at 1 GPU; p50/p99 block latency",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "int8 MFMA -> int32 sums, f64 correlation, f32 eigen + f64 refinement, f64 clip",
         "data": "synthetic (seeded FAST-shaped, generated on the GPU)",
         "config": {"workload": f"FAST-shaped block: {nb} beams x {nc} channels x {ns} samples "
                                f"(10 s at 49.152 us), L={L}, {nsub} sub-ints, "
@@ -588,8 +672,12 @@ def main():
                              else "fp64 jacobi")},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
-        "stages_ms": {"path": "three calls", "ccm": round(float(ms_ccm), 4),
+        "stages_ms": {"path": "three calls", "mean": {"ccm": round(float(ms_ccm), 4),
                       "eig": round(float(ms_eig), 4), "flag": round(float(ms_flag), 4)},
+                      "median": {"ccm": round(float(med[0]), 4), "eig": round(float(med[1]), 4),
+                                 "flag": round(float(med[2]), 4)}},
+        ("fused_ms_per_step" if args.path == "stages" else "stages_ms_per_step"):
+            round(ms_other, 4),
         "hbm_frac_whole_path": round(value / HBM_PEAK_GBS, 4),
         "stream_read_gbs": round(read_gbs, 1),
         "frac_of_measured_read": round(value / read_gbs, 4),
