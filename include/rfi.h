@@ -352,7 +352,9 @@ rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const flo
  * 1 GiB. The results equal those of the three separate calls bit for bit
  * (same arithmetic, whatever the grouping).
  * Outputs: stat, status, mask [ncell] as in rfi_eig_batched / rfi_flag;
- * eigvals [nbeam][ncell] and v1 [nbeam][ncell] are optional (NULL). state,
+ * eigvals [nbeam][ncell] and v1 [nbeam][ncell] are optional (NULL); with
+ * p->beam_mask the per-beam stage runs after the clip (the paper's final
+ * output: which beams of a masked cell carry the interference). state,
  * protect_chan and out as in rfi_flag. The call is asynchronous on `stream`
  * (all work, including the helper stream's, completes before later work on
  * `stream` starts). Calls that run concurrently from several host threads
@@ -374,6 +376,11 @@ typedef struct {
   int32_t max_sweeps;    /* 0 = 12 */
   int32_t max_iter;      /* clip fits, 0 = 50 */
   double kappa;          /* clip multiple (Sec. 4.5), >= 0 */
+  double kappa_v;        /* per-beam eigenvector multiple (Sec. 4.5), >= 0; read only when
+                            beam_mask is given */
+  uint8_t* beam_mask;    /* NULL, or a device [nbeam][ncell] output: the per-beam mask of
+                            the eigenvector stage (Sec. 3.3 last paragraph) on this call's
+                            mask and v1, exactly as rfi_eigvec_flag; then v1 must be given */
 } rfi_process_params;
 
 size_t rfi_process_workspace_size(int32_t nbeam, int32_t nchan,

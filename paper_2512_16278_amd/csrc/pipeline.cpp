@@ -207,6 +207,10 @@ rfi_status rfi_process_block(const rfi_block* blk, const rfi_process_params* p,
   if ((st = rfi::resolve_process(blk->nbeam, blk->nchan, p, &pl, who)) != RFI_OK) return st;
   if (pl.nsub == 0) return RFI_OK;   // nothing to do; outputs may be empty (NULL)
   if (!stat || !status || !mask) return fail(RFI_E_INVALID, "%s: NULL output", who);
+  if (p->beam_mask && !v1)
+    return fail(RFI_E_INVALID, "%s: the per-beam mask needs the v1 output", who);
+  if (p->beam_mask && !(p->kappa_v >= 0.0))
+    return fail(RFI_E_INVALID, "%s: kappa_v must be >= 0", who);
   if (!workspace) return fail(RFI_E_INVALID, "%s: workspace is NULL", who);
   if ((uintptr_t)workspace % 256 != 0)
     return fail(RFI_E_INVALID, "%s: workspace not 256-byte aligned", who);
@@ -225,7 +229,11 @@ rfi_status rfi_process_block(const rfi_block* blk, const rfi_process_params* p,
   const rfi::ClipJob cj = rfi::make_clip_job(pl.nsub, pl.nchan, stat, status, protect_chan,
                                              pl.kappa, pl.max_iter, state, mask, out, workspace);
   e = rfi::launch_clip(cj, s);
-  return rfi::check_hip(e, "rfi_process_block: clip launch");
+  if (e != hipSuccess) return rfi::check_hip(e, "rfi_process_block: clip launch");
+  if (p->beam_mask)
+    e = rfi::launch_eigvec_flag(blk->nbeam, pl.nsub, pl.nchan, v1, mask, status, protect_chan,
+                                p->kappa_v, p->beam_mask, nullptr, nullptr, s);
+  return rfi::check_hip(e, "rfi_process_block: per-beam stage launch");
 }
 
 }  // extern "C"

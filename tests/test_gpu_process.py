@@ -140,6 +140,51 @@ def test_process_block_stream_state(dev):
     assert np.array_equal(sa.cpu().numpy(), sb.cpu().numpy())
 
 
+def test_process_block_beam_mask(dev):
+    """The per-beam stage inside the whole-block call (Sec. 3.3 last
+    paragraph): bit-equal to rfi_eigvec_flag on the call's own v1 and mask,
+    and against the oracle's stage on the same cells (identical except where
+    |v1_b| lies within FP32 resolution of the beam's threshold). Both
+    precisions, a 36-beam block on the tridiagonal solver, and the error when
+    v1 is not requested."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    from oracle import eigvec
+    for nb, nc, L, nsub, prec in ((19, 96, 512, 6, 32), (19, 64, 256, 4, 64), (36, 40, 300, 3, 32)):
+        x = _data(nb, nc, nsub * L, seed=nb + nc)
+        buf = upload(x, dev)
+        blk = rfi.make_block(buf, nc)
+        ncell = nsub * nc
+        bm = torch.full((nb, ncell), 7, dtype=torch.uint8, device=dev)
+        p = rfi.process_params(L, nsub, eig_precision=prec, kappa_v=1.0, beam_mask=bm)
+        ws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, p), dtype=torch.uint8, device=dev)
+        stat, status, _, v1 = eig_buffers(nb, ncell, dev)
+        mask = torch.empty(ncell, dtype=torch.uint8, device=dev)
+        say("process_block beam mask", nb, nc, L, nsub, prec)
+        rfi.rfi_process_block(blk, p, stat, status, mask, ws, v1=v1)
+        bm2 = torch.full((nb, ncell), 9, dtype=torch.uint8, device=dev)
+        rfi.rfi_eigvec_flag(nb, nsub, nc, v1, mask, status, bm2, kappa_v=1.0)
+        torch.cuda.synchronize()
+        g = bm.cpu().numpy()
+        assert set(np.unique(g)) <= {0, 1}
+        assert np.array_equal(g, bm2.cpu().numpy())
+        cr, res, bo = pipeline.block(x, L, nsub, kappa_v=1.0)
+        assert np.array_equal(mask.cpu().numpy().astype(bool), res.mask.ravel())
+        diff = g.astype(bool) != bo.reshape(nb, -1)
+        if diff.any():
+            ok = ~cr.degenerate.ravel()
+            _, mu, sd = eigvec.eigvec_mask(cr.v1.reshape(-1, nb), res.mask.ravel(), ok, 1.0)
+            a = np.abs(cr.v1.reshape(-1, nb)).T
+            assert (np.abs(a - (mu + sd)[:, None])[diff] < 1e-5).all()
+        assert g[:, ~res.mask.ravel()].sum() == 0          # only masked cells carry beam flags
+    p = rfi.process_params(L, nsub, beam_mask=bm)
+    with pytest.raises(rfi.RfiError):
+        rfi.rfi_process_block(blk, p, stat, status, mask, ws)            # no v1 output
+    p = rfi.process_params(L, nsub, kappa_v=-1.0, beam_mask=bm)
+    with pytest.raises(rfi.RfiError):
+        rfi.rfi_process_block(blk, p, stat, status, mask, ws, v1=v1)
+
+
 def test_process_block_empty_and_errors(dev):
     import torch
     from paper_2512_16278_amd import rfi
