@@ -10,7 +10,14 @@
 // blocks of different streams run concurrently. Blocks of one stream are
 // chained by a per-stream event, because each reads and writes that stream's
 // device state: the pooled clip state and fit history, and the carry of the
-// partial sub-interval. Completion is observed by polling per-block events.
+// partial sub-interval. Completion is event-driven: behind each block's work
+// the slot's stream runs a host function that rings the scheduler's doorbell
+// (a flag under a mutex that no thread holds across a HIP call, so the HIP
+// runtime's callback thread never waits on a thread that waits on HIP).
+// Result buffers come from a session pool of power-of-two size classes and go
+// back to it on release. A block whose launches fail part-way keeps its slot
+// until what was enqueued has run, and fails its stream: later blocks of that
+// stream are refused (its carry and clip state are no longer defined).
 //
 // Per block (all on the slot's stream, after the stream's previous block):
 //   1. if the stream carries c samples of a sub-interval, the first L - c
@@ -55,6 +62,7 @@ struct StreamCtx {
   int64_t carry_samples = 0;         // samples in the carry after the last admitted block
   hipEvent_t last = nullptr;         // completion of the stream's last admitted block
   bool has_last = false;
+  bool failed = false;               // a block's launches failed part-way: state undefined
   int queued = 0, inflight = 0;
   bool tuned = false;                // te holds the session's tune entry for nbeam
   rfi_tune_entry te{};
@@ -80,24 +88,33 @@ struct Request {
   int nsub = 0, carried = 0;
   int64_t carry_after = 0;
   int64_t charge_run = 0, charge_res = 0;
-  void* res = nullptr;               // stat | cell status | mask, one allocation
+  void* res = nullptr;               // stat | cell status | mask, one pooled buffer
+  size_t res_cls = 0;                // its pool size class
   double* stat = nullptr;
   uint8_t* cstat = nullptr;
   uint8_t* mask = nullptr;
   rfi_flag_stats flag{};
   double t_submit = 0, t_admit = 0, t_done = 0;
   int slot = -1;
-  hipEvent_t done = nullptr;
+  rfi_status pending = RFI_OK;       // failure to report once the enqueued work has run
 };
 
 struct Slot {
   hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;         // recorded behind the running block's work
+  bool poll = false;                 // no host function behind it: query the event
   PipeEvents ev;
   void* ws = nullptr;
   size_t ws_size = 0;
   rfi_flag_stats* dstats = nullptr;  // device
   rfi_flag_stats* hstats = nullptr;  // pinned host
   Request* req = nullptr;
+};
+
+// Argument of the host function behind a block's work (one per slot).
+struct SlotBell {
+  rfi_session* s;
+  int slot;
 };
 
 // The device stays current for the calling thread only inside the guard.
@@ -122,8 +139,17 @@ struct rfi_session {
   bool has_tune = false;  // session copy of the caller's tune table
   rfi_tune_table tune{};
   std::mutex mu;
-  std::condition_variable cv_work;   // new work / stop, for the scheduler
   std::condition_variable cv_done;   // a block finished, for waiters
+  // doorbell of the scheduler: new work, a freed budget, stop, or a slot's
+  // host function. db_mu is never held across a HIP call.
+  std::mutex db_mu;
+  std::condition_variable db_cv;
+  bool db_rung = false;
+  std::vector<unsigned char> db_slot;   // per slot: its host function has run
+  std::vector<rfi::SlotBell> bells;     // host-function arguments, one per slot
+  // result buffers by power-of-two size class, and the bytes they hold idle
+  std::map<size_t, std::vector<void*>> pool;
+  int64_t pool_idle = 0;
   std::thread sched;
   bool stop = false;
   std::deque<rfi::Request*> queue;
@@ -142,9 +168,49 @@ struct rfi_session {
   }
   void scheduler();
   bool admit(rfi::Request* r);        // false: does not fit now
-  rfi_status enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& st);
+  rfi_status enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& st, bool* launched);
   void finish(rfi::Slot& sl, bool ok);
+  void ring(int slot = -1) {
+    {
+      std::lock_guard<std::mutex> g(db_mu);
+      db_rung = true;
+      if (slot >= 0) db_slot[slot] = 1;
+    }
+    db_cv.notify_one();
+  }
+  hipError_t res_get(size_t n, hipStream_t s, void** p, size_t* cls);
+  void res_put(void* p, size_t cls);
 };
+
+// Host function behind a block's work on its slot's stream.
+static void slot_bell(void* arg) {
+  const rfi::SlotBell* b = (const rfi::SlotBell*)arg;
+  b->s->ring(b->slot);
+}
+
+hipError_t rfi_session::res_get(size_t n, hipStream_t s, void** p, size_t* cls) {
+  size_t c = (size_t)1 << 16;
+  while (c < n) c <<= 1;
+  *cls = c;
+  auto it = pool.find(c);
+  if (it != pool.end() && !it->second.empty()) {
+    *p = it->second.back();
+    it->second.pop_back();
+    pool_idle -= (int64_t)c;
+    return hipSuccess;
+  }
+  return hipMallocAsync(p, c, s);
+}
+
+void rfi_session::res_put(void* p, size_t cls) {
+  // keep at most a quarter of the budget idle in the pool
+  if (pool_idle + (int64_t)cls > budget / 4) {
+    (void)hipFreeAsync(p, free_stream);
+    return;
+  }
+  pool[cls].push_back(p);
+  pool_idle += (int64_t)cls;
+}
 
 namespace rfi {
 namespace {
@@ -211,9 +277,12 @@ int64_t input_bytes(const rfi_block& blk) {
 
 using rfi::fail;
 
-rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& st) {
+// On failure, *launched tells whether work of this block was already enqueued.
+rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& st,
+                                bool* launched) {
   using namespace rfi;
   hipError_t e;
+  *launched = false;
   BlockPlan b;
   rfi_status rs = plan_block(st, r->blk.nsamp, &b, "rfi_submit");
   if (rs != RFI_OK) return rs;
@@ -236,12 +305,16 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
     sl.ws_size = b.ws;
   }
   if (b.res) {
-    if ((e = hipMallocAsync(&r->res, b.res, s)) != hipSuccess) return dev(e, "rfi_submit: results");
+    if ((e = res_get(b.res, s, &r->res, &r->res_cls)) != hipSuccess)
+      return dev(e, "rfi_submit: results");
     const size_t ncell = (size_t)b.nsub * F;
     r->stat = (double*)r->res;
     r->cstat = (uint8_t*)r->res + up(ncell * 8);
     r->mask = r->cstat + up(ncell);
   }
+  // from here on a failure leaves work of this block enqueued behind it (the
+  // stream-order wait and the allocations above change no state)
+  *launched = true;
   // 1. complete (or extend) the carried sub-interval
   if (b.carry_add > 0) {
     e = launch_ccm_mfma(bp, n, F, stride, 0, (int)b.carry_add, 1, st.carry_sx(), st.carry_sxy(),
@@ -279,9 +352,6 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
                             s)) != hipSuccess)
       return dev(e, "rfi_submit: clip summary");
   }
-  if ((e = hipEventCreateWithFlags(&r->done, hipEventDisableTiming)) != hipSuccess)
-    return dev(e, "rfi_submit: event");
-  if ((e = hipEventRecord(r->done, s)) != hipSuccess) return dev(e, "rfi_submit: event");
   if ((e = hipEventRecord(st.last, s)) != hipSuccess) return dev(e, "rfi_submit: event");
   st.has_last = true;
   r->nsub = b.nsub;
@@ -295,8 +365,8 @@ bool rfi_session::admit(rfi::Request* r) {
   using namespace rfi;
   StreamCtx& st = *streams.at(r->stream_id);
   BlockPlan b;
-  if (plan_block(st, r->blk.nsamp, &b, "rfi_submit") != RFI_OK) {
-    r->status = RFI_E_INVALID;
+  if (st.failed || plan_block(st, r->blk.nsamp, &b, "rfi_submit") != RFI_OK) {
+    r->status = st.failed ? RFI_E_DEVICE : RFI_E_INVALID;
     r->st = RState::Done;
     r->t_admit = r->t_done = now_us();
     st.queued--;
@@ -313,13 +383,13 @@ bool rfi_session::admit(rfi::Request* r) {
   Slot& sl = slots[si];
   r->t_admit = now_us();
   st.queued--;
-  const rfi_status rs = enqueue(r, sl, st);
+  bool launched = false;
+  const rfi_status rs = enqueue(r, sl, st, &launched);
   r->charge_run = run;
   r->charge_res = res;
   charged += run + res;
-  if (rs != RFI_OK) {
-    // nothing more of this block is queued; the work already enqueued runs out
-    // before the slot is reused (the slot's stream is in order)
+  if (rs != RFI_OK && !launched) {
+    // nothing of this block reached the device
     r->status = rs;
     r->st = RState::Done;
     r->t_done = now_us();
@@ -327,6 +397,21 @@ bool rfi_session::admit(rfi::Request* r) {
     r->charge_run = 0;
     cv_done.notify_all();
     return true;
+  }
+  if (rs != RFI_OK) {
+    // part of the block is enqueued: it keeps the slot (and its buffers stay
+    // alive) until that work has run, and the stream's carry and clip state
+    // are no longer defined
+    r->pending = rs;
+    st.failed = true;
+  }
+  // completion: the slot's event, and a host function that rings the doorbell
+  sl.poll = false;
+  if (hipEventRecord(sl.done, sl.s) != hipSuccess) {
+    (void)hipStreamSynchronize(sl.s);   // cannot track it: wait here (error path)
+    sl.poll = true;
+  } else if (hipLaunchHostFunc(sl.s, slot_bell, &bells[si]) != hipSuccess) {
+    sl.poll = true;                      // fall back to querying the event
   }
   r->st = RState::Running;
   r->slot = si;
@@ -340,10 +425,12 @@ void rfi_session::finish(rfi::Slot& sl, bool ok) {
   using namespace rfi;
   Request* r = sl.req;
   StreamCtx& st = *streams.at(r->stream_id);
-  if (ok) {
-    if (r->nsub > 0) r->flag = *sl.hstats;
-  } else {
+  if (!ok) {
     r->status = RFI_E_DEVICE;
+  } else if (r->pending != RFI_OK) {
+    r->status = r->pending;
+  } else if (r->nsub > 0) {
+    r->flag = *sl.hstats;
   }
   r->st = RState::Done;
   r->t_done = now_us();
@@ -359,14 +446,24 @@ void rfi_session::finish(rfi::Slot& sl, bool ok) {
 void rfi_session::scheduler() {
   using namespace rfi;
   (void)hipSetDevice(device);
-  std::unique_lock<std::mutex> lk(mu);
+  std::vector<unsigned char> rung(slots.size(), 0);
   for (;;) {
-    // completions
-    for (Slot& sl : slots) {
-      if (!sl.req) continue;
-      const hipError_t q = hipEventQuery(sl.req->done);
+    bool any_poll = false;
+    {
+      std::lock_guard<std::mutex> g(db_mu);
+      db_rung = false;
+      rung.swap(db_slot);
+      std::fill(db_slot.begin(), db_slot.end(), 0);
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    // completions: slots whose host function has run, and slots without one
+    for (int i = 0; i < (int)slots.size(); ++i) {
+      Slot& sl = slots[i];
+      if (!sl.req || !(rung[i] || sl.poll)) continue;
+      const hipError_t q = hipEventQuery(sl.done);
       if (q == hipSuccess) finish(sl, true);
       else if (q != hipErrorNotReady) finish(sl, false);
+      else if (rung[i]) sl.poll = true;    // rung before the event reads done: query again
     }
     // admissions: submission order; a stream's later block waits behind its
     // earlier queued one, other streams may pass
@@ -385,10 +482,13 @@ void rfi_session::scheduler() {
       }
     }
     if (stop && queue.empty() && running == 0) break;
-    if (running > 0)
-      cv_work.wait_for(lk, std::chrono::microseconds(20));
+    for (const Slot& sl : slots) any_poll |= sl.req && sl.poll;
+    lk.unlock();
+    std::unique_lock<std::mutex> dl(db_mu);
+    if (any_poll)
+      db_cv.wait_for(dl, std::chrono::microseconds(200), [&] { return db_rung; });
     else
-      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+      db_cv.wait(dl, [&] { return db_rung; });
   }
 }
 
@@ -425,8 +525,12 @@ rfi_status rfi_session_create(const rfi_session_config* cfg, rfi_session** out) 
   s->t0 = rfi::Clock::now();
   rfi::DeviceGuard g(s->device);
   s->slots.resize(s->max_slots);
+  s->db_slot.assign(s->max_slots, 0);
+  s->bells.resize(s->max_slots);
+  for (int i = 0; i < s->max_slots; ++i) s->bells[i] = rfi::SlotBell{s.get(), i};
   for (rfi::Slot& sl : s->slots) {
     if ((e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
         (e = sl.ev.init()) != hipSuccess ||
         (e = hipMalloc((void**)&sl.dstats, sizeof(rfi_flag_stats))) != hipSuccess ||
         (e = hipHostMalloc((void**)&sl.hstats, sizeof(rfi_flag_stats), 0)) != hipSuccess) {
@@ -456,14 +560,14 @@ void rfi_session_destroy(rfi_session* s) {
     s->queue.clear();
     s->stop = true;
   }
-  s->cv_work.notify_all();
+  s->ring();
   if (s->sched.joinable()) s->sched.join();
   rfi::DeviceGuard g(s->device);
   (void)hipDeviceSynchronize();
-  for (auto& kv : s->reqs) {
+  for (auto& kv : s->reqs)
     if (kv.second->res) (void)hipFree(kv.second->res);
-    if (kv.second->done) (void)hipEventDestroy(kv.second->done);
-  }
+  for (auto& kv : s->pool)
+    for (void* p : kv.second) (void)hipFree(p);
   for (auto& kv : s->streams) {
     rfi::StreamCtx& st = *kv.second;
     if (st.protect) (void)hipFree(st.protect);
@@ -472,6 +576,7 @@ void rfi_session_destroy(rfi_session* s) {
     if (st.last) (void)hipEventDestroy(st.last);
   }
   for (rfi::Slot& sl : s->slots) {
+    if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.ws) (void)hipFree(sl.ws);
     if (sl.dstats) (void)hipFree(sl.dstats);
     if (sl.hstats) (void)hipHostFree(sl.hstats);
@@ -570,7 +675,7 @@ rfi_status rfi_submit(rfi_session* s, int32_t stream_id, const rfi_block* blk, u
   s->queue.push_back(r.get());
   s->reqs[r->ticket] = std::move(r);
   lk.unlock();
-  s->cv_work.notify_one();
+  s->ring();
   return RFI_OK;
 }
 
@@ -665,18 +770,18 @@ rfi_status rfi_result_copy(rfi_session* s, uint64_t ticket, double* stat, uint8_
 rfi_status rfi_result_release(rfi_session* s, uint64_t ticket) {
   rfi::clear_error();
   if (!s) return fail(RFI_E_INVALID, "rfi_result_release: NULL session");
-  std::lock_guard<std::mutex> lk(s->mu);
+  std::unique_lock<std::mutex> lk(s->mu);
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return fail(RFI_E_INVALID, "rfi_result_release: unknown ticket");
   rfi::Request* r = it->second.get();
   if (r->st != rfi::RState::Done)
     return fail(RFI_E_NOT_READY, "rfi_result_release: ticket still queued or running");
   rfi::DeviceGuard g(s->device);
-  if (r->res) (void)hipFreeAsync(r->res, s->free_stream);
-  if (r->done) (void)hipEventDestroy(r->done);
+  if (r->res) s->res_put(r->res, r->res_cls);
   s->charged -= r->charge_res;
   s->reqs.erase(it);
-  s->cv_work.notify_one();   // budget freed
+  lk.unlock();
+  s->ring();   // budget freed
   return RFI_OK;
 }
 
