@@ -211,6 +211,78 @@ def precision_split(dev, spec, data, blk, nsub, ev_time):
     return out
 
 
+def widened_rows(dev, spec, data, blk, nsub, sx, sxy, cnt, stat, status, mask, ev_time, peak):
+    """The calls beyond the three-step path, on the same FAST-shaped block,
+    each timed with HIP events on the launch stream (median of 3 after one
+    warm-up): the per-beam eigenvector stage, the clip scopes (moment and
+    histogram fits), the ArPLS bandpass and the non-centred statistic, and the
+    whole 10 s block as one long sub-interval. Bytes are the algorithmic ones
+    each call must move (inputs read once, outputs written once)."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    nb, nc, L = spec.nbeam, spec.nchan, spec.L
+    ncell = nsub * nc
+    out = {}
+
+    def rec(name, ms, nbytes, note):
+        out[name] = {"ms": round(ms, 4), "bytes": int(nbytes),
+                     "gbs": round(nbytes / (ms / 1e3) / 1e9, 1),
+                     "hbm_frac": round(nbytes / (ms / 1e3) / 1e9 / peak, 4), "note": note}
+
+    # per-beam stage on the block's v1 and mask
+    v1 = torch.empty((nb, ncell), dtype=torch.float32, device=dev)
+    rfi.rfi_eig_batched(nb, nsub, nc, sx, sxy, cnt, stat, status, v1=v1)
+    rfi.rfi_flag(nsub, nc, stat, status, mask)
+    bm = torch.empty((nb, ncell), dtype=torch.uint8, device=dev)
+    vws = torch.empty(rfi.rfi_eigvec_workspace_size(nb, nsub, nc), dtype=torch.uint8, device=dev)
+    ms = ev_time(lambda: rfi.rfi_eigvec_flag(nb, nsub, nc, v1, mask, status, bm, kappa_v=1.0,
+                                             workspace=vws))
+    rec("eigvec_stage", ms, nb * ncell * 4 + 2 * ncell + nb * ncell,
+        "rfi_eigvec_flag: |v1| fit per beam, beam mask")
+    del v1, bm
+    # clip scopes
+    ws = rfi.flag_workspace(nsub, nc, dev)
+    m2 = torch.empty_like(mask)
+    for fitname, fit in (("moments", rfi.RFI_FIT_MOMENTS), ("histogram", rfi.RFI_FIT_HISTOGRAM)):
+        ms = ev_time(lambda: rfi.rfi_flag_scoped(nsub, nc, stat, status, m2, scopes=7, fit=fit,
+                                                 workspace=ws))
+        rec(f"scopes_{fitname}", ms, ncell * (8 + 1 + 1),
+            f"rfi_flag_scoped: global + per channel + per sub-interval, {fitname} fit")
+    del ws, m2
+    # ArPLS bandpass from the channel sums, then the non-centred statistic
+    z = torch.empty((nb, ncell), dtype=torch.float64, device=dev)
+    bws = torch.empty(rfi.rfi_bandpass_workspace_size(nb, nc, nsub), dtype=torch.uint8,
+                      device=dev)
+    passes = torch.empty((nsub, nb), dtype=torch.int32, device=dev)
+    ms = ev_time(lambda: rfi.rfi_bandpass_arpls(nb, nsub, nc, sx, cnt, z, workspace=bws,
+                                                passes=passes), reps=1)
+    pm = passes.float().mean().item()
+    rec("arpls", ms, nb * ncell * (4 + 8),
+        f"rfi_bandpass_arpls: {nb * nsub} systems of {nc} channels, mean {pm:.1f} passes")
+    del bws
+    st2 = torch.empty_like(stat)
+    ss2 = torch.empty_like(status)
+    npair = nb * (nb + 1) // 2
+    ms = ev_time(lambda: rfi.rfi_eig_noncentred(nb, nsub, nc, sx, sxy, cnt, z, st2, ss2))
+    rec("noncentred_stat", ms, (nb + npair) * ncell * 4 + nb * ncell * 8 + ncell * 9,
+        "rfi_eig_noncentred: FP64 tridiagonal solver on the raw-moment matrix")
+    del z, st2, ss2
+    # the whole block as one sub-interval of 10 s (Table 1's longest)
+    Ll = spec.nsamp
+    p = rfi.process_params(Ll, 1)
+    pws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, p), dtype=torch.uint8, device=dev)
+    sl = torch.empty(nc, dtype=torch.float64, device=dev)
+    ssl = torch.empty(nc, dtype=torch.uint8, device=dev)
+    msl = torch.empty(nc, dtype=torch.uint8, device=dev)
+    ms = ev_time(lambda: rfi.rfi_process_block(blk, p, sl, ssl, msl, pws))
+    rec("long_subint", ms, nb * nc * Ll,
+        f"rfi_process_block with L = {Ll} (one 10 s sub-interval, {nc} cells): int32 time "
+        f"chunks widened to int64, FP64 tridiagonal solver")
+    del pws
+    torch.cuda.empty_cache()
+    return out
+
+
 def batch_bench(dev, nblocks=24, seed=11):
     """Uneven blocks (beam counts 7/19/36/72, channels 1024/4096/8192, L
     512/1024/4096, 0.1-2 s each) through (a) one rfi_process_block per
@@ -416,6 +488,9 @@ def main():
                     help="arrival rates (blocks/s) of the serving run; empty = skip it")
     ap.add_argument("--serve-blocks", type=int, default=40, help="blocks per serving rate")
     ap.add_argument("--no-precision-split", action="store_true")
+    ap.add_argument("--no-widened", action="store_true",
+                    help="skip the timings of the per-beam stage, scopes, bandpass and long "
+                         "sub-interval calls")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving loop and print its JSON")
@@ -629,6 +704,12 @@ def main():
             ts.append(a.elapsed_time(b))
         return float(np.median(ts[1:]))
 
+    widened = None
+    if not args.no_widened:
+        widened = widened_rows(dev, spec, data, blk, nsub, sx, sxy, cnt, stat, status, mask,
+                               ev_time, HBM_PEAK_GBS)
+        log(f"widened rows: {widened}")
+
     psplit = None
     if not args.no_precision_split:
         del sx, sxy
@@ -683,6 +764,7 @@ def main():
         "frac_of_measured_read": round(value / read_gbs, 4),
         "flagged_cells": int(flags["nflag"]), "clip_iterations": int(flags["iterations"]),
         "roofline": roof,
+        "widened": widened,
         "precision_split": psplit,
         "batch": batch,
         "serving": serving,

@@ -331,12 +331,17 @@ rfi_status rfi_clip_fit(int32_t n, const int64_t* N, const uint64_t* Q1, const u
  * for each beam b, mu_b and sigma_b (population) of |v1_b| over eligible
  * unmasked cells; beam_mask[b][cell] = mask[cell] && |v1_b| > mu_b +
  * kappa_v sigma_b. Eligibility as in rfi_flag. beam_mu / beam_sigma
- * (nullable, [nbeam] FP64) receive the fits. */
+ * (nullable, [nbeam] FP64) receive the fits (FP64 sums of |v1_b| and
+ * |v1_b|^2 over the cells, sigma^2 = (sum x^2 - mu sum x) / n; NaN with no
+ * cell). workspace: rfi_eigvec_workspace_size bytes of device memory,
+ * 8-byte aligned, owned by the caller, one call at a time (at most 485 KB).
+ * Errors: RFI_E_INVALID for bad sizes, NULL pointers, kappa_v < 0. */
+size_t rfi_eigvec_workspace_size(int32_t nbeam, int32_t nsub, int32_t nchan);
 rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const float* v1,
                            const uint8_t* mask, const uint8_t* status,
                            const uint8_t* protect_chan, double kappa_v,
                            uint8_t* beam_mask, double* beam_mu, double* beam_sigma,
-                           rfi_stream_t stream);
+                           void* workspace, rfi_stream_t stream);
 
 /* The whole per-block path in one call: the sums of Eq. 1, the eigen stage
  * of Eq. 2 and the statistic (as rfi_eig_batched, FP32 Jacobi unless
@@ -547,6 +552,11 @@ typedef struct {
   int32_t max_iter;      /* clip fits, 0 = 50 */
   double kappa;          /* clip multiple (Sec. 4.5), >= 0 */
   const uint8_t* protect_chan; /* HOST [nchan] (1 = preserved channel) or NULL; copied */
+  int32_t beam_stage;    /* 1: every block also yields v1 and the per-beam mask of the
+                            eigenvector stage (Sec. 3.3 last paragraph; as rfi_eigvec_flag
+                            on the block's mask); 0: not */
+  int32_t pad;
+  double kappa_v;        /* per-beam multiple (Sec. 4.5), >= 0, read when beam_stage = 1 */
 } rfi_stream_config;
 
 typedef struct {
@@ -561,6 +571,9 @@ typedef struct {
   const uint8_t* mask;   /* DEVICE [nsub * nchan] 1 = masked */
   rfi_flag_stats flag;   /* host copy of the block's clip summary */
   double t_submit_us, t_admit_us, t_done_us; /* host clock, microseconds since session start */
+  const float* v1;       /* DEVICE [nbeam][nsub * nchan] dominant eigenvectors, or NULL
+                            (stream without beam_stage) */
+  const uint8_t* beam_mask; /* DEVICE [nbeam][nsub * nchan] per-beam mask, or NULL */
 } rfi_result;
 
 rfi_status rfi_session_create(const rfi_session_config* cfg /* host, nullable */,
@@ -590,6 +603,11 @@ rfi_status rfi_cancel(rfi_session* s, uint64_t ticket);
  * elements (each pointer nullable). Synchronous. */
 rfi_status rfi_result_copy(rfi_session* s, uint64_t ticket, double* stat, uint8_t* cell_status,
                            uint8_t* mask);
+/* Copy a done ticket's v1 and per-beam mask ([nbeam][nsub * nchan] each,
+ * HOST, nullable) of a stream opened with beam_stage = 1. Synchronous.
+ * RFI_E_INVALID for a stream without the stage. */
+rfi_status rfi_result_copy_beams(rfi_session* s, uint64_t ticket, float* v1,
+                                 uint8_t* beam_mask);
 /* Free a done ticket's result buffers and budget. */
 rfi_status rfi_result_release(rfi_session* s, uint64_t ticket);
 /* Checkpoint / resume of a stream (clip state, fit history, partial

@@ -303,18 +303,29 @@ rfi_status rfi_clip_fit(int32_t n, const int64_t* N, const uint64_t* Q1, const u
                    "rfi_clip_fit launch");
 }
 
+size_t rfi_eigvec_workspace_size(int32_t nbeam, int32_t nsub, int32_t nchan) {
+  if (nbeam < 2 || nbeam > RFI_MAX_BEAMS || nsub < 0 || nchan < 1) return 0;
+  return rfi::eigvec_workspace_size(nbeam, (int64_t)nsub * nchan);
+}
+
 rfi_status rfi_eigvec_flag(int32_t nbeam, int32_t nsub, int32_t nchan, const float* v1,
                            const uint8_t* mask, const uint8_t* status,
                            const uint8_t* protect_chan, double kappa_v, uint8_t* beam_mask,
-                           double* beam_mu, double* beam_sigma, rfi_stream_t stream) {
+                           double* beam_mu, double* beam_sigma, void* workspace,
+                           rfi_stream_t stream) {
   rfi::clear_error();
   if (nbeam < 2 || nbeam > RFI_MAX_BEAMS || nsub < 0 || nchan < 1)
     return fail(RFI_E_INVALID, "rfi_eigvec_flag: bad sizes");
+  if ((int64_t)nsub * nchan > (int64_t)1 << 30)
+    return fail(RFI_E_INVALID, "rfi_eigvec_flag: nsub * nchan exceeds 2^30 cells");
   if (!v1 || !mask || !status || !beam_mask)
     return fail(RFI_E_INVALID, "rfi_eigvec_flag: NULL input or output");
+  if (!workspace) return fail(RFI_E_INVALID, "rfi_eigvec_flag: workspace is NULL");
+  if ((uintptr_t)workspace % 8 != 0)
+    return fail(RFI_E_INVALID, "rfi_eigvec_flag: workspace not 8-byte aligned");
   if (!(kappa_v >= 0.0)) return fail(RFI_E_INVALID, "rfi_eigvec_flag: kappa_v must be >= 0");
   return check_hip(rfi::launch_eigvec_flag(nbeam, nsub, nchan, v1, mask, status, protect_chan,
-                                           kappa_v, beam_mask, beam_mu, beam_sigma,
+                                           kappa_v, beam_mask, beam_mu, beam_sigma, workspace,
                                            (hipStream_t)stream),
                    "rfi_eigvec_flag launch");
 }

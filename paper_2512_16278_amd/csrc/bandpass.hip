@@ -12,9 +12,11 @@
 // One thread per (beam, sub-interval) system: the solve is a sequential
 // recurrence along the channels (banded Cholesky of the pentadiagonal
 // matrix, then the two triangular sweeps), so the parallelism is across
-// systems; the per-system vectors live in a workspace laid out
+// systems. The per-system vectors live in a workspace laid out
 // [channel][system], so that neighbouring threads touch neighbouring words
-// at every step.
+// at every step; the spectrum y is staged there once per call. Every sweep
+// walks the channels in blocks of kBlk: the loads of a block are issued
+// together before its steps run, so a step never waits on memory alone.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -24,6 +26,8 @@ namespace rfi {
 namespace {
 
 constexpr int kBpThreads = 64;
+constexpr int kBlk = 16;
+constexpr int kVecs = 7;          // w, 1/R_jj, R_{j,j+1}, R_{j,j+2}, u, z, y
 
 struct BpArgs {
   int nbeam, nsub, nchan, itermax;
@@ -32,7 +36,7 @@ struct BpArgs {
   const int32_t* count;   // [nsub]
   double* z;              // out [nbeam][ncell]
   int32_t* passes;        // out [nsub][nbeam] or NULL
-  double* ws;             // 6 vectors of nchan * nsys doubles
+  double* ws;             // kVecs vectors of nchan * nsys doubles
 };
 
 // (D^T D) entries of row i: diagonal, first and second super-diagonal (D has
@@ -61,80 +65,165 @@ __global__ __launch_bounds__(kBpThreads) void arpls_kernel(BpArgs a) {
   const int32_t* sx = a.sum_x + (int64_t)b * ncell + (int64_t)k * F;
   double* zo = a.z + (int64_t)b * ncell + (int64_t)k * F;
   // workspace vectors, element j of this system at [j * nsys + sys]
+  const size_t vs = (size_t)F * nsys;
   double* w = a.ws;
-  double* r0 = w + (size_t)F * nsys;
-  double* r1 = r0 + (size_t)F * nsys;
-  double* r2 = r1 + (size_t)F * nsys;
-  double* u = r2 + (size_t)F * nsys;
-  double* z = u + (size_t)F * nsys;
+  double* r0 = w + vs;            // 1 / R_jj
+  double* r1 = r0 + vs;
+  double* r2 = r1 + vs;
+  double* u = r2 + vs;
+  double* z = u + vs;
+  double* y = z + vs;
   auto at = [&](double* v, int j) -> double& { return v[(size_t)j * nsys + sys]; };
-  auto yv = [&](int j) { return (double)sx[j] / L; };
   if (F < 3) {
-    for (int j = 0; j < F; ++j) zo[j] = yv(j);
+    for (int j = 0; j < F; ++j) zo[j] = (double)sx[j] / L;
     if (a.passes) a.passes[k * a.nbeam + b] = 0;
     return;
   }
-  for (int j = 0; j < F; ++j) at(w, j) = 1.0;
+  // stage the spectrum (channel means) and the first weights
+  for (int j0 = 0; j0 < F; j0 += kBlk) {
+    int32_t v[kBlk];
+#pragma unroll
+    for (int t = 0; t < kBlk; ++t) v[t] = sx[j0 + t < F ? j0 + t : F - 1];
+#pragma unroll
+    for (int t = 0; t < kBlk; ++t)
+      if (j0 + t < F) {
+        at(y, j0 + t) = (double)v[t] / L;
+        at(w, j0 + t) = 1.0;
+      }
+  }
   int passes = 0;
   for (int it = 0; it < a.itermax; ++it) {
     ++passes;
     // Cholesky A = R^T R of A = W + lam D^T D (R upper, bandwidth 2), then
-    // R^T u = W y and R z = u
-    for (int j = 0; j < F; ++j) {
-      double d0, d1, d2;
-      dtd_row(j, F, d0, d1, d2);
-      const double p1 = j >= 1 ? at(r1, j - 1) : 0.0;   // R_{j-1, j}
-      const double p2 = j >= 2 ? at(r2, j - 2) : 0.0;   // R_{j-2, j}
-      const double q1 = j >= 1 ? at(r2, j - 1) : 0.0;   // R_{j-1, j+1}
-      const double rjj = sqrt(at(w, j) + a.lam * d0 - p1 * p1 - p2 * p2);
-      at(r0, j) = rjj;
-      at(r1, j) = (a.lam * d1 - p1 * q1) / rjj;
-      at(r2, j) = a.lam * d2 / rjj;
-      const double u1 = j >= 1 ? at(u, j - 1) : 0.0;
-      const double u2 = j >= 2 ? at(u, j - 2) : 0.0;
-      at(u, j) = (at(w, j) * yv(j) - p1 * u1 - p2 * u2) / rjj;
+    // R^T u = W y and R z = u. The recurrences carry the previous two rows in
+    // registers (p1 = R_{j-1,j}, p2 = R_{j-2,j}, q1 = R_{j-1,j+1}, u1, u2);
+    // R and u go to the workspace for the backward sweep only.
+    double p1 = 0.0, p2 = 0.0, q1 = 0.0, u1 = 0.0, u2 = 0.0;
+    for (int j0 = 0; j0 < F; j0 += kBlk) {
+      double wb[kBlk], yb[kBlk];
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) {
+        const int j = j0 + t < F ? j0 + t : F - 1;
+        wb[t] = at(w, j);
+        yb[t] = at(y, j);
+      }
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) {
+        const int j = j0 + t;
+        if (j >= F) break;
+        double d0, d1, d2;
+        dtd_row(j, F, d0, d1, d2);
+        // one division per row: the row is scaled by 1 / R_jj
+        const double ir = 1.0 / sqrt(wb[t] + a.lam * d0 - p1 * p1 - p2 * p2);
+        const double r1j = (a.lam * d1 - p1 * q1) * ir;
+        const double r2j = a.lam * d2 * ir;
+        const double uj = (wb[t] * yb[t] - p1 * u1 - p2 * u2) * ir;
+        at(r0, j) = ir;
+        at(r1, j) = r1j;
+        at(r2, j) = r2j;
+        at(u, j) = uj;
+        p2 = q1;        // R_{j-1, j+1} is R_{(j+1)-2, j+1}
+        p1 = r1j;       // R_{j, j+1}
+        q1 = r2j;       // R_{j, j+2}
+        u2 = u1;
+        u1 = uj;
+      }
     }
-    for (int j = F - 1; j >= 0; --j) {
-      const double z1 = j + 1 < F ? at(z, j + 1) : 0.0;
-      const double z2 = j + 2 < F ? at(z, j + 2) : 0.0;
-      at(z, j) = (at(u, j) - at(r1, j) * z1 - at(r2, j) * z2) / at(r0, j);
+    double z1 = 0.0, z2 = 0.0;
+    for (int j1 = F - 1; j1 >= 0; j1 -= kBlk) {
+      double ub[kBlk], ab[kBlk], bb[kBlk], cb[kBlk];
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) {
+        const int j = j1 - t >= 0 ? j1 - t : 0;
+        ub[t] = at(u, j);
+        ab[t] = at(r1, j);
+        bb[t] = at(r2, j);
+        cb[t] = at(r0, j);
+      }
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) {
+        const int j = j1 - t;
+        if (j < 0) break;
+        const double zj = (ub[t] - ab[t] * z1 - bb[t] * z2) * cb[t];
+        at(z, j) = zj;
+        z2 = z1;
+        z1 = zj;
+      }
     }
     // negative residuals: mean and sample standard deviation
     double sn = 0.0;
     int nn = 0;
-    for (int j = 0; j < F; ++j) {
-      const double d = yv(j) - at(z, j);
-      if (d < 0.0) { sn += d; ++nn; }
+    for (int j0 = 0; j0 < F; j0 += kBlk) {
+      double d[kBlk];
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) {
+        const int j = j0 + t < F ? j0 + t : F - 1;
+        d[t] = at(y, j) - at(z, j);
+      }
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t)
+        if (j0 + t < F && d[t] < 0.0) { sn += d[t]; ++nn; }
     }
     if (nn < 2) break;
     const double m = sn / nn;
     double ss = 0.0;
-    for (int j = 0; j < F; ++j) {
-      const double d = yv(j) - at(z, j);
-      if (d < 0.0) ss += (d - m) * (d - m);
+    for (int j0 = 0; j0 < F; j0 += kBlk) {
+      double d[kBlk];
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) {
+        const int j = j0 + t < F ? j0 + t : F - 1;
+        d[t] = at(y, j) - at(z, j);
+      }
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t)
+        if (j0 + t < F && d[t] < 0.0) ss += (d[t] - m) * (d[t] - m);
     }
-    const double s = sqrt(ss / (nn - 1));
-    if (!(s > 0.0)) break;
+    const double sd = sqrt(ss / (nn - 1));
+    if (!(sd > 0.0)) break;
+    // new weights into u (free until the next pass), kept until the test
     double dw = 0.0, nw = 0.0;
-    for (int j = 0; j < F; ++j) {
-      const double d = yv(j) - at(z, j);
-      const double wt = 1.0 / (1.0 + exp(2.0 * (d - (2.0 * s - m)) / s));
-      const double wj = at(w, j);
-      dw += (wj - wt) * (wj - wt);
-      nw += wj * wj;
-      at(u, j) = wt;                               // new weights, kept until the test
+    for (int j0 = 0; j0 < F; j0 += kBlk) {
+      double d[kBlk], wo[kBlk];
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) {
+        const int j = j0 + t < F ? j0 + t : F - 1;
+        d[t] = at(y, j) - at(z, j);
+        wo[t] = at(w, j);
+      }
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) {
+        if (j0 + t >= F) break;
+        const double wt = 1.0 / (1.0 + exp(2.0 * (d[t] - (2.0 * sd - m)) / sd));
+        dw += (wo[t] - wt) * (wo[t] - wt);
+        nw += wo[t] * wo[t];
+        at(u, j0 + t) = wt;
+      }
     }
     if (sqrt(dw) / sqrt(nw) < a.ratio) break;
-    for (int j = 0; j < F; ++j) at(w, j) = at(u, j);
+    for (int j0 = 0; j0 < F; j0 += kBlk) {
+      double v[kBlk];
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t) v[t] = at(u, j0 + t < F ? j0 + t : F - 1);
+#pragma unroll
+      for (int t = 0; t < kBlk; ++t)
+        if (j0 + t < F) at(w, j0 + t) = v[t];
+    }
   }
-  for (int j = 0; j < F; ++j) zo[j] = at(z, j);
+  for (int j0 = 0; j0 < F; j0 += kBlk) {
+    double v[kBlk];
+#pragma unroll
+    for (int t = 0; t < kBlk; ++t) v[t] = at(z, j0 + t < F ? j0 + t : F - 1);
+#pragma unroll
+    for (int t = 0; t < kBlk; ++t)
+      if (j0 + t < F) zo[j0 + t] = v[t];
+  }
   if (a.passes) a.passes[k * a.nbeam + b] = passes;
 }
 
 }  // namespace
 
 size_t bandpass_workspace_size(int nbeam, int nchan, int nsub) {
-  return (size_t)6 * nchan * nbeam * nsub * sizeof(double);
+  return (size_t)kVecs * nchan * nbeam * nsub * sizeof(double);
 }
 
 hipError_t launch_arpls(int nbeam, int nsub, int nchan, const int32_t* sum_x,

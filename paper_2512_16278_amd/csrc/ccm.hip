@@ -138,7 +138,7 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
     BeamPtrs bp, int nbeam, int nchan, int64_t row_stride, int64_t t0, int L, int nsub,
     int nct, int32_t* __restrict__ sum_x, int32_t* __restrict__ sum_xy,
     int32_t* __restrict__ count, int accumulate, int G, int nh, int prio, int layout,
-    int64_t kstride, const CcmItem* __restrict__ items, int nitem) {
+    int64_t kstride, int ksplit, const CcmItem* __restrict__ items, int nitem) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   // the beam pointer table is the first kernel argument: index it in place
   const uint8_t* const* beam_tab = (const uint8_t* const*)__builtin_amdgcn_kernarg_segment_ptr();
@@ -168,9 +168,12 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
     w -= it.wg0;
     if (w >= nsub * nct) return;      // padding to a multiple of 8 workgroups
     kstride = 0;
+    ksplit = 1;
   }
-  // sub-interval k starts at t0 + k kstride (kstride = L: back to back; a
-  // longer stride sums one time chunk of each of several long sub-intervals)
+  // sub-interval k of the launch starts at t0 + (k / ksplit) kstride +
+  // (k mod ksplit) L: with ksplit = 1 and kstride = L they are back to back; a
+  // longer stride sums one time chunk of each of several long sub-intervals,
+  // and ksplit > 1 cuts each of those into ksplit consecutive chunks of L
   if (kstride == 0) kstride = L;
   // optional issue priority over waves of other kernels on the same SIMD
   if (prio) __builtin_amdgcn_s_setprio(2);
@@ -223,7 +226,8 @@ __global__ __launch_bounds__((MfmaCfg<NB, CW, CPW, IPW, NST>::NTHR), 1) void ccm
     const int c0 = (T % nct) * CW;
     uint8_t* buf = lds + slot * C::STAGE;
     const int rows = min(TC, L - chunk * TC);
-    const int64_t row = t0 + (int64_t)k * kstride + (int64_t)chunk * TC;
+    const int64_t row = t0 + (int64_t)(k / ksplit) * kstride + (int64_t)(k % ksplit) * L +
+                        (int64_t)chunk * TC;
 #pragma unroll
     for (int i = 0; i < IPW; ++i) {
       const int64_t col = c0 + src_col[i];
@@ -463,7 +467,7 @@ template <int NB, int CW, int CPW, int IPW, int NST>
 hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, int group_bytes, int layout,
-                           int64_t kstride, hipStream_t s) {
+                           int64_t kstride, int ksplit, hipStream_t s) {
   using C = MfmaCfg<NB, CW, CPW, IPW, NST>;
   if ((int64_t)nbeam * C::UPB > (int64_t)64 * IPW * C::NWAVE) return hipErrorInvalidValue;
   if (nbeam > C::MAXB) return hipErrorInvalidValue;
@@ -479,7 +483,7 @@ hipError_t launch_mfma_cfg(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
   const int prio = 0;   // raised issue priority of the streaming waves measured no gain
   hipLaunchKernelGGL(kern, dim3((unsigned)ntiles), dim3(C::NTHR), C::LDS, s, bp, nbeam, nchan,
                      row_stride, t0, L, nsub, nct, sum_x, sum_xy, count, accumulate, G, nh, prio,
-                     layout, kstride, (const CcmItem*)nullptr, 0);
+                     layout, kstride, ksplit, (const CcmItem*)nullptr, 0);
   return hipGetLastError();
 }
 
@@ -496,7 +500,7 @@ hipError_t launch_batch_cfg(const CcmItem* items, int nitem, int total_wg, int g
   memset(&none, 0, sizeof(none));
   hipLaunchKernelGGL(kern, dim3((unsigned)total_wg), dim3(C::NTHR), C::LDS, s, none, 0, 0,
                      (int64_t)0, (int64_t)0, 0, 0, 0, (int32_t*)nullptr, (int32_t*)nullptr,
-                     (int32_t*)nullptr, 0, G, 1, 0, 0, (int64_t)0, items, nitem);
+                     (int32_t*)nullptr, 0, G, 1, 0, 0, (int64_t)0, 1, items, nitem);
   return hipGetLastError();
 }
 
@@ -565,12 +569,13 @@ struct LaunchOne {
   int32_t *sum_x, *sum_xy, *count;
   int accumulate, group_bytes, layout;
   int64_t kstride;
+  int ksplit;
   hipStream_t s;
   template <int NB, int CW, int CPW, int IPW, int NST>
   hipError_t run() {
     return launch_mfma_cfg<NB, CW, CPW, IPW, NST>(bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x,
                                                   sum_xy, count, accumulate, group_bytes, layout,
-                                                  kstride, s);
+                                                  kstride, ksplit, s);
   }
 };
 
@@ -669,9 +674,9 @@ int ccm_tile_variants(int nbeam) {
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, int shared_cu, hipStream_t s,
-                           const CcmTune* t, int layout, int64_t kstride) {
+                           const CcmTune* t, int layout, int64_t kstride, int ksplit) {
   LaunchOne op{bp, nbeam, nchan, row_stride, t0, L, nsub, sum_x, sum_xy, count, accumulate,
-               t ? t->group_bytes : 0, layout, kstride, s};
+               t ? t->group_bytes : 0, layout, kstride, ksplit < 1 ? 1 : ksplit, s};
   return ccm_dispatch(nbeam, shared_cu, op, t);
 }
 

@@ -843,7 +843,9 @@ __global__ __launch_bounds__(kGridThreads) void clip_mask_kernel(ClipJob job0, c
 // weights c^2 (one thread, bins in index order, the operation order of the
 // definition, no fused multiply-add), falling back to the moments where the
 // parabola is undefined.
-constexpr int kSegThreads = 256;
+constexpr int kSegThreads = 256;      // channel and sub-interval segments
+constexpr int kSegThreadsAll = 1024;  // the whole block as one segment
+constexpr int kSegUnroll = 4;         // cells per thread whose loads are issued together
 constexpr int kBins = 64;
 
 struct SegArgs {
@@ -909,9 +911,9 @@ __device__ void hist_fit(const unsigned* cnt, int64_t N, double mu_m, double sg_
   sg = sg_z * sg_m;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kSegThreads) void segclip_kernel(SegArgs a) {
-  __shared__ Red3<kSegThreads> red;
+template <int MODE, int NT>
+__global__ __launch_bounds__(NT) void segclip_kernel(SegArgs a) {
+  __shared__ Red3<NT> red;
   __shared__ unsigned hcnt[kBins];
   __shared__ int64_t sT;
   __shared__ double sfit[3];
@@ -933,13 +935,21 @@ __global__ __launch_bounds__(kSegThreads) void segclip_kernel(SegArgs a) {
     __syncthreads();
     int64_t n = 0;
     u128 q1 = 0, q2 = 0;
-    for (int64_t i = threadIdx.x; i < m; i += kSegThreads) {
-      const CellLd x = load_cell(J, seg_cell<MODE>(a, i), ncell);
-      if (!elig(x)) continue;
-      const int64_t q = quant(x.s);
-      if (q <= T) acc(q, n, q1, q2);
+    for (int64_t i0 = threadIdx.x; i0 < m; i0 += (int64_t)NT * kSegUnroll) {
+      CellLd x[kSegUnroll];
+#pragma unroll
+      for (int u = 0; u < kSegUnroll; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        x[u] = load_cell(J, seg_cell<MODE>(a, i < m ? i : 0), ncell);
+      }
+#pragma unroll
+      for (int u = 0; u < kSegUnroll; ++u) {
+        if (i0 + (int64_t)u * NT >= m || !elig(x[u])) continue;
+        const int64_t q = quant(x[u].s);
+        if (q <= T) acc(q, n, q1, q2);
+      }
     }
-    block_sum3<kSegThreads>(n, q1, q2, red);
+    block_sum3<NT>(n, q1, q2, red);
     N = n; Q1 = q1; Q2 = q2;
     if (Nelig < 0) Nelig = N;
     if (it > 0 && N == prevN) break;
@@ -968,21 +978,29 @@ __global__ __launch_bounds__(kSegThreads) void segclip_kernel(SegArgs a) {
         fit_wave(N, Q1, Q2, a.kappa, m_, s_, t_);
         if (threadIdx.x == 0) { sfit[0] = m_; sfit[1] = s_; }
       }
-      for (int i = threadIdx.x; i < kBins; i += kSegThreads) hcnt[i] = 0;
+      for (int i = threadIdx.x; i < kBins; i += NT) hcnt[i] = 0;
       __syncthreads();
       const double mu_m = sfit[0], sg_m = sfit[1];
       {
 #pragma clang fp contract(off)
         const double lo = mu_m - 4.0 * sg_m;
         const double w = sg_m * 0.125;
-        for (int64_t i = threadIdx.x; i < m; i += kSegThreads) {
-          const CellLd x = load_cell(J, seg_cell<MODE>(a, i), ncell);
-          if (!elig(x)) continue;
-          const int64_t q = quant(x.s);
-          if (q > T) continue;
-          const double v = (double)q / TWO40;
-          const double f = floor((v - lo) / w);
-          if (f >= 0.0 && f < (double)kBins) atomicAdd(&hcnt[(int)f], 1u);
+        for (int64_t i0 = threadIdx.x; i0 < m; i0 += (int64_t)NT * kSegUnroll) {
+          CellLd x[kSegUnroll];
+#pragma unroll
+          for (int u = 0; u < kSegUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * NT;
+            x[u] = load_cell(J, seg_cell<MODE>(a, i < m ? i : 0), ncell);
+          }
+#pragma unroll
+          for (int u = 0; u < kSegUnroll; ++u) {
+            if (i0 + (int64_t)u * NT >= m || !elig(x[u])) continue;
+            const int64_t q = quant(x[u].s);
+            if (q > T) continue;
+            const double v = (double)q / TWO40;
+            const double f = floor((v - lo) / w);
+            if (f >= 0.0 && f < (double)kBins) atomicAdd(&hcnt[(int)f], 1u);
+          }
         }
       }
       __syncthreads();
@@ -1014,7 +1032,7 @@ __global__ __launch_bounds__(kSegThreads) void segclip_kernel(SegArgs a) {
   }
   __syncthreads();
   const int64_t T = sT;
-  for (int64_t i = threadIdx.x; i < m; i += kSegThreads) {
+  for (int64_t i = threadIdx.x; i < m; i += NT) {
     const int64_t c = seg_cell<MODE>(a, i);
     const CellLd x = load_cell(J, c, ncell);
     const uint8_t hit = (elig(x) && quant(x.s) > T) ? 1 : 0;
@@ -1056,76 +1074,131 @@ __global__ __launch_bounds__(256) void fit_kernel(int n, const int64_t* N, const
   }
 }
 
-__device__ __forceinline__ bool eligible(const uint8_t* status, const uint8_t* protect,
-                                         int64_t c, int nchan) {
-  if (status[c] & (RFI_CELL_DEGENERATE | RFI_CELL_BAD_COUNT)) return false;
-  if (protect && protect[c % nchan]) return false;
-  return true;
+// Per-beam eigenvector threshold, two launches over (beam, cell range)
+// workgroups: (1) each workgroup's (n, sum |v|, sum |v|^2) over the eligible
+// unmasked cells of its range, in FP64; (2) every workgroup of a beam sums its
+// beam's partials in one fixed order (so all of them get the same fit), forms
+// mu, sigma (population) and thr = mu + kappa_v sigma, and writes the beam
+// mask of its range. Loads are issued four cells at a time, unconditionally.
+constexpr int kVT = 256;                // threads per workgroup
+constexpr int kVPer = 4;                // cells per thread and step
+constexpr int kVCells = 16384;          // cells per workgroup and beam (at least)
+constexpr int kVMaxBlk = 256;           // workgroups per beam (at most)
+
+int eigvec_blocks(int64_t ncell) {
+  int64_t nb = (ncell + kVCells - 1) / kVCells;
+  return nb < 1 ? 1 : (nb > kVMaxBlk ? kVMaxBlk : (int)nb);
 }
 
-// Per-beam eigenvector threshold: one workgroup per beam.
-constexpr int FT = 1024;
-__global__ __launch_bounds__(FT) void eigvec_kernel(int nbeam, int nsub, int nchan,
-                                                    const float* __restrict__ v1,
-                                                    const uint8_t* __restrict__ mask,
-                                                    const uint8_t* __restrict__ status,
-                                                    const uint8_t* __restrict__ protect,
-                                                    double kappa_v, uint8_t* __restrict__ beam_mask,
-                                                    double* beam_mu, double* beam_sigma) {
-  __shared__ double s1[FT / 64], s2[FT / 64];
-  __shared__ int64_t sn[FT / 64];
-  __shared__ double fit_thr;
-  const int b = blockIdx.x;
+__device__ __forceinline__ void eigvec_range(int64_t ncell, int nblk, int blk, int64_t& c0,
+                                             int64_t& c1) {
+  const int64_t per = (ncell + nblk - 1) / nblk;
+  c0 = (int64_t)blk * per;
+  c1 = c0 + per < ncell ? c0 + per : ncell;
+}
+
+__global__ __launch_bounds__(kVT) void eigvec_stats_kernel(int nsub, int nchan, int nblk,
+                                                           const float* __restrict__ v1,
+                                                           const uint8_t* __restrict__ mask,
+                                                           const uint8_t* __restrict__ status,
+                                                           const uint8_t* __restrict__ protect,
+                                                           double* __restrict__ part) {
+  const int blk = blockIdx.x, b = blockIdx.y;
   const int64_t ncell = (int64_t)nsub * nchan;
+  int64_t c0, c1;
+  eigvec_range(ncell, nblk, blk, c0, c1);
   const float* vb = v1 + (int64_t)b * ncell;
-  // pass 1: mean of |v_b| over eligible unmasked cells
-  double a1 = 0.0;
-  int64_t n = 0;
-  for (int64_t c = threadIdx.x; c < ncell; c += FT) {
-    if (!eligible(status, protect, c, nchan) || mask[c]) continue;
-    a1 += fabs((double)vb[c]);
-    n += 1;
+  double n = 0.0, a1 = 0.0, a2 = 0.0;
+  for (int64_t base = c0 + threadIdx.x; base < c1; base += (int64_t)kVT * kVPer) {
+    float v[kVPer];
+    uint8_t m[kVPer], st[kVPer], pr[kVPer];
+#pragma unroll
+    for (int i = 0; i < kVPer; ++i) {
+      const int64_t c = base + (int64_t)i * kVT;
+      const int64_t cc = c < c1 ? c : c0;
+      v[i] = vb[cc];
+      m[i] = mask[cc];
+      st[i] = status[cc];
+      pr[i] = protect ? protect[cc % nchan] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kVPer; ++i) {
+      const int64_t c = base + (int64_t)i * kVT;
+      const bool use = c < c1 && !(st[i] & (RFI_CELL_DEGENERATE | RFI_CELL_BAD_COUNT)) &&
+                       !pr[i] && !m[i];
+      const double x = fabs((double)v[i]);
+      n += use ? 1.0 : 0.0;
+      a1 += use ? x : 0.0;
+      a2 += use ? x * x : 0.0;
+    }
   }
+  __shared__ double sh[3][kVT / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int off = 32; off > 0; off >>= 1) {
-    a1 += __shfl_down(a1, off);
     n += __shfl_down(n, off);
+    a1 += __shfl_down(a1, off);
+    a2 += __shfl_down(a2, off);
   }
-  if (lane == 0) { s1[wave] = a1; sn[wave] = n; }
+  if (lane == 0) {
+    sh[0][wave] = n;
+    sh[1][wave] = a1;
+    sh[2][wave] = a2;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    int64_t nn = 0;
-    for (int w = 0; w < FT / 64; ++w) { t += s1[w]; nn += sn[w]; }
-    s1[0] = nn > 0 ? t / (double)nn : NAN;
-    sn[0] = nn;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+    for (int w = 0; w < kVT / 64; ++w) {
+      t0 += sh[0][w];
+      t1 += sh[1][w];
+      t2 += sh[2][w];
+    }
+    double* o = part + ((int64_t)b * nblk + blk) * 3;
+    o[0] = t0;
+    o[1] = t1;
+    o[2] = t2;
   }
+}
+
+__global__ __launch_bounds__(kVT) void eigvec_mask_kernel(int nsub, int nchan, int nblk,
+                                                          const float* __restrict__ v1,
+                                                          const uint8_t* __restrict__ mask,
+                                                          const double* __restrict__ part,
+                                                          double kappa_v,
+                                                          uint8_t* __restrict__ beam_mask,
+                                                          double* beam_mu, double* beam_sigma) {
+  const int blk = blockIdx.x, b = blockIdx.y;
+  const int64_t ncell = (int64_t)nsub * nchan;
+  // the beam's fit from its partials: thread t takes partial t (nblk <= kVT),
+  // then a fixed tree, so every workgroup of the beam gets the same bits
+  __shared__ double sh[3][kVT];
+  const double* pb = part + (int64_t)b * nblk * 3;
+  const int t = threadIdx.x;
+  sh[0][t] = t < nblk ? pb[3 * t] : 0.0;
+  sh[1][t] = t < nblk ? pb[3 * t + 1] : 0.0;
+  sh[2][t] = t < nblk ? pb[3 * t + 2] : 0.0;
   __syncthreads();
-  const double mu = s1[0];
-  const int64_t ntot = sn[0];
-  __syncthreads();
-  // pass 2: population variance about mu
-  double a2 = 0.0;
-  for (int64_t c = threadIdx.x; c < ncell; c += FT) {
-    if (!eligible(status, protect, c, nchan) || mask[c]) continue;
-    const double dv = fabs((double)vb[c]) - mu;
-    a2 += dv * dv;
+  for (int h = kVT / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      sh[0][t] += sh[0][t + h];
+      sh[1][t] += sh[1][t + h];
+      sh[2][t] += sh[2][t + h];
+    }
+    __syncthreads();
   }
-  for (int off = 32; off > 0; off >>= 1) a2 += __shfl_down(a2, off);
-  if (lane == 0) s2[wave] = a2;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < FT / 64; ++w) t += s2[w];
-    const double sd = ntot > 0 ? sqrt(t / (double)ntot) : NAN;
-    fit_thr = mu + kappa_v * sd;
+  const double n = sh[0][0], s1 = sh[1][0], s2 = sh[2][0];
+  const double mu = n > 0.0 ? s1 / n : NAN;
+  const double var = n > 0.0 ? (s2 - s1 * mu) / n : NAN;
+  const double sd = n > 0.0 ? sqrt(var > 0.0 ? var : 0.0) : NAN;
+  const double thr = mu + kappa_v * sd;
+  if (blk == 0 && t == 0) {
     if (beam_mu) beam_mu[b] = mu;
     if (beam_sigma) beam_sigma[b] = sd;
   }
-  __syncthreads();
-  const double thr = fit_thr;
+  int64_t c0, c1;
+  eigvec_range(ncell, nblk, blk, c0, c1);
+  const float* vb = v1 + (int64_t)b * ncell;
   uint8_t* out = beam_mask + (int64_t)b * ncell;
-  for (int64_t c = threadIdx.x; c < ncell; c += FT)
+  for (int64_t c = c0 + t; c < c1; c += kVT)
     out[c] = (mask[c] && fabs((double)vb[c]) > thr) ? 1 : 0;
 }
 
@@ -1209,7 +1282,8 @@ hipError_t launch_clip_scoped(const ClipJob& g, int scopes, int fit, rfi_flag_st
     } else {
       a.out = g.out;
       a.write = 1;
-      hipLaunchKernelGGL(segclip_kernel<2>, dim3(1), dim3(kSegThreads), 0, s, a);
+      hipLaunchKernelGGL((segclip_kernel<2, kSegThreadsAll>), dim3(1), dim3(kSegThreadsAll), 0, s,
+                         a);
     }
   } else if (ncell > 0) {
     const unsigned grid = (unsigned)std::min<int64_t>((ncell + 255) / 256, 4096);
@@ -1218,11 +1292,13 @@ hipError_t launch_clip_scoped(const ClipJob& g, int scopes, int fit, rfi_flag_st
   a.write = 0;
   if ((scopes & 2) && g.nsub > 0) {
     a.out = chan_out;
-    hipLaunchKernelGGL(segclip_kernel<0>, dim3((unsigned)g.nchan), dim3(kSegThreads), 0, s, a);
+    hipLaunchKernelGGL((segclip_kernel<0, kSegThreads>), dim3((unsigned)g.nchan), dim3(kSegThreads),
+                       0, s, a);
   }
   if ((scopes & 4) && g.nsub > 0) {
     a.out = sub_out;
-    hipLaunchKernelGGL(segclip_kernel<1>, dim3((unsigned)g.nsub), dim3(kSegThreads), 0, s, a);
+    hipLaunchKernelGGL((segclip_kernel<1, kSegThreads>), dim3((unsigned)g.nsub), dim3(kSegThreads),
+                       0, s, a);
   }
   return hipGetLastError();
 }
@@ -1235,13 +1311,24 @@ hipError_t launch_fit(int n, const int64_t* N, const uint64_t* Q1, const uint64_
   return hipGetLastError();
 }
 
+size_t eigvec_workspace_size(int nbeam, int64_t ncell) {
+  return (size_t)nbeam * eigvec_blocks(ncell) * 3 * sizeof(double);
+}
+
 hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float* v1,
                               const uint8_t* mask, const uint8_t* status,
                               const uint8_t* protect_chan, double kappa_v,
-                              uint8_t* beam_mask, double* beam_mu, double* beam_sigma,
+                              uint8_t* beam_mask, double* beam_mu, double* beam_sigma, void* ws,
                               hipStream_t s) {
-  hipLaunchKernelGGL(eigvec_kernel, dim3(nbeam), dim3(FT), 0, s, nbeam, nsub, nchan, v1, mask,
-                     status, protect_chan, kappa_v, beam_mask, beam_mu, beam_sigma);
+  const int64_t ncell = (int64_t)nsub * nchan;
+  const int nblk = eigvec_blocks(ncell);
+  double* part = (double*)ws;
+  hipLaunchKernelGGL(eigvec_stats_kernel, dim3(nblk, nbeam), dim3(kVT), 0, s, nsub, nchan, nblk,
+                     v1, mask, status, protect_chan, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(eigvec_mask_kernel, dim3(nblk, nbeam), dim3(kVT), 0, s, nsub, nchan, nblk,
+                     v1, mask, (const double*)part, kappa_v, beam_mask, beam_mu, beam_sigma);
   return hipGetLastError();
 }
 

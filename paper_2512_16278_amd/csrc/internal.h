@@ -48,11 +48,14 @@ hipError_t launch_ccm_batch(int nbeam_of_class, const CcmTune* t, const CcmItem*
 
 // Kernel launchers (return a HIP error code; arguments already validated).
 // kstride: samples from the start of one sub-interval to the next (0 = L:
-// back to back; longer strides sum one time chunk of long sub-intervals).
+// back to back; longer strides sum one time chunk of long sub-intervals);
+// ksplit > 1: launch sub-interval k starts at t0 + (k / ksplit) kstride +
+// (k mod ksplit) L (ksplit consecutive chunks of L samples per stride).
 hipError_t launch_ccm_mfma(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int32_t* sum_x, int32_t* sum_xy,
                            int32_t* count, int accumulate, int shared_cu, hipStream_t s,
-                           const CcmTune* t = nullptr, int layout = 0, int64_t kstride = 0);
+                           const CcmTune* t = nullptr, int layout = 0, int64_t kstride = 0,
+                           int ksplit = 1);
 // Sums layouts: 0 = the C ABI's rows (sum_x[b][cell], sum_xy[pair][cell]);
 // 1 = one record per cell, sum_x[cell * (nbeam + npair) + row] with rows b
 // then nbeam + pair (sum_xy unused): what a one-cell-per-wave consumer reads
@@ -159,10 +162,13 @@ hipError_t launch_clip_scoped(const ClipJob& g, int scopes, int fit, rfi_flag_st
 // Q1, Q2 as little-endian 64-bit limb pairs).
 hipError_t launch_fit(int n, const int64_t* N, const uint64_t* Q1, const uint64_t* Q2,
                       double kappa, double* mu, double* sigma, double* thr, hipStream_t s);
+// Per-beam eigenvector stage: ws holds eigvec_workspace_size bytes of
+// per-workgroup partial sums.
+size_t eigvec_workspace_size(int nbeam, int64_t ncell);
 hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float* v1,
                               const uint8_t* mask, const uint8_t* status,
                               const uint8_t* protect_chan, double kappa_v,
-                              uint8_t* beam_mask, double* beam_mu, double* beam_sigma,
+                              uint8_t* beam_mask, double* beam_mu, double* beam_sigma, void* ws,
                               hipStream_t s);
 
 // Error reporting shared by the entry points (thread-local message).

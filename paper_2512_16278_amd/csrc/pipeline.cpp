@@ -230,9 +230,11 @@ rfi_status rfi_process_block(const rfi_block* blk, const rfi_process_params* p,
                                              pl.kappa, pl.max_iter, state, mask, out, workspace);
   e = rfi::launch_clip(cj, s);
   if (e != hipSuccess) return rfi::check_hip(e, "rfi_process_block: clip launch");
+  // the per-beam stage's partial sums reuse the clip's workspace (the clip
+  // has run by then: same stream), which is always larger
   if (p->beam_mask)
     e = rfi::launch_eigvec_flag(blk->nbeam, pl.nsub, pl.nchan, v1, mask, status, protect_chan,
-                                p->kappa_v, p->beam_mask, nullptr, nullptr, s);
+                                p->kappa_v, p->beam_mask, nullptr, nullptr, workspace, s);
   return rfi::check_hip(e, "rfi_process_block: per-beam stage launch");
 }
 

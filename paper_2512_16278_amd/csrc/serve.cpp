@@ -93,6 +93,9 @@ struct Request {
   double* stat = nullptr;
   uint8_t* cstat = nullptr;
   uint8_t* mask = nullptr;
+  float* v1 = nullptr;               // per-beam stage outputs (streams with beam_stage)
+  uint8_t* bmask = nullptr;
+  bool beams = false;                // the stream has the per-beam stage
   rfi_flag_stats flag{};
   double t_submit = 0, t_admit = 0, t_done = 0;
   int slot = -1;
@@ -265,6 +268,8 @@ rfi_status plan_block(const StreamCtx& st, int64_t nsamp, BlockPlan* b, const ch
   b->ws = b->pl.ws_bytes;
   const size_t ncell = (size_t)b->nsub * st.cfg.nchan;
   b->res = ncell ? up(ncell * 8) + up(ncell) + up(ncell) : 0;
+  if (ncell && st.cfg.beam_stage)
+    b->res += up(ncell * st.cfg.nbeam * 4) + up(ncell * st.cfg.nbeam);
   return RFI_OK;
 }
 
@@ -311,6 +316,10 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
     r->stat = (double*)r->res;
     r->cstat = (uint8_t*)r->res + up(ncell * 8);
     r->mask = r->cstat + up(ncell);
+    if (st.cfg.beam_stage) {
+      r->v1 = (float*)(r->mask + up(ncell));
+      r->bmask = (uint8_t*)r->v1 + up(ncell * n * 4);
+    }
   }
   // from here on a failure leaves work of this block enqueued behind it (the
   // stream-order wait and the allocations above change no state)
@@ -323,7 +332,7 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
   }
   if (b.carried) {
     EigArgs a{n, 1, F, st.carry_sx(), st.carry_sxy(), st.carry_cnt(), b.pl.eig.max_sweeps, 1,
-              nullptr, r->stat, nullptr, r->cstat, (int64_t)b.nsub * F};
+              nullptr, r->stat, r->v1, r->cstat, (int64_t)b.nsub * F};
     e = launch_eig(a, b.pl.eig, s, b.pl.eig_wg ? b.pl.eig_wg : 256);
     if (e != hipSuccess) return dev(e, "rfi_submit: carry eigen stage");
   }
@@ -332,7 +341,8 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
     ProcessPlan pl = b.pl;
     char* ws = (char*)sl.ws;
     e = enqueue_eig_groups(bp, stride, b.t_full, L, pl, r->stat + (size_t)b.carried * F,
-                           r->cstat + (size_t)b.carried * F, nullptr, nullptr,
+                           r->cstat + (size_t)b.carried * F, nullptr,
+                           r->v1 ? r->v1 + (size_t)b.carried * F : nullptr,
                            (int64_t)b.nsub * F, ws + pl.flag_ws, sl.ev, s);
     if (e != hipSuccess) return dev(e, "rfi_submit: sums / eigen stage");
   }
@@ -348,6 +358,12 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
                                      b.pl.max_iter, st.state, r->mask, sl.dstats, sl.ws);
     e = launch_clip(cj, s);
     if (e != hipSuccess) return dev(e, "rfi_submit: clip");
+    // per-beam stage: its partial sums reuse the clip's workspace (larger)
+    if (r->bmask) {
+      e = launch_eigvec_flag(n, b.nsub, F, r->v1, r->mask, r->cstat, st.protect, st.cfg.kappa_v,
+                             r->bmask, nullptr, nullptr, sl.ws, s);
+      if (e != hipSuccess) return dev(e, "rfi_submit: per-beam stage");
+    }
     if ((e = hipMemcpyAsync(sl.hstats, sl.dstats, sizeof(rfi_flag_stats), hipMemcpyDeviceToHost,
                             s)) != hipSuccess)
       return dev(e, "rfi_submit: clip summary");
@@ -598,6 +614,10 @@ rfi_status rfi_stream_open(rfi_session* s, const rfi_stream_config* c, int32_t* 
   if (cfg.L < 1 || cfg.L > RFI_MAX_COUNT)
     return fail(RFI_E_INVALID, "%s: L %d outside 1..%d", who, cfg.L, RFI_MAX_COUNT);
   if (!(cfg.kappa >= 0.0)) return fail(RFI_E_INVALID, "%s: kappa must be >= 0", who);
+  if (cfg.beam_stage != 0 && cfg.beam_stage != 1)
+    return fail(RFI_E_INVALID, "%s: beam_stage must be 0 or 1", who);
+  if (cfg.beam_stage && !(cfg.kappa_v >= 0.0))
+    return fail(RFI_E_INVALID, "%s: kappa_v must be >= 0", who);
   if (cfg.max_iter < 1) return fail(RFI_E_INVALID, "%s: max_iter %d < 1", who, cfg.max_iter);
   rfi::ProcessPlan pl;
   rfi_process_params p{};
@@ -665,6 +685,7 @@ rfi_status rfi_submit(rfi_session* s, int32_t stream_id, const rfi_block* blk, u
     return fail(RFI_E_BUDGET, "%s: block of %lld bytes exceeds the budget of %lld", who,
                 (long long)rfi::input_bytes(*blk), (long long)s->budget);
   std::unique_ptr<rfi::Request> r(new rfi::Request);
+  r->beams = st.cfg.beam_stage != 0;
   r->ticket = s->next_ticket++;
   r->tag = user_tag;
   r->stream_id = stream_id;
@@ -696,6 +717,8 @@ static void fill_result(const rfi::Request& r, rfi_result* out) {
   out->t_submit_us = r.t_submit;
   out->t_admit_us = r.t_admit;
   out->t_done_us = r.t_done;
+  out->v1 = r.v1;
+  out->beam_mask = r.bmask;
 }
 
 rfi_status rfi_poll(rfi_session* s, uint64_t ticket, rfi_result* r) {
@@ -765,6 +788,26 @@ rfi_status rfi_result_copy(rfi_session* s, uint64_t ticket, double* stat, uint8_
     e = hipMemcpy(cell_status, r->cstat, n, hipMemcpyDeviceToHost);
   if (e == hipSuccess && mask) e = hipMemcpy(mask, r->mask, n, hipMemcpyDeviceToHost);
   return rfi::check_hip(e, "rfi_result_copy");
+}
+
+rfi_status rfi_result_copy_beams(rfi_session* s, uint64_t ticket, float* v1, uint8_t* beam_mask) {
+  rfi::clear_error();
+  if (!s) return fail(RFI_E_INVALID, "rfi_result_copy_beams: NULL session");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(RFI_E_INVALID, "rfi_result_copy_beams: unknown ticket");
+  rfi::Request* r = it->second.get();
+  if (r->st != rfi::RState::Done)
+    return fail(RFI_E_NOT_READY, "rfi_result_copy_beams: ticket still queued or running");
+  if (!r->beams)
+    return fail(RFI_E_INVALID, "rfi_result_copy_beams: the stream has no per-beam stage");
+  const size_t n = (size_t)r->nsub * r->blk.nchan * r->blk.nbeam;
+  if (n == 0 || !r->bmask) return RFI_OK;
+  rfi::DeviceGuard g(s->device);
+  hipError_t e = hipSuccess;
+  if (v1) e = hipMemcpy(v1, r->v1, n * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && beam_mask) e = hipMemcpy(beam_mask, r->bmask, n, hipMemcpyDeviceToHost);
+  return rfi::check_hip(e, "rfi_result_copy_beams");
 }
 
 rfi_status rfi_result_release(rfi_session* s, uint64_t ticket) {

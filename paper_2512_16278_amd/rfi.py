@@ -107,7 +107,8 @@ class rfi_session_config(C.Structure):
 class rfi_stream_config(C.Structure):
     _fields_ = [("nbeam", C.c_int32), ("nchan", C.c_int32), ("L", C.c_int32),
                 ("eig_precision", C.c_int32), ("max_sweeps", C.c_int32), ("max_iter", C.c_int32),
-                ("kappa", C.c_double), ("protect_chan", C.c_void_p)]
+                ("kappa", C.c_double), ("protect_chan", C.c_void_p), ("beam_stage", C.c_int32),
+                ("pad", C.c_int32), ("kappa_v", C.c_double)]
 
 
 class rfi_result(C.Structure):
@@ -116,7 +117,7 @@ class rfi_result(C.Structure):
                 ("carried", C.c_int32), ("carry_samples", C.c_int64), ("stat", C.c_void_p),
                 ("cell_status", C.c_void_p), ("mask", C.c_void_p), ("flag", rfi_flag_stats),
                 ("t_submit_us", C.c_double), ("t_admit_us", C.c_double),
-                ("t_done_us", C.c_double)]
+                ("t_done_us", C.c_double), ("v1", C.c_void_p), ("beam_mask", C.c_void_p)]
 
 
 class rfi_synth_spec(C.Structure):
@@ -168,7 +169,9 @@ def lib():
         L.rfi_bandpass_workspace_size.restype = C.c_size_t
         L.rfi_bandpass_arpls.argtypes = [i32, i32, i32, vp, vp, dbl, dbl, i32, vp, vp, vp, vp]
         L.rfi_eig_noncentred.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
-        L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp]
+        L.rfi_eigvec_flag.argtypes = [i32, i32, i32, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp]
+        L.rfi_eigvec_workspace_size.argtypes = [i32, i32, i32]
+        L.rfi_eigvec_workspace_size.restype = C.c_size_t
         L.rfi_process_workspace_size.argtypes = [i32, i32, C.POINTER(rfi_process_params)]
         L.rfi_process_workspace_size.restype = C.c_size_t
         L.rfi_process_block.argtypes = [C.POINTER(rfi_block), C.POINTER(rfi_process_params),
@@ -185,6 +188,7 @@ def lib():
         L.rfi_cancel.argtypes = [vp, u64]
         L.rfi_result_release.argtypes = [vp, u64]
         L.rfi_result_copy.argtypes = [vp, u64, vp, vp, vp]
+        L.rfi_result_copy_beams.argtypes = [vp, u64, vp, vp]
         L.rfi_batch_workspace_size.argtypes = [i32, C.POINTER(rfi_batch_item),
                                                C.POINTER(rfi_batch_params)]
         L.rfi_batch_workspace_size.restype = C.c_size_t
@@ -209,7 +213,8 @@ def lib():
                   "rfi_process_block", "rfi_session_create", "rfi_stream_open",
                   "rfi_stream_close", "rfi_submit", "rfi_poll", "rfi_wait", "rfi_cancel",
                   "rfi_result_release", "rfi_stream_export", "rfi_stream_import",
-                  "rfi_result_copy", "rfi_process_batch", "rfi_batch_graph_create",
+                  "rfi_result_copy", "rfi_result_copy_beams", "rfi_process_batch",
+                  "rfi_batch_graph_create",
                   "rfi_batch_graph_launch", "rfi_tune_batch"):
             getattr(L, f).restype = i32
         L.rfi_last_error.restype = C.c_char_p
@@ -394,11 +399,21 @@ def rfi_process_block(blk: rfi_block, p: rfi_process_params, stat, status, mask,
                                    _ptr(out), _ptr(workspace), _stream(stream)))
 
 
+def rfi_eigvec_workspace_size(nbeam, nsub, nchan):
+    return int(lib().rfi_eigvec_workspace_size(int(nbeam), int(nsub), int(nchan)))
+
+
 def rfi_eigvec_flag(nbeam, nsub, nchan, v1, mask, status, beam_mask, protect_chan=None,
-                    kappa_v=1.0, beam_mu=None, beam_sigma=None, stream=None):
+                    kappa_v=1.0, beam_mu=None, beam_sigma=None, workspace=None, stream=None):
+    """rfi_eigvec_flag; workspace=None takes a buffer from torch."""
+    if workspace is None:
+        import torch
+        workspace = torch.empty(max(rfi_eigvec_workspace_size(nbeam, nsub, nchan), 8),
+                                dtype=torch.uint8, device=v1.device)
     _check(lib().rfi_eigvec_flag(int(nbeam), int(nsub), int(nchan), _ptr(v1), _ptr(mask),
                                  _ptr(status), _ptr(protect_chan), float(kappa_v), _ptr(beam_mask),
-                                 _ptr(beam_mu), _ptr(beam_sigma), _stream(stream)))
+                                 _ptr(beam_mu), _ptr(beam_sigma), _ptr(workspace),
+                                 _stream(stream)))
 
 
 # --- batched uneven blocks --------------------------------------------------------
@@ -494,14 +509,15 @@ class Session:
         self.close()
 
     def open_stream(self, nbeam, nchan, L, kappa=3.0, max_iter=50, eig_precision=32,
-                    max_sweeps=12, protect_chan=None) -> int:
+                    max_sweeps=12, protect_chan=None, beam_stage=False, kappa_v=1.0) -> int:
         keep = None
         pp = None
         if protect_chan is not None:
             keep = np.ascontiguousarray(np.asarray(protect_chan, dtype=np.uint8))
             pp = keep.ctypes.data
         cfg = rfi_stream_config(int(nbeam), int(nchan), int(L), int(eig_precision),
-                                int(max_sweeps), int(max_iter), float(kappa), pp)
+                                int(max_sweeps), int(max_iter), float(kappa), pp,
+                                1 if beam_stage else 0, 0, float(kappa_v))
         sid = C.c_int32()
         _check(lib().rfi_stream_open(self.h, C.byref(cfg), C.byref(sid)))
         return sid.value
@@ -554,6 +570,16 @@ def result_arrays(sess: "Session", r: rfi_result):
     _check(lib().rfi_result_copy(sess.h, r.ticket, stat.ctypes.data, cst.ctypes.data,
                                  mask.ctypes.data))
     return stat, cst, mask
+
+
+def result_beams(sess: "Session", r: rfi_result, nbeam: int):
+    """Host copies (v1 [nbeam, ncell], beam mask [nbeam, ncell]) of a done
+    ticket of a stream opened with beam_stage."""
+    n = r.nsub * r.nchan
+    v1 = np.zeros((nbeam, n), dtype=np.float32)
+    bm = np.zeros((nbeam, n), dtype=np.uint8)
+    _check(lib().rfi_result_copy_beams(sess.h, r.ticket, v1.ctypes.data, bm.ctypes.data))
+    return v1, bm
 
 
 def flag_stats_from_bytes(raw: bytes) -> dict:

@@ -381,7 +381,7 @@ void PipeEvents::destroy() { ready = false; }
 
 hipError_t launch_ccm_mfma(const BeamPtrs&, int, int, int64_t, int64_t, int L, int nsub,
                            int32_t*, int32_t*, int32_t* count, int accumulate, int, hipStream_t s,
-                           const CcmTune*, int, int64_t) {
+                           const CcmTune*, int, int64_t, int) {
   if (take(g_fail_launch)) return hipErrorLaunchFailure;
   if (nsub != 1) g_errors++;
   work(s, [=] { count[0] = accumulate ? count[0] + L : L; });
@@ -413,6 +413,19 @@ hipError_t enqueue_eig_groups(const BeamPtrs& bp, int64_t row_stride, int64_t t0
         stat[(int64_t)k * F + j] = b0[(t0 + (int64_t)k * L) * row_stride + j];
         status[(int64_t)k * F + j] = 0;
       }
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_eigvec_flag(int nbeam, int nsub, int nchan, const float*, const uint8_t* mask,
+                              const uint8_t*, const uint8_t*, double, uint8_t* beam_mask,
+                              double*, double*, void* ws, hipStream_t s) {
+  if (take(g_fail_launch)) return hipErrorLaunchFailure;
+  if (!ws) g_errors++;
+  const int64_t n = (int64_t)nsub * nchan;
+  work(s, [=] {
+    for (int b = 0; b < nbeam; ++b)
+      for (int64_t c = 0; c < n; ++c) beam_mask[b * n + c] = mask[c];
   });
   return hipSuccess;
 }

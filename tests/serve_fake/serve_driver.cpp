@@ -99,7 +99,7 @@ rfi_session* make_session(int slots, int64_t budget) {
 }
 
 int open_stream(rfi_session* s, int L) {
-  rfi_stream_config c{NB, NC, L, 32, 12, 50, 3.0, nullptr};
+  rfi_stream_config c{NB, NC, L, 32, 12, 50, 3.0, nullptr, 0, 0, 1.0};
   int32_t id = -1;
   if (rfi_stream_open(s, &c, &id) != RFI_OK) return -1;
   return id;
@@ -317,6 +317,40 @@ void partial_launch_failure() {
   std::printf("ok partial_launch_failure\n");
 }
 
+void beam_stage() {
+  fake_set_work_us(100);
+  rfi_session* s = make_session(2, 0);
+  CHECK(s);
+  rfi_stream_config c{NB, NC, 16, 32, 12, 50, 3.0, nullptr, 1, 0, 1.0};
+  int32_t id = -1;
+  CHECK(rfi_stream_open(s, &c, &id) == RFI_OK);
+  rfi_stream_config bad = c;
+  bad.kappa_v = -1.0;
+  int32_t id2 = -1;
+  CHECK(rfi_stream_open(s, &bad, &id2) == RFI_E_INVALID);
+  Expect ex{16};
+  Block B1(37, 5), B2(30, 6);
+  for (Block* b : {&B1, &B2}) {
+    uint64_t t;
+    CHECK(rfi_submit(s, id, &b->blk, 0, &t) == RFI_OK);
+    rfi_result r{};
+    CHECK(rfi_wait(s, t, -1, &r) == RFI_OK && r.status == RFI_OK);
+    CHECK(r.v1 != nullptr && r.beam_mask != nullptr);
+    const Expect::One e = ex.next(b->blk.nsamp);
+    const size_t n = (size_t)e.nsub * NC;
+    std::vector<uint8_t> mask(n + 1), bm(NB * n + 1);
+    std::vector<float> v1(NB * n + 1);
+    CHECK(rfi_result_copy(s, t, nullptr, nullptr, mask.data()) == RFI_OK);
+    CHECK(rfi_result_copy_beams(s, t, v1.data(), bm.data()) == RFI_OK);
+    for (int bb = 0; bb < NB; ++bb)
+      for (size_t i = 0; i < n; ++i) CHECK(bm[bb * n + i] == mask[i]);   // the fake stage
+    CHECK(rfi_result_release(s, t) == RFI_OK);
+  }
+  rfi_session_destroy(s);
+  CHECK(fake_errors() == 0);
+  std::printf("ok beam_stage\n");
+}
+
 void many_threads() {
   fake_set_work_us(50);
   rfi_session* s = make_session(3, 0);
@@ -374,6 +408,7 @@ int main() {
   export_import();
   allocation_failure();
   partial_launch_failure();
+  beam_stage();
   many_threads();
   std::printf(g_fail ? "SOME CHECKS FAILED\n" : "ALL OK\n");
   return g_fail ? 1 : 0;

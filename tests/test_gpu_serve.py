@@ -133,6 +133,76 @@ def test_serve_alone_equals_mix_and_oracle(dev):
             done = kend
 
 
+def test_serve_beam_stage(dev):
+    """Streams opened with the per-beam stage (Sec. 3.3 last paragraph): each
+    block also returns v1 and the per-beam mask. The stat, status and mask
+    are those of the same stream without the stage, bit for bit; v1 is unit
+    norm on every non-degenerate cell (row 0 of a carried block included);
+    the per-beam mask equals rfi_eigvec_flag run on the block's own v1, mask
+    and status; results are the same alone and in the mix."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    specs = [STREAMS[0], STREAMS[3]]
+    data = [_blocks(dev, spec, 70 + i) for i, spec in enumerate(specs)]
+
+    def run(slots, beams):
+        out = []
+        with rfi.Session(max_inflight=slots) as s:
+            sids = [s.open_stream(nb, nc, L, beam_stage=beams, kappa_v=1.0)
+                    for nb, nc, L, _ in specs]
+            tk = [[s.submit(sid, rfi.make_block(b, spec[1]), tag=i) for i, b in enumerate(bufs)]
+                  for sid, spec, (_, bufs) in zip(sids, specs, data)]
+            for spec, ts in zip(specs, tk):
+                res = []
+                for t in ts:
+                    r = s.wait(t, timeout_us=60_000_000)
+                    assert r.status == rfi.RFI_OK
+                    arr = rfi.result_arrays(s, r)
+                    if beams:
+                        # outputs exist for blocks with cells (a block that only
+                        # extends the carry has none)
+                        assert bool(r.v1) == bool(r.beam_mask) == (r.nsub > 0)
+                        bm = rfi.result_beams(s, r, spec[0])
+                    else:
+                        assert not r.v1 and not r.beam_mask
+                        with pytest.raises(rfi.RfiError):
+                            rfi.result_beams(s, r, spec[0])
+                        bm = None
+                    res.append((r.nsub, r.carried, arr, bm))
+                    s.release(t)
+                out.append(res)
+        return out
+
+    say("serve: beam stage")
+    plain = run(1, False)
+    alone = run(1, True)
+    mixed = run(4, True)
+    for j, spec in enumerate(specs):
+        nb, nc = spec[0], spec[1]
+        for p, a, m in zip(plain[j], alone[j], mixed[j]):
+            assert p[:2] == a[:2] == m[:2]
+            for u, v, w in zip(p[2], a[2], m[2]):
+                assert np.array_equal(u, v) and np.array_equal(v, w)
+            assert np.array_equal(a[3][0], m[3][0]) and np.array_equal(a[3][1], m[3][1])
+            nsub = a[0]
+            if not nsub:
+                continue
+            stat, cst, mask = a[2]
+            v1, bm = a[3]
+            ok = (cst & (rfi.RFI_CELL_DEGENERATE | rfi.RFI_CELL_BAD_COUNT)) == 0
+            nrm = np.linalg.norm(v1.astype(np.float64), axis=0)
+            assert np.abs(nrm[ok] - 1.0).max() < 1e-5
+            # the per-beam stage recomputed on the device from the block's own outputs
+            vt = torch.from_numpy(v1).to(dev)
+            mt = torch.from_numpy(mask).to(dev)
+            ct = torch.from_numpy(cst).to(dev)
+            bt = torch.empty((nb, nsub * nc), dtype=torch.uint8, device=dev)
+            rfi.rfi_eigvec_flag(nb, nsub, nc, vt, mt, ct, bt, kappa_v=1.0)
+            torch.cuda.synchronize()
+            assert np.array_equal(bt.cpu().numpy(), bm)
+            assert not (bm.astype(bool) & ~mask.astype(bool)[None, :]).any()
+
+
 def test_serve_export_import(dev):
     from paper_2512_16278_amd import rfi
     nb, nc, L, lens = STREAMS[0]

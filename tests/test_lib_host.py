@@ -95,8 +95,14 @@ def test_argument_errors_are_synchronous():
     assert L.rfi_clip_fit(4, None, None, None, 3.0, None, None, None, None) == rfi.RFI_E_INVALID
     assert L.rfi_flag_noalloc(1 << 11, 1 << 10, C.c_void_p(256), C.c_void_p(256), None, 3.0,
                               50, None, C.c_void_p(256), None, None) == rfi.RFI_E_INVALID
+    # per-beam stage: workspace required
+    assert 0 < rfi.rfi_eigvec_workspace_size(19, 99, 4096) <= 79 * 256 * 24
+    assert rfi.rfi_eigvec_workspace_size(1, 99, 4096) == 0
+    assert L.rfi_eigvec_flag(19, 1, 64, C.c_void_p(256), C.c_void_p(256), C.c_void_p(256), None,
+                             1.0, C.c_void_p(256), None, None, None, None) == rfi.RFI_E_INVALID
+    assert b"workspace" in L.rfi_last_error()
     # ArPLS bandpass and the non-centred matrix: argument checks before any launch
-    assert rfi.rfi_bandpass_workspace_size(19, 4096, 1) == 6 * 19 * 4096 * 8
+    assert rfi.rfi_bandpass_workspace_size(19, 4096, 1) == 7 * 19 * 4096 * 8
     assert rfi.rfi_bandpass_workspace_size(1, 4096, 1) == 0
     v = C.c_void_p(256)
     assert L.rfi_bandpass_arpls(19, 1, 64, v, v, 0.0, 0.05, 100, v, None, v, None) == rfi.RFI_E_INVALID
