@@ -426,6 +426,10 @@ typedef struct {
   uint8_t* status;               /* device [nsub * nchan] */
   uint8_t* mask;                 /* device [nsub * nchan] */
   rfi_flag_stats* out;           /* device or NULL */
+  float* v1;                     /* device [nbeam][nsub * nchan] or NULL: dominant eigenvectors */
+  uint8_t* beam_mask;            /* device [nbeam][nsub * nchan] or NULL: the per-beam mask
+                                    (Sec. 3.3 last paragraph), as rfi_eigvec_flag on this
+                                    block's v1 and mask; needs v1 */
 } rfi_batch_item;
 
 /* Launch configuration of one shape class of the batched path. A class is
@@ -468,6 +472,8 @@ typedef struct {
   double kappa;                  /* clip multiple, >= 0 */
   const rfi_tune_table* tune;    /* host, nullable: per-class launch choices
                                     (read when the call plans the batch) */
+  double kappa_v;                /* per-beam multiple (Sec. 4.5), >= 0; read for items
+                                    with a beam_mask */
 } rfi_batch_params;
 
 /* Workspace bytes for the batch (0 on invalid arguments; rfi_last_error). */

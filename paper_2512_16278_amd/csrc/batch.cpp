@@ -46,6 +46,7 @@ struct ItemPlan {
 struct EigClass {
   int lane_cls, solver, precision, wg, max_nbeam;
   std::vector<int> items;  // indices into plans
+  bool v1 = false;         // some item asks for v1
 };
 
 struct CcmLaunchClass {
@@ -63,13 +64,14 @@ struct BatchPlan {
   std::vector<ItemPlan> plans;
   rfi_eig_params eig;      // sweeps, precision (solver per item)
   int max_iter = 50;
-  double kappa = 3.0;
+  double kappa = 3.0, kappa_v = 1.0;
   // descriptor area
   size_t tab_off = 0, ccm_off = 0, eig_off = 0, cell0_off = 0, flag_off = 0, desc_bytes = 0;
   size_t ws_bytes = 0;
   std::vector<CcmLaunchClass> ccm_classes;
   std::vector<EigClass> eig_classes;
   std::vector<char> host;  // descriptor bytes (device addresses resolved for ws)
+  std::vector<rfi_batch_item> items;  // the caller's items (host copy)
   std::vector<ClipJob> clip_jobs;  // host copy of the clip descriptors (grid sizes)
 };
 
@@ -77,7 +79,7 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
                       BatchPlan* bpn, const char* who) {
   if (nitem < 0) return fail(RFI_E_INVALID, "%s: nitem < 0", who);
   if (nitem > 0 && !items) return fail(RFI_E_INVALID, "%s: items is NULL", who);
-  rfi_batch_params prm{32, 12, 50, 0, 3.0, nullptr};
+  rfi_batch_params prm{32, 12, 50, 0, 3.0, nullptr, 1.0};
   if (p) prm = *p;
   if (prm.tune && (prm.tune->n < 0 || prm.tune->n > RFI_TUNE_MAX))
     return fail(RFI_E_INVALID, "%s: tune table with %d entries", who, prm.tune->n);
@@ -88,6 +90,8 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
   if (prm.max_iter < 1) return fail(RFI_E_INVALID, "%s: max_iter < 1", who);
   bpn->max_iter = prm.max_iter;
   bpn->kappa = prm.kappa;
+  bpn->kappa_v = prm.kappa_v;
+  bpn->items.assign(items, items + nitem);
   size_t tab_bytes = 0;
   for (int i = 0; i < nitem; ++i) {
     const rfi_batch_item& it = items[i];
@@ -99,6 +103,10 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
     if (it.nsub == 0) continue;
     if (!it.stat || !it.status || !it.mask)
       return fail(RFI_E_INVALID, "%s: item %d has a NULL output", who, i);
+    if (it.beam_mask && !it.v1)
+      return fail(RFI_E_INVALID, "%s: item %d: the per-beam mask needs v1", who, i);
+    if (it.beam_mask && !(prm.kappa_v >= 0.0))
+      return fail(RFI_E_INVALID, "%s: kappa_v must be >= 0", who);
     const rfi_tune_entry* te = find_tune(prm.tune, it.blk->nbeam);
     rfi_eig_params ep{prm.eig_precision, prm.max_sweeps, 1, te ? te->eig_solver : RFI_EIG_AUTO};
     rfi_eig_params res;
@@ -149,7 +157,10 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
   for (auto& kv : eig) {
     EigClass ec{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
                 std::get<3>(kv.first), 0, kv.second};
-    for (int k : kv.second) ec.max_nbeam = std::max(ec.max_nbeam, bpn->plans[k].nbeam);
+    for (int k : kv.second) {
+      ec.max_nbeam = std::max(ec.max_nbeam, bpn->plans[k].nbeam);
+      if (items[bpn->plans[k].idx].v1) ec.v1 = true;
+    }
     bpn->eig_classes.push_back(ec);
   }
   // layout
@@ -234,7 +245,7 @@ void fill_descriptors(const rfi_batch_item* items, BatchPlan* bpn, char* ws) {
       int32_t *sx, *sxy, *cnt;
       sums(ip, &sx, &sxy, &cnt);
       a = EigArgs{ip.nbeam, it.nsub, ip.nchan, sx, sxy, cnt, bpn->eig.max_sweeps, 1,
-                  nullptr, it.stat, nullptr, it.status, ip.ncell,
+                  nullptr, it.stat, it.v1, it.status, ip.ncell,
                   ip.solver == RFI_EIG_TRIDIAG ? 1 : 0};
       c0[cpos++] = cell;
       cell += ip.ncell;
@@ -287,7 +298,7 @@ hipError_t enqueue_eig(const BatchPlan& bpn, const void* desc, char* ws, hipStre
       e = launch_eig_lane_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s, ec.wg,
                                 ec.solver == RFI_EIG_LANE_TRI);
     else if (ec.solver == RFI_EIG_TRIDIAG)
-      e = launch_eig_tri_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s);
+      e = launch_eig_tri_batch(ec.lane_cls, ea + pos, c0 + cpos, m, total, s, ec.v1);
     else
       e = launch_eig_wave_batch(ec.precision, ec.max_nbeam, ea + pos, c0 + cpos, m, total, s);
     if (e != hipSuccess) return e;
@@ -304,7 +315,18 @@ hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipSt
   if (e == hipSuccess) e = enqueue_ccm(bpn, desc, ws, s);
   if (e == hipSuccess) e = enqueue_eig(bpn, desc, ws, s);
   if (e != hipSuccess) return e;
-  return launch_clip_batch((const ClipJob*)(ws + bpn.flag_off), bpn.clip_jobs.data(), n, s);
+  e = launch_clip_batch((const ClipJob*)(ws + bpn.flag_off), bpn.clip_jobs.data(), n, s);
+  // per-beam stages, after every clip: their partial sums reuse each block's
+  // clip workspace (always larger)
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    const ItemPlan& ip = bpn.plans[k];
+    const rfi_batch_item& it = bpn.items[ip.idx];
+    if (!it.beam_mask) continue;
+    e = launch_eigvec_flag(ip.nbeam, it.nsub, ip.nchan, it.v1, it.mask, it.status,
+                           it.protect_chan, bpn.kappa_v, it.beam_mask, nullptr, nullptr,
+                           ws + ip.clip_off, s);
+  }
+  return e;
 }
 
 // Median time (ms) of three runs of fn on s after one warm-up; -1 on a

@@ -577,10 +577,11 @@ hipError_t launch_eig_tri_nc(const EigArgs& a, const double* zb, hipStream_t s) 
 }
 
 hipError_t launch_eig_tri_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
-                                int64_t total, hipStream_t s) {
+                                int64_t total, hipStream_t s, bool v1) {
   if (total == 0) return hipSuccess;
   EigArgs none{};
-  return launch_cls<false>(cls, 0, none, items, cell0, nitem, total, false, s);
+  // with v1, LDS for the reflectors of the class's largest matrix (8 cls rows)
+  return launch_cls<false>(cls, v1 ? 8 * cls : 0, none, items, cell0, nitem, total, v1, s);
 }
 
 }  // namespace rfi

@@ -108,7 +108,7 @@ hipError_t launch_eig_wave_batch(int precision, int max_nbeam, const EigArgs* it
 // items of one class.
 int eig_tri_class(int n);
 hipError_t launch_eig_tri_batch(int cls, const EigArgs* items, const int64_t* cell0, int nitem,
-                                int64_t total, hipStream_t s);
+                                int64_t total, hipStream_t s, bool v1 = false);
 
 // ArPLS bandpass of every (beam, sub-interval) from the channel sums (rows
 // layout sum_x[b][cell]); z [nbeam][ncell] FP64; passes [nsub][nbeam] or NULL;

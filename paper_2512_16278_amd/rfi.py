@@ -71,7 +71,7 @@ class rfi_batch_item(C.Structure):
     _fields_ = [("blk", C.POINTER(rfi_block)), ("t0", C.c_int64), ("L", C.c_int32),
                 ("nsub", C.c_int32), ("protect_chan", C.c_void_p), ("state", C.c_void_p),
                 ("stat", C.c_void_p), ("status", C.c_void_p), ("mask", C.c_void_p),
-                ("out", C.c_void_p)]
+                ("out", C.c_void_p), ("v1", C.c_void_p), ("beam_mask", C.c_void_p)]
 
 
 class rfi_tune_entry(C.Structure):
@@ -96,7 +96,8 @@ def tune_table_dict(t: rfi_tune_table) -> list:
 
 class rfi_batch_params(C.Structure):
     _fields_ = [("eig_precision", C.c_int32), ("max_sweeps", C.c_int32), ("max_iter", C.c_int32),
-                ("pad", C.c_int32), ("kappa", C.c_double), ("tune", C.POINTER(rfi_tune_table))]
+                ("pad", C.c_int32), ("kappa", C.c_double), ("tune", C.POINTER(rfi_tune_table)),
+                ("kappa_v", C.c_double)]
 
 
 class rfi_session_config(C.Structure):
@@ -424,7 +425,7 @@ class Batch:
     device tensors; the ctypes structures are kept alive here."""
 
     def __init__(self, items, eig_precision=32, max_sweeps=12, max_iter=50, kappa=3.0,
-                 tune: "rfi_tune_table | None" = None):
+                 tune: "rfi_tune_table | None" = None, kappa_v=1.0):
         self._blocks = [it["blk"] for it in items]
         n = len(items)
         self.n = n
@@ -441,9 +442,12 @@ class Batch:
             a.status = _ptr(it["status"])
             a.mask = _ptr(it["mask"])
             a.out = _ptr(it.get("out"))
+            a.v1 = _ptr(it.get("v1"))
+            a.beam_mask = _ptr(it.get("beam_mask"))
         self.tune_table = tune
         self.p = rfi_batch_params(int(eig_precision), int(max_sweeps), int(max_iter), 0,
-                                  float(kappa), C.pointer(tune) if tune is not None else None)
+                                  float(kappa), C.pointer(tune) if tune is not None else None,
+                                  float(kappa_v))
 
     def workspace_size(self):
         return int(lib().rfi_batch_workspace_size(self.n, self.arr, C.byref(self.p)))

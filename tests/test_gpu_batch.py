@@ -123,6 +123,64 @@ def test_batch_equals_single_blocks_and_oracle(dev):
         assert np.array_equal(it["mask"].cpu().numpy().astype(bool), res.mask), b["nb"]
 
 
+def test_batch_beam_stage(dev):
+    """Per-beam outputs in a batch (Sec. 3.3 last paragraph): items with v1
+    and a beam mask (per-lane and tridiagonal solver classes, a preserved-
+    channel item), items without; each item's v1 and beam mask equal those
+    of rfi_process_block for that block alone with the same outputs, bit for
+    bit, and so do stat, status and mask; a beam mask without v1 is refused.
+    The graph of the batch reproduces them."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    blocks = _make(dev)
+    items = _batch_items(blocks, dev)
+    for b, it in zip(blocks, items):
+        b["state"] = None
+        it["state"] = None
+    want = [0, 1, 2, 3, 4]                       # 7, 19, 36, 72 beams and a preserved-channel item
+    for i in want:
+        b = blocks[i]
+        n = b["nsub"] * b["nc"]
+        items[i]["v1"] = torch.full((b["nb"], n), -9.0, dtype=torch.float32, device=dev)
+        items[i]["beam_mask"] = torch.full((b["nb"], n), 7, dtype=torch.uint8, device=dev)
+    bt = rfi.Batch(items, kappa_v=1.0)
+    ws = torch.empty(bt.workspace_size(), dtype=torch.uint8, device=dev)
+    say("batch: beam stage")
+    bt.run(ws)
+    torch.cuda.synchronize()
+    got = {i: (items[i]["v1"].cpu().numpy(), items[i]["beam_mask"].cpu().numpy()) for i in want}
+    for i in want:
+        b = blocks[i]
+        n = b["nsub"] * b["nc"]
+        stat, status, mask, out = _outputs(b["nb"], b["nc"], b["nsub"], dev)
+        v1 = torch.empty((b["nb"], n), dtype=torch.float32, device=dev)
+        bm = torch.empty((b["nb"], n), dtype=torch.uint8, device=dev)
+        p = rfi.process_params(b["L"], b["nsub"], t0=b["t0"], kappa_v=1.0, beam_mask=bm)
+        pws = torch.empty(rfi.rfi_process_workspace_size(b["nb"], b["nc"], p), dtype=torch.uint8,
+                          device=dev)
+        rfi.rfi_process_block(b["blk"], p, stat, status, mask, pws,
+                              protect_chan=b["protect_chan"], v1=v1, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[i][0], v1.cpu().numpy()), b["nb"]
+        assert np.array_equal(got[i][1], bm.cpu().numpy()), b["nb"]
+        assert np.array_equal(items[i]["mask"].cpu().numpy(), mask.cpu().numpy())
+        assert set(np.unique(got[i][1])) <= {0, 1}
+    # the graph of the same batch reproduces the beam outputs
+    g = bt.graph(ws)
+    for i in want:
+        items[i]["beam_mask"].fill_(5)
+    g.launch()
+    torch.cuda.synchronize()
+    for i in want:
+        assert np.array_equal(items[i]["beam_mask"].cpu().numpy(), got[i][1])
+    g.close()
+    items[0]["v1"] = None                        # a beam mask without v1
+    bad = rfi.Batch(items, kappa_v=1.0)
+    assert bad.workspace_size() == 0
+    with pytest.raises(rfi.RfiError):
+        bad.run(ws)
+
+
 def test_batch_graph_replays(dev):
     import torch
     from paper_2512_16278_amd import rfi
