@@ -371,7 +371,29 @@ def batch_bench(dev, nblocks=24, seed=11):
     tg = tb.graph(tws)
     t_tg = timed(lambda: tg.launch())
     tg.close()
+    # per beam-count class: its blocks alone as one batch; the bound that binds
+    # it: HBM (its bytes at 8 TB/s) or, for the FP64 tridiagonal solver above
+    # 20 beams, the FP64 vector issue of the reduction ((4/3) n^3 flop per cell
+    # at 78.6 TFLOP/s, the floor a perfect kernel would need)
+    classes = []
+    for nbk in sorted(per_class):
+        sub = [it for it in items if it["blk"].nbeam == nbk]
+        cb = rfi.Batch(sub)
+        cws = bws if cb.workspace_size() <= bws.numel() else torch.empty(
+            cb.workspace_size(), dtype=torch.uint8, device=dev)
+        tc = timed(lambda: cb.run(cws))
+        cells = sum(it["nsub"] * it["blk"].nchan for it in sub)
+        hbm_ms = per_class[nbk] / 8e12 * 1e3
+        fp64_ms = cells * (4.0 / 3.0) * nbk ** 3 / 78.6e12 * 1e3 if nbk > 20 else 0.0
+        classes.append({"nbeam": nbk, "blocks": len(sub), "bytes_gb": round(per_class[nbk] / 1e9, 2),
+                        "cells": cells, "ms": round(tc, 3),
+                        "gbs": round(per_class[nbk] / tc / 1e6, 1),
+                        "hbm_frac": round(hbm_ms / tc, 4),
+                        "ns_per_cell": round(tc * 1e6 / cells, 2),
+                        "bound": "fp64" if fp64_ms > hbm_ms else "hbm",
+                        "bound_frac": round(max(hbm_ms, fp64_ms) / tc, 4)})
     out = {"blocks": len(items), "bytes_gb": round(nbytes / 1e9, 2),
+           "classes": classes,
            "bytes_by_nbeam_gb": {str(k): round(v / 1e9, 2) for k, v in sorted(per_class.items())},
            "separate_ms": round(t_sep, 3), "batch_ms": round(t_bat, 3), "graph_ms": round(t_gr, 3),
            "tuned_graph_ms": round(t_tg, 3),

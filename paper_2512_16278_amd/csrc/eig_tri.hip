@@ -58,11 +58,6 @@ __device__ __forceinline__ int64_t pidx(int a, int b, int n) {
   return (int64_t)a * n - (int64_t)a * (a - 1) / 2 + (b - a);
 }
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
 
 // DPP move of a double (two 32-bit halves); every source lane is valid for
 // the patterns used here, so no old value is needed.
@@ -83,6 +78,38 @@ __device__ __forceinline__ double sum8(double x) {
   x += dpp_mov<0x4E>(x);   // quad_perm [2, 3, 0, 1]
   x += dpp_mov<0x141>(x);  // row_half_mirror
   return x;
+}
+
+__device__ __forceinline__ double lane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Wavefront reductions without LDS-routed lane permutes: the 8-lane stages
+// above, then the mirror within each 16-lane row, then the four row results
+// read as scalars and combined in a fixed order (every lane gets the same
+// bits). A permute address held across the long reduction would cost
+// registers the kernel does not have.
+__device__ __forceinline__ double wave_sum(double x) {
+  x = sum8(x);
+  x += dpp_mov<0x140>(x);  // row_mirror
+  return (lane_f64(x, 0) + lane_f64(x, 16)) + (lane_f64(x, 32) + lane_f64(x, 48));
+}
+__device__ __forceinline__ double wave_min(double x) {
+  x = fmin(x, dpp_mov<0xB1>(x));
+  x = fmin(x, dpp_mov<0x4E>(x));
+  x = fmin(x, dpp_mov<0x141>(x));
+  x = fmin(x, dpp_mov<0x140>(x));
+  return fmin(fmin(lane_f64(x, 0), lane_f64(x, 16)), fmin(lane_f64(x, 32), lane_f64(x, 48)));
+}
+__device__ __forceinline__ double wave_max(double x) {
+  x = fmax(x, dpp_mov<0xB1>(x));
+  x = fmax(x, dpp_mov<0x4E>(x));
+  x = fmax(x, dpp_mov<0x141>(x));
+  x = fmax(x, dpp_mov<0x140>(x));
+  return fmax(fmax(lane_f64(x, 0), lane_f64(x, 16)), fmax(lane_f64(x, 32), lane_f64(x, 48)));
 }
 
 // Reciprocal of q to about full FP64 precision: the hardware estimate and one
@@ -213,6 +240,10 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
   using ST = std::conditional_t<W, int64_t, int32_t>;
   __shared__ double X[NN], P[NN], alpha[NN], offd[NN], tau[NN], dinv[NN], z[NN];
   __shared__ double2 ae[NN];
+  // values needed only at the end, kept in LDS instead of registers through
+  // the reduction (registers are what bounds this kernel's occupancy)
+  __shared__ double s_frob2;
+  __shared__ int s_degen;
   __shared__ ST S[NN], SP[NN * (NN + 1) / 2];
   extern __shared__ __attribute__((aligned(16))) double vst[];
   int64_t cell = xcd_order(blockIdx.x, gridDim.x);
@@ -240,20 +271,42 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
 
   // correlation matrix in FP64 and ||C||_F^2 (the cell's sums first go to
   // LDS, one pair per lane)
+  // The loads of kLd rows per lane are issued before any is stored (indices
+  // clamped into the record, so every load is unconditional): one memory
+  // round trip per kLd x 64 sums instead of one per 64.
   const int np = n * (n + 1) / 2;
+  constexpr int kLd = 16;
+  auto stage = [&](auto load) {
+    for (int q0 = lane; q0 < n + np; q0 += 64 * kLd) {
+      decltype(load(0)) v[kLd];
+#pragma unroll
+      for (int u = 0; u < kLd; ++u) {
+        const int q = q0 + 64 * u;
+        v[u] = load(q < n + np ? q : n + np - 1);
+      }
+#pragma unroll
+      for (int u = 0; u < kLd; ++u) {
+        const int q = q0 + 64 * u;
+        if (q < n) S[q] = v[u];
+        else if (q < n + np) SP[q - n] = v[u];
+      }
+    }
+  };
   if constexpr (W) {
     // one contiguous int64 record per cell
     const int64_t* rec = (const int64_t*)g.sum_x + cell * (int64_t)(n + np);
-    for (int q = lane; q < np; q += 64) SP[q] = rec[n + q];
-    for (int a = lane; a < n; a += 64) S[a] = rec[a];
+    stage([&](int q) { return rec[q]; });
   } else if (g.layout) {
     // one contiguous record per cell: coalesced
     const int32_t* rec = g.sum_x + cell * (int64_t)(n + np);
-    for (int q = lane; q < np; q += 64) SP[q] = rec[n + q];
-    for (int a = lane; a < n; a += 64) S[a] = rec[a];
+    stage([&](int q) { return rec[q]; });
   } else {
-    for (int q = lane; q < np; q += 64) SP[q] = g.sum_xy[(int64_t)q * ncell + cell];
-    for (int a = lane; a < n; a += 64) S[a] = g.sum_x[a * ncell + cell];
+    // rows layout: row q of the record is sum_x[q] (q < n) or sum_xy[q - n]
+    stage([&](int q) {
+      const int32_t* row = q < n ? g.sum_x + (int64_t)q * ncell
+                                 : g.sum_xy + (int64_t)(q - n) * ncell;
+      return row[cell];
+    });
   }
   __syncthreads();
   int dead = 0;
@@ -297,8 +350,14 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
       A[ii][jj] = val;
     });
   });
-  const double frob2 = NC ? wave_sum(offsq) : (double)n + 2.0 * wave_sum(offsq);
-  if constexpr (NC) degenerate = !(frob2 > 0.0);
+  {
+    const double frob2 = NC ? wave_sum(offsq) : (double)n + 2.0 * wave_sum(offsq);
+    if constexpr (NC) degenerate = !(frob2 > 0.0);
+    if (lane == 0) {
+      s_frob2 = frob2;
+      s_degen = degenerate;
+    }
+  }
 
   // Householder reduction: steps k = 0 .. n - 2 (the last one only records
   // the final sub-diagonal entry)
@@ -407,12 +466,9 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
     }
     lb = fmax(lb, m);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    glo = fmin(glo, __shfl_xor(glo, o));
-    ghi = fmax(ghi, __shfl_xor(ghi, o));
-    lb = fmax(lb, __shfl_xor(lb, o));
-  }
+  glo = wave_min(glo);
+  ghi = wave_max(ghi);
+  lb = wave_max(lb);
   const double span = fmax(ghi - glo, 1e-300);
   glo -= 1e-12 * span;
   ghi += 1e-12 * span;
@@ -452,6 +508,8 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
   const double lam1 = 0.5 * (lo + hi);
 
   if (lane == 0) {
+    const double frob2 = s_frob2;
+    const int degenerate = s_degen;
     g.stat[cell] = (NC && degenerate) ? 0.0 : lam1 * lam1 / frob2;
     g.status[cell] = degenerate ? RFI_CELL_DEGENERATE : 0;
   }
