@@ -386,6 +386,11 @@ typedef struct {
   uint8_t* beam_mask;    /* NULL, or a device [nbeam][ncell] output: the per-beam mask of
                             the eigenvector stage (Sec. 3.3 last paragraph) on this call's
                             mask and v1, exactly as rfi_eigvec_flag; then v1 must be given */
+  int32_t scopes;        /* clip scopes as rfi_flag_scoped (RFI_SCOPE_* bits); 0 = the global
+                            clip */
+  int32_t fit;           /* RFI_FIT_MOMENTS (0) or RFI_FIT_HISTOGRAM; with scopes or the
+                            histogram fit the clip is rfi_flag_scoped's (no pooled state:
+                            state must be NULL) and out gets the global scope's summary */
 } rfi_process_params;
 
 size_t rfi_process_workspace_size(int32_t nbeam, int32_t nchan,

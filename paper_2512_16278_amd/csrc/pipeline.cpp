@@ -211,6 +211,14 @@ rfi_status rfi_process_block(const rfi_block* blk, const rfi_process_params* p,
     return fail(RFI_E_INVALID, "%s: the per-beam mask needs the v1 output", who);
   if (p->beam_mask && !(p->kappa_v >= 0.0))
     return fail(RFI_E_INVALID, "%s: kappa_v must be >= 0", who);
+  const bool scoped = p->scopes != 0 || p->fit != 0;
+  if (p->scopes < 0 || p->scopes > 7)
+    return fail(RFI_E_INVALID, "%s: scopes %d not in 0..7", who, p->scopes);
+  if (p->fit != RFI_FIT_MOMENTS && p->fit != RFI_FIT_HISTOGRAM)
+    return fail(RFI_E_INVALID, "%s: unknown fit %d", who, p->fit);
+  if (scoped && state)
+    return fail(RFI_E_INVALID, "%s: the pooled stream state needs the global moment clip "
+                "(scopes 0, fit 0)", who);
   if (!workspace) return fail(RFI_E_INVALID, "%s: workspace is NULL", who);
   if ((uintptr_t)workspace % 256 != 0)
     return fail(RFI_E_INVALID, "%s: workspace not 256-byte aligned", who);
@@ -228,7 +236,9 @@ rfi_status rfi_process_block(const rfi_block* blk, const rfi_process_params* p,
   if (e != hipSuccess) return rfi::check_hip(e, "rfi_process_block: sums / eigen launch");
   const rfi::ClipJob cj = rfi::make_clip_job(pl.nsub, pl.nchan, stat, status, protect_chan,
                                              pl.kappa, pl.max_iter, state, mask, out, workspace);
-  e = rfi::launch_clip(cj, s);
+  e = scoped ? rfi::launch_clip_scoped(cj, p->scopes ? p->scopes : RFI_SCOPE_GLOBAL, p->fit,
+                                       nullptr, nullptr, s)
+             : rfi::launch_clip(cj, s);
   if (e != hipSuccess) return rfi::check_hip(e, "rfi_process_block: clip launch");
   // the per-beam stage's partial sums reuse the clip's workspace (the clip
   // has run by then: same stream), which is always larger

@@ -64,7 +64,8 @@ class rfi_stream_state(C.Structure):
 class rfi_process_params(C.Structure):
     _fields_ = [("t0", C.c_int64), ("L", C.c_int32), ("nsub", C.c_int32), ("group", C.c_int32),
                 ("eig_precision", C.c_int32), ("max_sweeps", C.c_int32), ("max_iter", C.c_int32),
-                ("kappa", C.c_double), ("kappa_v", C.c_double), ("beam_mask", C.c_void_p)]
+                ("kappa", C.c_double), ("kappa_v", C.c_double), ("beam_mask", C.c_void_p),
+                ("scopes", C.c_int32), ("fit", C.c_int32)]
 
 
 class rfi_batch_item(C.Structure):
@@ -381,11 +382,14 @@ def rfi_clip_fit(N, Q1, Q2, mu, sigma, thr, kappa=3.0, stream=None):
 
 
 def process_params(L, nsub, t0=0, group=0, eig_precision=32, max_sweeps=12, max_iter=50,
-                   kappa=3.0, kappa_v=1.0, beam_mask=None) -> rfi_process_params:
-    """beam_mask: a device uint8 tensor [nbeam, ncell] to run the per-beam stage into."""
+                   kappa=3.0, kappa_v=1.0, beam_mask=None, scopes=0,
+                   fit=RFI_FIT_MOMENTS) -> rfi_process_params:
+    """beam_mask: a device uint8 tensor [nbeam, ncell] to run the per-beam stage into;
+    scopes / fit: the clip of rfi_flag_scoped instead of the global moment clip."""
     return rfi_process_params(int(t0), int(L), int(nsub), int(group), int(eig_precision),
                               int(max_sweeps), int(max_iter), float(kappa), float(kappa_v),
-                              None if beam_mask is None else beam_mask.data_ptr())
+                              None if beam_mask is None else beam_mask.data_ptr(), int(scopes),
+                              int(fit))
 
 
 def rfi_process_workspace_size(nbeam, nchan, p: rfi_process_params):

@@ -185,6 +185,41 @@ def test_process_block_beam_mask(dev):
         rfi.rfi_process_block(blk, p, stat, status, mask, ws, v1=v1)
 
 
+@pytest.mark.parametrize("scopes,fit", [(7, 0), (7, 1), (2, 1), (0, 1), (4, 0)])
+def test_process_block_scoped_clip(dev, scopes, fit):
+    """The whole-block call with the clip scopes / histogram fit of Sec. 3.3
+    (rfi_flag_scoped's clip on the call's own statistic): mask and global
+    summary bit-equal to rfi_flag_scoped run after the call; stat and status
+    unchanged by the choice; a pooled state is refused with scopes."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    nb, nc, L, nsub = 19, 96, 256, 9
+    x = _data(nb, nc, nsub * L, seed=17)
+    buf = upload(x, dev)
+    blk = rfi.make_block(buf, nc)
+    p = rfi.process_params(L, nsub, scopes=scopes, fit=fit)
+    ws = torch.empty(rfi.rfi_process_workspace_size(nb, nc, p), dtype=torch.uint8, device=dev)
+    stat, status, _, _ = eig_buffers(nb, nsub * nc, dev, with_vectors=False)
+    mask = torch.full((nsub * nc,), 7, dtype=torch.uint8, device=dev)
+    out = torch.zeros(48, dtype=torch.uint8, device=dev)
+    say("process_block scoped", scopes, fit)
+    rfi.rfi_process_block(blk, p, stat, status, mask, ws, out=out)
+    m2 = torch.full_like(mask, 9)
+    out2 = torch.zeros_like(out)
+    rfi.rfi_flag_scoped(nsub, nc, stat, status, m2, scopes=scopes or rfi.RFI_SCOPE_GLOBAL, fit=fit,
+                        out=out2)
+    torch.cuda.synchronize()
+    assert np.array_equal(mask.cpu().numpy(), m2.cpu().numpy())
+    if (scopes or 1) & 1:
+        assert np.array_equal(out.cpu().numpy(), out2.cpu().numpy())
+    a = _separate(blk, nb, nc, 0, L, nsub, dev, 32)
+    assert np.array_equal(a[0].cpu().numpy(), stat.cpu().numpy())
+    assert np.array_equal(a[1].cpu().numpy(), status.cpu().numpy())
+    st = _state(dev)
+    with pytest.raises(rfi.RfiError):
+        rfi.rfi_process_block(blk, p, stat, status, mask, ws, state=st)
+
+
 def test_process_block_empty_and_errors(dev):
     import torch
     from paper_2512_16278_amd import rfi
