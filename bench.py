@@ -295,7 +295,7 @@ def batch_bench(dev, nblocks=24, seed=11):
     pools = {}
     for F in MIX_NCHAN:
         spec = synth.mixed_spec(seed + F, max(MIX_NBEAM), F, 512, 2.1)
-        t = torch.empty((spec.nbeam, spec.nsamp, F), dtype=torch.uint8, device=dev)
+        _, t = rfi.alloc_beams(spec.nbeam, spec.nsamp, F, dev)   # per-beam views
         ds = rfi.DeviceSynth(spec, dev)
         for b in range(spec.nbeam):
             ds.fill(t[b], b)
@@ -308,9 +308,9 @@ def batch_bench(dev, nblocks=24, seed=11):
         nsub = nsamp // L
         if nsub == 0:
             continue
-        start = int(rng.integers(0, pools[F].shape[1] - nsamp))
+        start = int(rng.integers(0, pools[F][0].shape[0] - nsamp))
         pool = pools[F]
-        blk = rfi.make_block([pool[b, start:start + nsamp] for b in range(nb)], F)
+        blk = rfi.make_block([pool[b][start:start + nsamp] for b in range(nb)], F)
         n = nsub * F
         it = dict(blk=blk, L=L, nsub=nsub,
                   stat=torch.empty(n, dtype=torch.float64, device=dev),
@@ -424,7 +424,7 @@ def serve_bench(dev, rates, nblocks, nstreams=8, seed=7, slots=8, budget=64 << 3
     pools = {}
     for F in MIX_NCHAN:
         spec = synth.mixed_spec(seed + F, max(MIX_NBEAM), F, 512, pool_s)
-        t = torch.empty((spec.nbeam, spec.nsamp, F), dtype=torch.uint8, device=dev)
+        _, t = rfi.alloc_beams(spec.nbeam, spec.nsamp, F, dev)   # per-beam views
         ds = rfi.DeviceSynth(spec, dev)
         for b in range(spec.nbeam):
             ds.fill(t[b], b)
@@ -432,7 +432,7 @@ def serve_bench(dev, rates, nblocks, nstreams=8, seed=7, slots=8, budget=64 << 3
     torch.cuda.synchronize()
     shapes = [(int(rng.choice(MIX_NBEAM)), int(rng.choice(MIX_NCHAN)), int(rng.choice(MIX_L)))
               for _ in range(nstreams)]
-    log(f"serving: {nstreams} streams {shapes}; pools {sum(p.numel() for p in pools.values()) / 1e9:.1f} GB")
+    log(f"serving: {nstreams} streams {shapes}; pools {sum(t.numel() for p in pools.values() for t in p) / 1e9:.1f} GB")
 
     def trace(rate):
         r = np.random.default_rng(seed + int(rate))
@@ -442,7 +442,7 @@ def serve_bench(dev, rates, nblocks, nstreams=8, seed=7, slots=8, budget=64 << 3
             si = int(r.integers(nstreams))
             nb, F, L = shapes[si]
             nsamp = int(r.uniform(0.1, 2.0) / synth.TSAMP)
-            start = int(r.integers(0, pools[F].shape[1] - nsamp))
+            start = int(r.integers(0, pools[F][0].shape[0] - nsamp))
             out.append((float(ta), si, start, nsamp))
         return out
 
@@ -453,7 +453,7 @@ def serve_bench(dev, rates, nblocks, nstreams=8, seed=7, slots=8, budget=64 << 3
             for ta, si, start, nsamp in tr:
                 nb, F, L = shapes[si]
                 pool = pools[F]
-                blks.append(rfi.make_block([pool[b, start:start + nsamp] for b in range(nb)], F))
+                blks.append(rfi.make_block([pool[b][start:start + nsamp] for b in range(nb)], F))
             tickets = []
             t0 = time.perf_counter()
             for (ta, si, start, nsamp), blk in zip(tr, blks):
@@ -514,6 +514,8 @@ def main():
                     help="skip the timings of the per-beam stage, scopes, bandpass and long "
                          "sub-interval calls")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch comparison")
+    ap.add_argument("--no-placement", action="store_true",
+                    help="skip the sums call on the aligned beam placement")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving loop and print its JSON")
     ap.add_argument("--batch-only", action="store_true",
@@ -548,10 +550,12 @@ def main():
     stride = (nc + 15) // 16 * 16
     log(f"workload: {nb} beams x {nc} ch x {ns} samples, L={L}, {nsub} sub-ints, "
         f"{spec.nbytes() / 1e9:.2f} GB")
-    data = torch.empty((nb, ns, stride), dtype=torch.uint8, device=dev)
+    # beams placed by rfi_beam_offsets (beam b 64 b bytes past a 4 KB
+    # boundary); the aligned placement is timed beside it below
+    data, beams = rfi.alloc_beams(nb, ns, stride, dev)
     ds = rfi.DeviceSynth(spec, dev)
     for b in range(nb):
-        ds.fill(data[b], b)
+        ds.fill(beams[b], b)
     torch.cuda.synchronize()
     log("input generated on the GPU")
 
@@ -576,7 +580,7 @@ def main():
     read_gbs = data.numel() / (float(np.median(rd)) / 1e3) / 1e9
     log(f"streaming read of {data.numel() / 1e9:.2f} GB: {read_gbs:.0f} GB/s")
 
-    blk = rfi.make_block(data, nc)
+    blk = rfi.make_block(beams, nc)
     sx = torch.empty((nb, ncell), dtype=torch.int32, device=dev)
     sxy = torch.empty((npair, ncell), dtype=torch.int32, device=dev)
     cnt = torch.empty(nsub, dtype=torch.int32, device=dev)
@@ -726,6 +730,29 @@ def main():
             ts.append(a.elapsed_time(b))
         return float(np.median(ts[1:]))
 
+    # the same block with every beam at the same offset modulo 4 KB (one
+    # [nbeam][nsamp][row] tensor): the sums call alone, median of 5
+    layout = None
+    if not (args.profile_run or args.no_placement):
+        alias = torch.empty((nb, ns, stride), dtype=torch.uint8, device=dev)
+        for b in range(nb):
+            ds.fill(alias[b], b)
+        ablk = rfi.make_block(alias, nc)
+        sx2, sxy2, cnt2 = torch.empty_like(sx), torch.empty_like(sxy), torch.empty_like(cnt)
+        ms_alias = ev_time(lambda: rfi.rfi_ccm_accumulate(ablk, 0, L, nsub, sx2, sxy2, cnt2,
+                                                          variant=variant), reps=5)
+        ms_stag = ev_time(lambda: rfi.rfi_ccm_accumulate(blk, 0, L, nsub, sx2, sxy2, cnt2,
+                                                         variant=variant), reps=5)
+        same = bool(torch.equal(sx2, sx) and torch.equal(sxy2, sxy))
+        layout = {"placement": "beam b at 64 (b mod 64) bytes past a 4 KB boundary "
+                               "(rfi_beam_offsets)",
+                  "ccm_ms_staggered": round(ms_stag, 4), "ccm_ms_aligned": round(ms_alias, 4),
+                  "aligned_note": "all beams at the same offset modulo 4 KB",
+                  "sums_equal": same}
+        del alias, sx2, sxy2, cnt2
+        torch.cuda.empty_cache()
+        log(f"placement: {layout}")
+
     widened = None
     if not args.no_widened:
         widened = widened_rows(dev, spec, data, blk, nsub, sx, sxy, cnt, stat, status, mask,
@@ -742,7 +769,7 @@ def main():
     serving = None
     batch = None
     if args.serve_rates or not args.no_batch:
-        del data
+        del data, beams
         torch.cuda.empty_cache()
     if not args.no_batch:
         batch = batch_bench(dev)
@@ -786,6 +813,7 @@ def main():
         "frac_of_measured_read": round(value / read_gbs, 4),
         "flagged_cells": int(flags["nflag"]), "clip_iterations": int(flags["iterations"]),
         "roofline": roof,
+        "placement": layout,
         "widened": widened,
         "precision_split": psplit,
         "batch": batch,

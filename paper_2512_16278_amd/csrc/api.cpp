@@ -240,6 +240,24 @@ rfi_status rfi_eig_noncentred(int32_t nbeam, int32_t nsub, int32_t nchan, const 
   return check_hip(rfi::launch_eig_tri_nc(a, z, (hipStream_t)stream), "rfi_eig_noncentred launch");
 }
 
+rfi_status rfi_beam_offsets(int32_t nbeam, int64_t nsamp, int64_t row_stride, int64_t* offsets,
+                            int64_t* total) {
+  rfi::clear_error();
+  if (nbeam < 1 || nbeam > RFI_MAX_BEAMS || nsamp < 0 || row_stride < 1 || row_stride % 16 ||
+      !offsets || !total)
+    return fail(RFI_E_INVALID, "rfi_beam_offsets: bad arguments");
+  constexpr int64_t kPage = 4096, kStep = 64;
+  const int64_t lim = (int64_t)1 << 62;
+  if (nsamp > lim / row_stride) return fail(RFI_E_OVERFLOW, "rfi_beam_offsets: beam too large");
+  const int64_t bytes = nsamp * row_stride;
+  // a beam plus the largest stagger (63 steps) fits in its pitch
+  const int64_t pitch = (bytes + kPage - 1) / kPage * kPage + kPage;
+  if (pitch > lim / nbeam) return fail(RFI_E_OVERFLOW, "rfi_beam_offsets: block too large");
+  for (int b = 0; b < nbeam; ++b) offsets[b] = b * pitch + kStep * (b % 64);
+  *total = offsets[nbeam - 1] + bytes;
+  return RFI_OK;
+}
+
 size_t rfi_flag_workspace_size(int32_t nsub, int32_t nchan) {
   if (nsub < 0 || nchan < 1) return 0;
   return rfi::clip_workspace_size((int64_t)nsub * nchan);

@@ -158,6 +158,7 @@ def lib():
                                       vp, vp, vp, vp, vp]
         L.rfi_flag.argtypes = [i32, i32, vp, vp, vp, dbl, i32, vp, vp, vp, vp, vp]
         L.rfi_flag_workspace_size.argtypes = [i32, i32]
+        L.rfi_beam_offsets.argtypes = [i32, i64, i64, vp, vp]
         L.rfi_flag_workspace_size.restype = C.c_size_t
         L.rfi_clip_fit.argtypes = [i32, vp, vp, vp, dbl, vp, vp, vp, vp]
         L.rfi_flag_scoped.argtypes = [i32, i32, vp, vp, vp, dbl, i32, i32, i32, vp, vp, vp, vp, vp,
@@ -253,6 +254,27 @@ def _stream(stream):
         return C.c_void_p(stream)
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def rfi_beam_offsets(nbeam, nsamp, row_stride):
+    """(offsets, total): rfi_beam_offsets' staggered beam placement."""
+    offs = (C.c_int64 * int(nbeam))()
+    tot = C.c_int64()
+    _check(lib().rfi_beam_offsets(int(nbeam), int(nsamp), int(row_stride), offs, C.byref(tot)))
+    return [int(o) for o in offs], int(tot.value)
+
+
+def alloc_beams(nbeam, nsamp, row_stride, device="cuda"):
+    """(storage, beams): one device allocation holding nbeam uint8
+    [nsamp, row_stride] beams placed by rfi_beam_offsets (from a 4 KB-aligned
+    base inside the storage); beams is the list of per-beam views."""
+    import torch
+    offs, tot = rfi_beam_offsets(nbeam, nsamp, row_stride)
+    raw = torch.empty(tot + 4096, dtype=torch.uint8, device=device)
+    pad = (-raw.data_ptr()) % 4096
+    n = int(nsamp) * int(row_stride)
+    beams = [raw[pad + o: pad + o + n].view(int(nsamp), int(row_stride)) for o in offs]
+    return raw, beams
 
 
 def make_block(data, nchan=None) -> rfi_block:

@@ -49,6 +49,29 @@ def run_ccm(x, L, nsub, dev, variant=0, t0=0, stride=None, nchan=None):
     return sx.cpu().numpy(), sxy.cpu().numpy(), cnt.cpu().numpy(), (buf, blk, sx, sxy, cnt)
 
 
+def test_ccm_staggered_placement(dev, tiny):
+    """Beams placed by rfi_beam_offsets give the oracle's sums bit for bit
+    (placement is a speed matter only)."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    spec, x = tiny
+    nb, nt, nc = x.shape
+    L, nsub = spec.L, spec.nsamp // spec.L
+    say("ccm staggered placement", nb, nt, nc)
+    raw, beams = rfi.alloc_beams(nb, nt, 64, dev)
+    for b in range(nb):
+        assert beams[b].data_ptr() % 4096 == 64 * b
+        beams[b][:, :nc].copy_(torch.from_numpy(np.ascontiguousarray(x[b])).to(dev))
+    blk = rfi.make_block(beams, nc)
+    sx, sxy, cnt = sums_buffers(nb, nsub, nc, dev)
+    rfi.rfi_ccm_accumulate(blk, 0, L, nsub, sx, sxy, cnt)
+    torch.cuda.synchronize()
+    S, S2 = ccm.sums_fp64(x, L, nsub)
+    rsx, rsxy = packed_oracle_sums(S, S2)
+    assert np.array_equal(sx.cpu().numpy(), rsx)
+    assert np.array_equal(sxy.cpu().numpy(), rsxy)
+
+
 @pytest.mark.parametrize("variant", [1, 2])
 def test_ccm_tiny_bit_exact(dev, tiny, variant):
     spec, x = tiny

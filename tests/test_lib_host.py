@@ -260,3 +260,26 @@ def test_session_without_device_or_with_bad_arguments():
     if not torch.cuda.is_available():
         cfg = rfi.rfi_session_config(0, 4, 0)
         assert L.rfi_session_create(C.byref(cfg), C.byref(h)) == rfi.RFI_E_DEVICE
+
+
+def test_beam_offsets_stagger():
+    """rfi_beam_offsets: beam b starts 64 (b mod 64) bytes past a 4 KB
+    boundary, 16-byte aligned, and no two beams overlap."""
+    from paper_2512_16278_amd import rfi
+    for nbeam, nsamp, stride in ((19, 203450, 4096), (72, 1000, 1024), (1, 0, 16), (79, 3, 4112)):
+        offs, tot = rfi.rfi_beam_offsets(nbeam, nsamp, stride)
+        n = nsamp * stride
+        assert len(offs) == nbeam
+        for b, o in enumerate(offs):
+            assert o % 4096 == 64 * (b % 64)
+            assert o % 16 == 0
+            assert o + n <= tot
+            if b:
+                assert offs[b - 1] + n <= o
+        assert tot == offs[-1] + n
+    L = rfi.lib()
+    o, t = (C.c_int64 * 80)(), C.c_int64()
+    for args in ((0, 10, 4096), (80, 10, 4096), (19, -1, 4096), (19, 10, 0), (19, 10, 4100)):
+        assert L.rfi_beam_offsets(*args, o, C.byref(t)) == rfi.RFI_E_INVALID
+    assert L.rfi_beam_offsets(19, 10, 4096, None, C.byref(t)) == rfi.RFI_E_INVALID
+    assert L.rfi_beam_offsets(79, 1 << 50, 4096, o, C.byref(t)) == rfi.RFI_E_OVERFLOW
