@@ -458,8 +458,9 @@ typedef struct {
  * family serves (2-15, 16-31, 32-47, 48-63, 64-79); 0 in a choice field
  * means the library default:
  *  ccm_tile        sums tile variant, 0 .. rfi_ccm_tile_variants(nbeam) - 1
- *                  (16-31 beams: 0 = 64 channels on 8 waves, 1 = 64 channels
- *                  on 16 waves, 2 = 32 channels on 8 waves; others: 0 only);
+ *                  (16-31 beams: 0 = 64 channels on 16 waves, 1 = 64
+ *                  channels on 8 waves, 2 = 32 channels on 8 waves; others:
+ *                  0 only);
  *  ccm_stages      cap of the global-to-LDS load ring depth, 2..4;
  *  ccm_group_bytes contiguous row bytes of the tiles one XCD takes in turn
  *                  (16 .. 16384; default 1024);

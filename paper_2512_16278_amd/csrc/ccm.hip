@@ -525,17 +525,21 @@ hipError_t dispatch_nst(int max_stages, Op& op) {
 template <class Op>
 hipError_t ccm_dispatch(int nbeam, int shared_cu, Op& op, const CcmTune* t = nullptr) {
   const int nb = (nbeam + 1 + 15) / 16;
-  // tile shape per block count: (CW channels, CPW channels per wave). With
-  // shared_cu the 19-beam tile is 32 channels on 8 waves of ~120 VGPRs.
+  // tile shape per block count: (CW channels, CPW channels per wave). The
+  // 16-31-beam default is 64 channels on 16 waves of 4 channels (a 3-deep
+  // ring of 48 KB chunks): on the 19-beam FAST block it beats 8 waves of 8
+  // channels (4-deep ring), variant 1, by about 3 % once the beams are
+  // staggered across the memory channels. With shared_cu the tile is 32
+  // channels on 8 waves of ~120 VGPRs.
   int cw, cpw;
   const int tile = t ? t->tile : 0;
   if (tile < 0 || tile >= ccm_tile_variants(nbeam)) return hipErrorInvalidValue;
   switch (nb) {
     case 1: cw = 64; cpw = 8; break;
     case 2:
-      if (tile == 1) { cw = 64; cpw = 4; }
+      if (tile == 1) { cw = 64; cpw = 8; }
       else if (tile == 2 || shared_cu) { cw = 32; cpw = 4; }
-      else { cw = 64; cpw = 8; }
+      else { cw = 64; cpw = 4; }
       break;
     case 3: cw = 32; cpw = 4; break;
     case 4: case 5: cw = 16; cpw = 2; break;
