@@ -283,12 +283,10 @@ def widened_rows(dev, spec, data, blk, nsub, sx, sxy, cnt, stat, status, mask, e
     return out
 
 
-def batch_bench(dev, nblocks=24, seed=11):
-    """Uneven blocks (beam counts 7/19/36/72, channels 1024/4096/8192, L
-    512/1024/4096, 0.1-2 s each) through (a) one rfi_process_block per
-    block on one stream, (b) one rfi_process_batch, (c) one replay of the
-    batch's HIP graph. Same blocks, same outputs; throughput in beam-sample
-    GB/s of the full sub-intervals."""
+def mix_items(dev, nblocks=24, seed=11):
+    """The seeded uneven mix (beam counts 7/19/36/72, channels 1024/4096/8192,
+    L 512/1024/4096, 0.1-2 s each) as views into per-channel-count pools of
+    generated beams: (items, bytes per beam count, total bytes, pools)."""
     import torch
     from paper_2512_16278_amd import rfi, synth
     rng = np.random.default_rng(seed)
@@ -319,6 +317,45 @@ def batch_bench(dev, nblocks=24, seed=11):
         items.append(it)
         nbytes += nb * F * nsub * L
         per_class[nb] = per_class.get(nb, 0) + nb * F * nsub * L
+    return items, per_class, nbytes, pools
+
+
+def batch_class_run(dev, nbeam, reps=3, nblocks=24, seed=11):
+    """The blocks of one beam count of the uneven mix as one rfi_process_batch,
+    run reps times (a short workload for counter profiles of that class)."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    items, per_class, _, pools = mix_items(dev, nblocks, seed)
+    sub = [it for it in items if it["blk"].nbeam == nbeam]
+    if not sub:
+        raise SystemExit(f"no block of {nbeam} beams in the mix")
+    cb = rfi.Batch(sub)
+    ws = torch.empty(cb.workspace_size(), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        cb.run(ws)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    cells = sum(it["nsub"] * it["blk"].nchan for it in sub)
+    del pools
+    return {"nbeam": nbeam, "blocks": len(sub), "cells": cells,
+            "bytes_gb": round(per_class[nbeam] / 1e9, 2), "ms": [round(t, 3) for t in ts],
+            "ns_per_cell": round(float(np.median(ts)) * 1e6 / cells, 2)}
+
+
+def batch_bench(dev, nblocks=24, seed=11):
+    """Uneven blocks (beam counts 7/19/36/72, channels 1024/4096/8192, L
+    512/1024/4096, 0.1-2 s each) through (a) one rfi_process_block per
+    block on one stream, (b) one rfi_process_batch, (c) one replay of the
+    batch's HIP graph. Same blocks, same outputs; throughput in beam-sample
+    GB/s of the full sub-intervals."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    items, per_class, nbytes, pools = mix_items(dev, nblocks, seed)
     stream = torch.cuda.current_stream()
     wss = []
     for it in items:
@@ -518,6 +555,9 @@ def main():
                     help="skip the sums call on the aligned beam placement")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving loop and print its JSON")
+    ap.add_argument("--batch-class", type=int, default=0,
+                    help="only run the uneven mix's blocks of this beam count as one batch "
+                         "(three runs; a short workload for counter profiles)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the uneven-batch comparison and print its JSON")
     ap.add_argument("--quick", action="store_true",
@@ -535,6 +575,9 @@ def main():
     from paper_2512_16278_amd import rfi, synth
 
     dev = torch.device("cuda:0")
+    if args.batch_class:
+        print(json.dumps({"batch_class": batch_class_run(dev, args.batch_class)}), flush=True)
+        return
     if args.batch_only:
         print(json.dumps({"batch": batch_bench(dev)}), flush=True)
         return

@@ -80,9 +80,14 @@ constexpr int kRowGroup = 48;
 // which the load takes as a scalar base and one offset register (the launch
 // checks ncell <= 2^30). A 64-bit per-lane address would hold two more
 // registers for every load in flight.
+// The pointer is taken as global memory: the batched kernels read it from
+// their item table, where the compiler cannot tell the address space, and
+// a flat load would also count against the LDS/scalar counter, so every wait
+// for a scalar load would wait for the sums in flight as well.
 __device__ __forceinline__ int32_t lane_row(const int32_t* base, int64_t row, int64_t ncell,
                                             uint32_t off4) {
-  return *(const int32_t*)((const char*)(base + row * ncell) + off4);
+  typedef const __attribute__((address_space(1))) int32_t gint32;
+  return *(gint32*)((const char*)(base + row * ncell) + off4);
 }
 
 // Entry k of the strict upper triangle of an N x N matrix in row order:
@@ -277,23 +282,73 @@ __device__ __forceinline__ int lane_sturm(const float (&dg)[N], const float (&e2
   return c;
 }
 
-// Kernel 1, alternative: Householder reduction of the FP32 correlation matrix
-// to tridiagonal form in the lane's registers (Golub & Van Loan Sec. 8.3:
-// about (4/3) n^3 flops instead of 6 n^3 per Jacobi sweep), then lambda_1 by
-// Sturm bisection on the tridiagonal (Sec. 8.4). Same outputs as the Jacobi
-// kernel: the FP32 dominant eigenvalue in stat[] (the shift of kernel 2,
-// which needs it to about 1e-5), optional sorted eigenvalues (one bisection
-// each), status bits.
+template <int N>
+__device__ __forceinline__ void ritz_fp64(const EigArgs& g, int64_t ncell, int64_t cell, int n,
+                                          int64_t cnt, float lam1, bool have_v, float (&v)[N],
+                                          float (&u)[N], uint8_t st);
+
+// Start vectors of the block inverse iteration: components with no exact
+// linear relation to any eigenvector that a correlation matrix can have
+// (all-ones is orthogonal to (1, -1) for two anticorrelated beams):
+// 0.5 + frac(0.5 + i g), g = 0.7548..., and frac(0.5 + i h) - 0.5,
+// h = 0.3819... (mixed signs); zero at padding indices.
+template <int N>
+__device__ __forceinline__ void start_vectors(int n, float (&v)[N], float (&u)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const float f = 0.5f + 0.7548776662466927f * (float)i;
+    const float h = 0.5f + 0.3819660112501051f * (float)i;
+    v[i] = i < n ? 0.5f + (f - floorf(f)) : 0.0f;
+    u[i] = i < n ? (h - floorf(h)) - 0.5f : 0.0f;
+  }
+}
+
+// v unit, u unit and orthogonal to v
+template <int N>
+__device__ __forceinline__ void orthonormalise(float (&v)[N], float (&u)[N]) {
+  float nv = 0.f;
+#pragma unroll
+  for (int i = 0; i < N; ++i) nv += v[i] * v[i];
+  const float sv = 1.0f / sqrtf(nv);
+  float vu = 0.f;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    v[i] *= sv;
+    vu += v[i] * u[i];
+  }
+  float nu = 0.f;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    u[i] -= vu * v[i];
+    nu += u[i] * u[i];
+  }
+  const float su = nu > 0.f ? 1.0f / sqrtf(nu) : 0.f;
+#pragma unroll
+  for (int i = 0; i < N; ++i) u[i] *= su;
+}
+
+// Householder + Sturm solver with its own FP64 refinement, one kernel:
+// reduction of the FP32 correlation matrix to tridiagonal form T = Q^T C Q in
+// the lane's registers (Golub & Van Loan Sec. 8.3: about (4/3) n^3 flops
+// instead of 6 n^3 per Jacobi sweep), the FP32 lambda_1 by Sturm bisection on
+// T (Sec. 8.4), optional sorted eigenvalues (one bisection each); then the
+// two-vector block inverse iteration of the refinement runs on T itself
+// (sigma I - T is tridiagonal and positive definite for sigma above lambda_1:
+// an O(n) LDL^T factor and O(n) solves), the two vectors go back to C's basis
+// through the stored reflectors, Q y = H_0 H_1 ... y, and the FP64 Ritz pass
+// over the exact sums gives lambda_1 and the statistic (ritz_fp64).
 template <int N>
 __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
   const int n = g.nbeam;
   const int64_t cnt = g.count[cell / g.nchan];
   if (cnt < 2 || cnt > RFI_MAX_COUNT) {
-    g.stat[cell] = 1.0;
+    g.stat[cell] = 0.0;
     g.status[cell] = RFI_CELL_BAD_COUNT | RFI_CELL_DEGENERATE;
     if (g.eigvals)
       for (int i = 0; i < n; ++i) g.eigvals[i * g.out_stride + cell] = 0.f;
+    if (g.v1)
+      for (int i = 0; i < n; ++i) g.v1[i * g.out_stride + cell] = 0.f;
     return;
   }
   float A[Sym<N>::NP];
@@ -302,7 +357,11 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
 
   // The tridiagonal T stays in the matrix's own registers: its diagonal in
   // A(i, i) (final once step i - 1 is done) and its squared couplings in
-  // A(i, i - 1) (the reduced column's head, dead after its step).
+  // A(i, i - 1) (the reduced column's head, dead after its step). The
+  // reflector of step k (v_{k+1} = 1 implied) is kept below it, in
+  // A(i, k), i > k + 1, and its beta in tau[k]; off[k] is the signed coupling
+  // T(k + 1, k).
+  float tau[N], off[N];
   static_for<0, N - 2>([&](auto K) {
     constexpr int k = RFI_CI(K);
     // reflector of (x0, x_{k+2}, ...) onto (mu, 0, ...): v0 = x0 - mu without
@@ -324,8 +383,11 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
     static_for<k + 1, N>([&](auto I) {
       constexpr int i = RFI_CI(I);
       v[i] = i == k + 1 ? 1.0f : A[Sym<N>::idx(i, k)] * iv0;
+      if constexpr (i > k + 1) A[Sym<N>::idx(i, k)] = v[i];
     });
     A[Sym<N>::idx(k + 1, k)] = mu2;
+    tau[k] = beta;
+    off[k] = refl ? mu : x0;
     // p = beta A22 v, K = beta p.v / 2, w = p - K v
     float pv = 0.f;
     static_for<k + 1, N>([&](auto I) {
@@ -355,6 +417,7 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
   });
   {
     const float x = A[Sym<N>::idx(N - 1, N - 2)];
+    off[N - 2] = x;
     A[Sym<N>::idx(N - 1, N - 2)] = x * x;
   }
   float dg[N], e2[N];
@@ -386,8 +449,7 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
     if (lane_sturm<N>(dg, e2, n, mid) >= n) hi = mid; else lo = mid;
   }
   const float lam1 = 0.5f * (lo + hi);
-  g.stat[cell] = (double)lam1;
-  g.status[cell] = degenerate ? RFI_CELL_DEGENERATE : 0;
+  uint8_t st = degenerate ? RFI_CELL_DEGENERATE : 0;
 
   if (g.eigvals) {
     // eigenvalue j (ascending) by bisection, then |lambda| descending
@@ -418,10 +480,81 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
     for (int i = 0; i < N; ++i)
       if (i < n) g.eigvals[i * g.out_stride + cell] = ev[i];
   }
+
+  // Two vectors of block inverse iteration on T (the same shift, start vectors
+  // and three iterations as the Jacobi path's refinement on C): the subspace
+  // converges to that of lambda_1 and lambda_2 at the rate
+  // (sigma - lambda_2) / (sigma - lambda_3).
+  float v[N], u[N];
+  bool have_v = false;
+  if (g.refine || g.v1) {
+    const float sigma = lam1 * (1.0f + 2e-5f) + 1e-6f;
+    // B = sigma I - T = L D L^T: pivots d_i (kept as 1 / d_i) and multipliers
+    // l_i = B(i, i - 1) / d_{i-1} = -off_{i-1} / d_{i-1}; indices >= n (the
+    // decoupled padding) get l = 1 / d = 0, so their components stay zero
+    float l[N], id[N];
+    bool ok = true;
+    static_for<0, N>([&](auto I) {
+      constexpr int i = RFI_CI(I);
+      float d = sigma - dg[i];
+      float li = 0.f;
+      if constexpr (i > 0) {
+        li = i < n ? -off[i - 1] * id[i - 1] : 0.f;
+        d = fmaf(li, off[i - 1], d);
+      }
+      ok = ok && (i >= n || d > 0.f);
+      l[i] = li;
+      id[i] = i < n ? 1.0f / fmaxf(d, 1e-30f) : 0.f;
+    });
+    start_vectors<N>(n, v, u);
+    for (int it = 0; it < 3; ++it) {
+      // L y = x (forward), y / d, then L^T z = y (backward), in place
+      static_for<1, N>([&](auto I) {
+        constexpr int i = RFI_CI(I);
+        v[i] = fmaf(-l[i], v[i - 1], v[i]);
+        u[i] = fmaf(-l[i], u[i - 1], u[i]);
+      });
+      static_for<0, N>([&](auto I) {
+        constexpr int i = RFI_CI(I);
+        v[i] *= id[i];
+        u[i] *= id[i];
+      });
+      static_for<1, N>([&](auto II) {
+        constexpr int i = N - 1 - RFI_CI(II);
+        v[i] = fmaf(-l[i + 1], v[i + 1], v[i]);
+        u[i] = fmaf(-l[i + 1], u[i + 1], u[i]);
+      });
+      orthonormalise<N>(v, u);
+    }
+    // back to C's basis: x <- H_k x for k = N - 3 .. 0,
+    // H_k = I - tau_k w w^T, w = (0 .. 0, 1, A(k + 2, k), ...)
+    static_for<0, N - 2>([&](auto KK) {
+      constexpr int k = N - 3 - RFI_CI(KK);
+      float dv = v[k + 1], du = u[k + 1];
+      static_for<k + 2, N>([&](auto I) {
+        constexpr int i = RFI_CI(I);
+        dv = fmaf(A[Sym<N>::idx(i, k)], v[i], dv);
+        du = fmaf(A[Sym<N>::idx(i, k)], u[i], du);
+      });
+      dv *= tau[k];
+      du *= tau[k];
+      v[k + 1] -= dv;
+      u[k + 1] -= du;
+      static_for<k + 2, N>([&](auto I) {
+        constexpr int i = RFI_CI(I);
+        v[i] = fmaf(-dv, A[Sym<N>::idx(i, k)], v[i]);
+        u[i] = fmaf(-du, A[Sym<N>::idx(i, k)], u[i]);
+      });
+    });
+    have_v = ok;
+    if (!ok) st |= RFI_CELL_REFINE_FAILED;
+  }
+  ritz_fp64<N>(g, ncell, cell, n, cnt, lam1, have_v, v, u, st);
 }
 
-// Kernel 2: block inverse iteration and the FP64 Ritz value of lambda_1;
-// writes the statistic lambda_1^2 / ||C||_F^2, v1 and the remaining status bits.
+// Kernel 2 of the Jacobi path: block inverse iteration and the FP64 Ritz value
+// of lambda_1; writes the statistic lambda_1^2 / ||C||_F^2, v1 and the
+// remaining status bits.
 template <int N>
 __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
@@ -470,17 +603,7 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
         A[Sym<N>::idx(i, j)] = x * rj;
       });
     });
-    // start vectors with no exact linear relation to any eigenvector that a
-    // correlation matrix can have (all-ones is orthogonal to (1, -1) for two
-    // anticorrelated beams): components 0.5 + frac(0.5 + i g), g = 0.7548...,
-    // and frac(0.5 + i h) - 0.5, h = 0.3819... (mixed signs)
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const float f = 0.5f + 0.7548776662466927f * (float)i;
-      const float h = 0.5f + 0.3819660112501051f * (float)i;
-      v[i] = i < n ? 0.5f + (f - floorf(f)) : 0.0f;
-      u[i] = i < n ? (h - floorf(h)) - 0.5f : 0.0f;
-    }
+    start_vectors<N>(n, v, u);
     for (int it = 0; it < 3; ++it) {
       // R y = x (forward), then R^T z = y (backward), in place, for x = v, u
       static_for<0, N>([&](auto I) {
@@ -505,43 +628,45 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
         v[i] = x * A[Sym<N>::idx(i, i)];
         u[i] = y * A[Sym<N>::idx(i, i)];
       });
-      // orthonormalise: v unit, u unit and orthogonal to v
-      float nv = 0.f;
-#pragma unroll
-      for (int i = 0; i < N; ++i) nv += v[i] * v[i];
-      const float sv = 1.0f / sqrtf(nv);
-      float vu = 0.f;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        v[i] *= sv;
-        vu += v[i] * u[i];
-      }
-      float nu = 0.f;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        u[i] -= vu * v[i];
-        nu += u[i] * u[i];
-      }
-      const float su = nu > 0.f ? 1.0f / sqrtf(nu) : 0.f;
-#pragma unroll
-      for (int i = 0; i < N; ++i) u[i] *= su;
+      orthonormalise<N>(v, u);
     }
     have_v = ok;
     if (!ok) st |= RFI_CELL_REFINE_FAILED;
   }
+  ritz_fp64<N>(g, ncell, cell, n, cnt, lam1, have_v, v, u, st);
+}
 
+// The FP64 part of the refinement: ||C||_F^2 from the exact sums and the
+// largest Ritz value of the FP64 correlation matrix on span(v, u) (v, u: FP32
+// vectors spanning nearly the eigenvectors of lambda_1 and lambda_2; unused
+// when !have_v, and then lambda_1 stays the FP32 lam1). Writes stat, status
+// and v1 (the Ritz vector).
+template <int N>
+__device__ __forceinline__ void ritz_fp64(const EigArgs& g, int64_t ncell, int64_t cell, int n,
+                                          int64_t cnt, float lam1, bool have_v, float (&v)[N],
+                                          float (&u)[N], uint8_t st) {
   // FP64 pass over the exact sums: ||C||_F^2 and the projections of C on
   // span(v, u): H = [v u]^T C [v u] and the Gram matrix of (v, u)
   double f2 = 0.0, h11 = 0.0, h12 = 0.0, h22 = 0.0, gvv = 0.0, gvu = 0.0, guu = 0.0;
   {
-    const uint32_t off4 = (uint32_t)cell * 4u;
+    // an opaque copy of the lane's offset: the per-lane addresses of this
+    // pass are formed anew instead of being kept (spilled) from the first
+    // read of the same sums
+    uint32_t off4 = (uint32_t)cell * 4u;
+    asm volatile("" : "+v"(off4));
     // Branch-free, and the loads of each group are issued together before
     // any is used: padding indices (>= n) read a clamped valid address and
     // get d = 0 (v = u = 0 there too), which zeroes their terms. N_ab =
     // cnt S_ab - S_a S_b is exact in FP64 (as in load_corr32).
     const double cd = (double)cnt;
     int32_t S[N], Sdg[N];
-    double d[N], vd[N], ud[N];
+    // v and u are widened to FP64 where they are used (exact conversions):
+    // FP64 copies of both would hold 4 N more registers through the pass
+    double d[N];
+    if (!have_v) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = u[i] = 0.f;
+    }
     static_for<0, N>([&](auto Ai) {
       constexpr int a = RFI_CI(Ai);
       const int aa = a < n ? a : 0;
@@ -554,11 +679,10 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
       const double Sa = (double)S[a];
       const double Naa = fma(cd, (double)Sdg[a], -Sa * Sa);
       d[a] = (a < n && Naa > 0.0) ? 1.0 / sqrt(Naa) : 0.0;
-      vd[a] = have_v ? (double)v[a] : 0.0;
-      ud[a] = have_v ? (double)u[a] : 0.0;
-      h11 += vd[a] * vd[a];
-      h12 += vd[a] * ud[a];
-      h22 += ud[a] * ud[a];
+      const double va = (double)v[a], ua = (double)u[a];
+      h11 += va * va;
+      h12 += va * ua;
+      h22 += ua * ua;
       f2 += a < n ? 1.0 : 0.0;
     });
     gvv = h11;
@@ -585,9 +709,11 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
         const double Nab = fma(cd, (double)R[k - k0], -(double)S[a] * (double)S[b]);
         const double r = Nab * d[a] * d[b];
         off += r * r;
-        o11 += r * (vd[a] * vd[b]);
-        o12 += r * (vd[a] * ud[b] + ud[a] * vd[b]);
-        o22 += r * (ud[a] * ud[b]);
+        const double va = (double)v[a], vb = (double)v[b];
+        const double ua = (double)u[a], ub = (double)u[b];
+        o11 += r * (va * vb);
+        o12 += r * (va * ub + ua * vb);
+        o22 += r * (ua * ub);
       });
       __builtin_amdgcn_sched_barrier(0);
     });
@@ -725,11 +851,11 @@ template <int N>
 hipError_t launch_batch_n(const EigArgs* items, const int64_t* cell0, int nitem, int64_t total,
                           int wg, bool tri, hipStream_t s) {
   const dim3 grid((unsigned)((total + wg - 1) / wg));
-  if (tri)
+  if (tri) {   // Householder, Sturm and the FP64 refinement in one kernel
     hipLaunchKernelGGL(eig_lane_tri_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem, total);
-  else
-    hipLaunchKernelGGL(eig_lane_jacobi_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem,
-                       total);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(eig_lane_jacobi_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem, total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(eig_lane_refine_batch<N>, grid, dim3(wg), 0, s, items, cell0, nitem, total);
@@ -740,10 +866,11 @@ template <int N>
 hipError_t launch_n(const EigArgs& a, int wg, bool tri, hipStream_t s) {
   const int64_t ncell = (int64_t)a.nsub * a.nchan;
   const dim3 grid((unsigned)((ncell + wg - 1) / wg));
-  if (tri)
+  if (tri) {   // Householder, Sturm and the FP64 refinement in one kernel
     hipLaunchKernelGGL(eig_lane_tri<N>, grid, dim3(wg), 0, s, a);
-  else
-    hipLaunchKernelGGL(eig_lane_jacobi<N>, grid, dim3(wg), 0, s, a);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(eig_lane_jacobi<N>, grid, dim3(wg), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(eig_lane_refine<N>, grid, dim3(wg), 0, s, a);

@@ -238,6 +238,10 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
     const double* zb) {
   constexpr int NN = 8 * NL;
   using ST = std::conditional_t<W, int64_t, int32_t>;
+  // the sums are global memory (batched launches read their pointers from the
+  // item table, where the compiler cannot tell the address space)
+  typedef const __attribute__((address_space(1))) int32_t gint32;
+  typedef const __attribute__((address_space(1))) int64_t gint64;
   __shared__ double X[NN], P[NN], alpha[NN], offd[NN], tau[NN], dinv[NN], z[NN];
   __shared__ double2 ae[NN];
   // values needed only at the end, kept in LDS instead of registers through
@@ -294,17 +298,17 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
   };
   if constexpr (W) {
     // one contiguous int64 record per cell
-    const int64_t* rec = (const int64_t*)g.sum_x + cell * (int64_t)(n + np);
+    const gint64* rec = (const gint64*)g.sum_x + cell * (int64_t)(n + np);
     stage([&](int q) { return rec[q]; });
   } else if (g.layout) {
     // one contiguous record per cell: coalesced
-    const int32_t* rec = g.sum_x + cell * (int64_t)(n + np);
+    const gint32* rec = (const gint32*)g.sum_x + cell * (int64_t)(n + np);
     stage([&](int q) { return rec[q]; });
   } else {
     // rows layout: row q of the record is sum_x[q] (q < n) or sum_xy[q - n]
     stage([&](int q) {
-      const int32_t* row = q < n ? g.sum_x + (int64_t)q * ncell
-                                 : g.sum_xy + (int64_t)(q - n) * ncell;
+      const gint32* row = (const gint32*)(q < n ? g.sum_x + (int64_t)q * ncell
+                                                : g.sum_xy + (int64_t)(q - n) * ncell);
       return row[cell];
     });
   }

@@ -3,8 +3,14 @@
     python -m paper_2512_16278_amd.prof_summary kernels <kernel_stats.csv> <out.md> <command>
     python -m paper_2512_16278_amd.prof_summary traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <out.json> <out.md> <command>
+    python -m paper_2512_16278_amd.prof_summary counters <kernel-substring> <out.md> \
+        <command1> <csv1> [<command2> <csv2> ...]
 
 `kernels` tabulates the per-kernel statistics of a --kernel-trace --stats run.
+
+`counters` sums the SQ / GRBM counters of one kernel over its dispatches
+(several --pmc runs, one csv each) and derives the VALU issue share, the
+executed FP64 flops and the LDS bank-conflict share per dispatch.
 
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the sums
 kernel into HBM bytes per launch. The counters are scaled by what they read
@@ -109,10 +115,73 @@ def traffic(fetch_csv: str, write_csv: str, out_json: str, out_md: str, command:
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+CU_NUM, XCD_NUM = 256, 8
+
+
+def counters(kernel: str, out_md: str, runs: list) -> None:
+    """runs: [(command, counter_collection.csv)]. Counters of the dispatches of
+    kernel (substring of the name), summed per counter, divided by the number
+    of dispatches. GRBM_GUI_ACTIVE is summed over the eight XCDs, so the
+    kernel's clock cycles are that sum / 8; SQ_ACTIVE_INST_VALU is in quad
+    cycles summed over the SIMDs, so SQ_ACTIVE_INST_VALU / CU_NUM / cycles is
+    the share of SIMD cycles issuing VALU work (rocprofv3's VALUBusy)."""
+    tot, disp, dur, name = {}, {}, {}, ""
+    for _, path in runs:
+        for r in csv.DictReader(open(path)):
+            if kernel not in r["Kernel_Name"]:
+                continue
+            name = short_name(r["Kernel_Name"])
+            key = (path, r["Dispatch_Id"])
+            dur[key] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            c = r["Counter_Name"]
+            tot[c] = tot.get(c, 0.0) + float(r["Counter_Value"])
+            disp.setdefault(c, set()).add(key)
+    per = {c: tot[c] / len(disp[c]) for c in tot}
+    lines = [f"# Counters of `{name}` (per dispatch)", "", "Commands (repository root, one "
+             "MI355X), one counter set per run:", "", "```"] + [cmd for cmd, _ in runs] + \
+            ["```", "", "| counter | per dispatch |", "|---|---|"]
+    for c in sorted(per):
+        lines.append(f"| {c} | {per[c]:.4g} |")
+    g = per.get("GRBM_GUI_ACTIVE")
+    lines += ["", f"Mean dispatch duration: {sum(dur.values()) / len(dur) / 1e6:.3f} ms "
+              f"({len(dur)} dispatches over the runs).", ""]
+    if g:
+        cyc = g / XCD_NUM
+        lines.append(f"- clock cycles per dispatch (GRBM_GUI_ACTIVE / {XCD_NUM}): {cyc:.4g}")
+        if "SQ_ACTIVE_INST_VALU" in per:
+            lines.append(f"- VALU issue share of SIMD cycles (SQ_ACTIVE_INST_VALU / CU_NUM / "
+                         f"cycles): {per['SQ_ACTIVE_INST_VALU'] / CU_NUM / cyc:.3f}")
+        if "SQ_ACTIVE_INST_LDS" in per:
+            lines.append(f"- LDS issue share (SQ_ACTIVE_INST_LDS / CU_NUM / cycles): "
+                         f"{per['SQ_ACTIVE_INST_LDS'] / CU_NUM / cyc:.3f}")
+    if "SQ_WAVES" in per and "SQ_INSTS_VALU" in per:
+        lines.append(f"- VALU instructions per wave: {per['SQ_INSTS_VALU'] / per['SQ_WAVES']:.4g}")
+        if "SQ_INSTS_LDS" in per:
+            lines.append(f"- LDS instructions per wave: {per['SQ_INSTS_LDS'] / per['SQ_WAVES']:.4g}")
+    if "SQ_INSTS_VALU_FMA_F64" in per:
+        f64 = (2 * per["SQ_INSTS_VALU_FMA_F64"] + per.get("SQ_INSTS_VALU_ADD_F64", 0) +
+               per.get("SQ_INSTS_VALU_MUL_F64", 0)) * 64
+        ms = sum(dur.values()) / len(dur) / 1e6
+        lines.append(f"- executed FP64 flops per dispatch ((2 FMA + ADD + MUL) x 64): {f64:.4g}, "
+                     f"{f64 / ms / 1e9:.1f} TFLOP/s over the mean duration (peak 78.6)")
+        if "SQ_INSTS_VALU" in per:
+            n64 = (per["SQ_INSTS_VALU_FMA_F64"] + per.get("SQ_INSTS_VALU_ADD_F64", 0) +
+                   per.get("SQ_INSTS_VALU_MUL_F64", 0))
+            lines.append(f"- FP64 FMA/ADD/MUL share of VALU instructions: "
+                         f"{n64 / per['SQ_INSTS_VALU']:.3f}")
+    if "SQ_LDS_BANK_CONFLICT" in per and "SQ_ACTIVE_INST_LDS" in per:
+        lines.append(f"- LDS bank-conflict cycles per LDS-active cycle: "
+                     f"{per['SQ_LDS_BANK_CONFLICT'] / per['SQ_ACTIVE_INST_LDS']:.3f}")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "kernels":
         kernels(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+    elif sys.argv[1] == "counters":
+        rest = sys.argv[4:]
+        counters(sys.argv[2], sys.argv[3], list(zip(rest[0::2], rest[1::2])))
     else:
         raise SystemExit(__doc__)
