@@ -14,9 +14,9 @@
 // Step k of the reduction:
 //  - row k (= column k) is broadcast through LDS by the 8 lanes that hold it;
 //  - the reflector v (v_{k+1} = 1, zero at indices <= k) and beta;
-//  - p = A v: each lane sums its partial rows, then a DPP reduction over the
-//    8 lanes of a lane row; p goes through LDS to the lanes that hold it as
-//    column indices;
+//  - p = A v: each lane sums its partial rows; the 8 partials of each row go
+//    through LDS and one lane per row adds them, so beta p is in LDS for the
+//    lanes that hold its entries as rows and as columns;
 //  - w = beta p - (beta^2 p.v / 2) v and A -= v w^T + w v^T.
 // The update is the full two-sided product H A H on the whole padded matrix:
 // rows and columns already reduced are only multiplied by the orthogonal H
@@ -248,7 +248,15 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
   // the reduction (registers are what bounds this kernel's occupancy)
   __shared__ double s_frob2;
   __shared__ int s_degen;
-  __shared__ ST S[NN], SP[NN * (NN + 1) / 2];
+  __shared__ ST S[NN];
+  __shared__ __attribute__((aligned(16))) ST SP[NN * (NN + 1) / 2];
+  // partial row sums of p = A v, [lane column][row] with an odd row stride;
+  // they live in the staged sums' space (dead once the matrix is formed)
+  // where it is large enough
+  constexpr int kPPS = NN + 1;
+  constexpr bool kPPAlias = sizeof(ST) * (NN * (NN + 1) / 2) >= sizeof(double) * 8 * kPPS;
+  __shared__ double PPown[kPPAlias ? 1 : 8 * kPPS];
+  double* const PP = kPPAlias ? reinterpret_cast<double*>(SP) : PPown;
   extern __shared__ __attribute__((aligned(16))) double vst[];
   int64_t cell = xcd_order(blockIdx.x, gridDim.x);
   if (items) {
@@ -326,6 +334,20 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
   int degenerate = __syncthreads_or(dead);
   double A[NL][NL];
   double offsq = 0.0;
+  // this lane's row and column values of S and 1 / sqrt(N_aa) (0 at padding
+  // indices), read once
+  [[maybe_unused]] double Srow[NL], Scol[NL], drow[NL], dcol[NL];
+  if constexpr (!NC) {
+    static_for<0, NL>([&](auto II) {
+      constexpr int ii = RFI_CI(II);
+      const int gi = r + 8 * ii, gj = c + 8 * ii;
+      Srow[ii] = (double)S[gi < n ? gi : 0];
+      Scol[ii] = (double)S[gj < n ? gj : 0];
+      drow[ii] = gi < n ? dinv[gi] : 0.0;
+      dcol[ii] = gj < n ? dinv[gj] : 0.0;
+    });
+  }
+  const double cd = (double)cnt;
   static_for<0, NL>([&](auto II) {
     constexpr int ii = RFI_CI(II);
     static_for<0, NL>([&](auto JJ) {
@@ -341,15 +363,16 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
           val = ((((double)SP[pidx(a, b, n)] - zbv * Sa) - za * Sb) + (Lc * za) * zbv) / Lc;
           offsq += gi == gj ? val * val : (gi < gj ? 2.0 * val * val : 0.0);
         }
-      } else if (gi < n && gj < n) {
-        if (gi == gj) {
-          val = 1.0;
-        } else {
-          const int a = gi < gj ? gi : gj, b = gi < gj ? gj : gi;
-          const int64_t Nab = cnt * (int64_t)SP[pidx(a, b, n)] - (int64_t)S[a] * S[b];
-          val = (double)Nab * dinv[a] * dinv[b];
-          if (gi < gj) offsq += val * val;
-        }
+      } else {
+        // N_ab = cnt S_ab - S_a S_b is exact in FP64: both products and the
+        // difference are integers below 2^53 (S_ab <= 255^2 L, L <= 262,143);
+        // branch-free, padding indices read a valid entry and get d = 0. The
+        // product d_a d_b keeps both triangles bit-identical.
+        const int ga = gi < n ? gi : 0, gb = gj < n ? gj : 0;
+        const int a = ga < gb ? ga : gb, b = ga < gb ? gb : ga;
+        const double Nab = fma(cd, (double)SP[pidx(a, b, n)], -Srow[ii] * Scol[jj]);
+        val = gi == gj ? (gi < n ? 1.0 : 0.0) : Nab * (drow[ii] * dcol[jj]);
+        offsq += gi < gj ? val * val : 0.0;
       }
       A[ii][jj] = val;
     });
@@ -386,7 +409,8 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
           x0 += gj == k + 1 ? x : 0.0;
         });
         s2 = sum8(s2);
-        x0 = sum8(x0);   // one non-zero term: exact
+        // one non-zero term, on the lane that holds column k + 1 of row k
+        x0 = lane_f64(x0, 8 * rk + ((k + 1) & 7));
         double beta = 0.0, sub = x0, iv0 = 0.0;
         if (s2 > 0.0) {
           const double mu = sqrt(fma(x0, x0, s2));
@@ -422,28 +446,41 @@ __global__ __launch_bounds__(64, (NL <= 9 && !W && !NC) ? 2 : 1) void eig_tri_ke
           pr[ii] = fma(A[ii][jj], vcj, pr[ii]);
         });
       });
-      static_for<IK, NL>([&](auto II) { pr[RFI_CI(II)] = sum8(pr[RFI_CI(II)]); });
-      if (c == 0) {
-        static_for<IK, NL>([&](auto II) { P[r + 8 * RFI_CI(II)] = pr[RFI_CI(II)]; });
+      // the row sums over the 8 lanes of a lane row go through LDS: every
+      // lane stores its partials, then lane (r, c) adds the eight partials of
+      // local row IK + c (and IK + c + 8) in a fixed order and stores beta
+      // times the sum in P (fewer instructions than an 8-lane DPP sum per row)
+      static_for<IK, NL>([&](auto II) {
+        constexpr int ii = RFI_CI(II);
+        PP[c * kPPS + r + 8 * ii] = pr[ii];
+      });
+      __syncthreads();
+      for (int jj = IK + c; jj < NL; jj += 8) {
+        const int i = r + 8 * jj;
+        const double s01 = PP[i] + PP[kPPS + i], s23 = PP[2 * kPPS + i] + PP[3 * kPPS + i];
+        const double s45 = PP[4 * kPPS + i] + PP[5 * kPPS + i];
+        const double s67 = PP[6 * kPPS + i] + PP[7 * kPPS + i];
+        P[i] = beta * ((s01 + s23) + (s45 + s67));
       }
       __syncthreads();
+      // with P = beta p: K = beta^2 (p.v) / 2 = beta (P.v) / 2
       double pv = 0.0;
       static_for<IK, NL>([&](auto JJ) {
         pv = fma(P[c + 8 * RFI_CI(JJ)], X[c + 8 * RFI_CI(JJ)], pv);
       });
       pv = sum8(pv);
-      const double K = 0.5 * beta * beta * pv;
+      const double K = 0.5 * beta * pv;
       // w = beta p - K v; A -= v w^T + w v^T
       double vr[NL];
       static_for<IK, NL>([&](auto II) {
         constexpr int ii = RFI_CI(II);
         vr[ii] = X[r + 8 * ii];
-        pr[ii] = beta * pr[ii] - K * vr[ii];
+        pr[ii] = fma(-K, vr[ii], P[r + 8 * ii]);
       });
       static_for<IK, NL>([&](auto JJ) {
         constexpr int jj = RFI_CI(JJ);
         const double vcj = X[c + 8 * jj];
-        const double wcj = beta * P[c + 8 * jj] - K * vcj;
+        const double wcj = fma(-K, vcj, P[c + 8 * jj]);
         static_for<IK, NL>([&](auto II) {
           constexpr int ii = RFI_CI(II);
           A[ii][jj] = fma(-vr[ii], wcj, fma(-pr[ii], vcj, A[ii][jj]));
