@@ -475,6 +475,67 @@ __device__ void block_sum3(int64_t& n, u128& a, u128& b, Red3<NT>& sh) {
   }
 }
 
+// The band cells' moments with 64-bit partials: for 0 <= q < 2^42 split
+// q = qh 2^21 + ql (qh, ql < 2^21), so that q^2 = qh^2 2^42 + qh ql 2^22 +
+// ql^2 and every partial sum over at most 2^14 cells stays below 2^64; four
+// 64-bit wave sums and one 32-bit instead of the nine 64-bit ones of the
+// 128-bit sums. The totals are rebuilt exactly in 128 bits.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 15) + (uint32_t)__builtin_amdgcn_readlane((int)v, 31) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 47) + (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+struct SplitSums {
+  uint32_t n;
+  uint64_t a, h2, hl, l2;
+};
+template <int NT>
+struct RedSplit {
+  uint32_t n[NT / 64];
+  uint64_t a[NT / 64], h2[NT / 64], hl[NT / 64], l2[NT / 64];
+};
+__device__ __forceinline__ void acc_split(int64_t q, SplitSums& t) {
+  const uint64_t qh = (uint64_t)q >> 21, ql = (uint64_t)q & ((1u << 21) - 1);
+  t.n += 1;
+  t.a += (uint64_t)q;
+  t.h2 += qh * qh;
+  t.hl += qh * ql;
+  t.l2 += ql * ql;
+}
+template <int NT>
+__device__ void block_sum_split(SplitSums& t, int64_t& n, u128& a, u128& b, RedSplit<NT>& sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  t.n = wave_sum_u32(t.n);
+  t.a = wave_sum_u64(t.a);
+  t.h2 = wave_sum_u64(t.h2);
+  t.hl = wave_sum_u64(t.hl);
+  t.l2 = wave_sum_u64(t.l2);
+  __syncthreads();                        // sh may still be read by an earlier call
+  if (lane == 0) {
+    sh.n[wave] = t.n;
+    sh.a[wave] = t.a;
+    sh.h2[wave] = t.h2;
+    sh.hl[wave] = t.hl;
+    sh.l2[wave] = t.l2;
+  }
+  __syncthreads();
+  uint64_t nn = 0, aa = 0, h2 = 0, hl = 0, l2 = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    nn += sh.n[w];
+    aa += sh.a[w];
+    h2 += sh.h2[w];
+    hl += sh.hl[w];
+    l2 += sh.l2[w];
+  }
+  n = (int64_t)nn;
+  a = (u128)aa;
+  b = ((u128)h2 << 42) + ((u128)hl << 22) + (u128)l2;
+}
+
 __device__ __forceinline__ void acc(int64_t q, int64_t& n, u128& a, u128& b) {
   n += 1;
   a += (u128)(uint64_t)q;
@@ -649,6 +710,7 @@ template <bool kBatch>
 __global__ __launch_bounds__(kIterThreads) void clip_iter_kernel(ClipJob job0, const ClipJob* jobs) {
   const ClipJob J = job_of<kBatch>(job0, jobs, blockIdx.x);
   __shared__ Red3<kIterThreads> red;
+  __shared__ RedSplit<kIterThreads> reds;
   __shared__ int64_t near[kNearMax];
   __shared__ int64_t sT;
   __shared__ double sfit[3];
@@ -673,6 +735,9 @@ __global__ __launch_bounds__(kIterThreads) void clip_iter_kernel(ClipJob job0, c
   const bool complete = cnt <= (unsigned long long)J.tail_cap;
   const int64_t M = complete ? (int64_t)cnt : 0;
   const bool in_lds = M <= kNearMax;
+  // every listed q lies in (L, H]: the 64-bit split sums are exact when
+  // 0 <= q < 2^42 and at most 2^14 cells are summed
+  const bool split = L >= -1 && H < ((int64_t)1 << 42) && kNearMax <= (1 << 14);
   const int64_t* tail = tail_of(J);
   if (complete && in_lds) {
     for (int64_t k0 = 0; k0 < M; k0 += (int64_t)kIterThreads * kIterLoad) {
@@ -716,7 +781,14 @@ __global__ __launch_bounds__(kIterThreads) void clip_iter_kernel(ClipJob job0, c
       // band cells above T (LDS, or the list itself when it is too long)
       int64_t n = 0;
       u128 a = 0, b = 0;
-      if (in_lds) {
+      if (in_lds && split) {
+        SplitSums t{0, 0, 0, 0, 0};
+        for (int64_t k = threadIdx.x; k < M; k += kIterThreads) {
+          const int64_t q = near[k];
+          if (q > T) acc_split(q, t);
+        }
+        block_sum_split<kIterThreads>(t, n, a, b, reds);
+      } else if (in_lds) {
         for (int64_t k = threadIdx.x; k < M; k += kIterThreads) {
           const int64_t q = near[k];
           if (q > T) acc(q, n, a, b);
@@ -736,7 +808,7 @@ __global__ __launch_bounds__(kIterThreads) void clip_iter_kernel(ClipJob job0, c
           }
         }
       }
-      block_sum3<kIterThreads>(n, a, b, red);
+      if (!(in_lds && split)) block_sum3<kIterThreads>(n, a, b, red);
       N = Nt - Nf - n; Q1 = Q1t - F1 - a; Q2 = Q2t - F2 - b;
     } else {
       // fallback: a pass over every cell
