@@ -443,7 +443,11 @@ rfi_status rfi_process_block(const rfi_block* blk /* host */,
 typedef struct {
   const rfi_block* blk;          /* host pointer to the block description */
   int64_t t0;                    /* first sample of the first sub-interval */
-  int32_t L;                     /* samples per sub-interval, 1..RFI_MAX_COUNT */
+  int32_t L;                     /* samples per sub-interval, 1..RFI_MAX_COUNT_LONG;
+                                    above RFI_MAX_COUNT the item takes the long route of
+                                    rfi_process_block (int64 sums of time chunks, FP64
+                                    tridiagonal solver) with launches of its own, and
+                                    the batched clip */
   int32_t nsub;                  /* full sub-intervals (0: the block is skipped) */
   const uint8_t* protect_chan;   /* device [nchan] or NULL */
   rfi_stream_state* state;       /* device or NULL: pooled clip state */

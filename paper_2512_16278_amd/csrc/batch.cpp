@@ -41,6 +41,8 @@ struct ItemPlan {
   int wg;                  // per-lane solver workgroup
   size_t sums_off;         // byte offset of the item's sums in the workspace
   size_t clip_off;         // byte offset of the item's clip workspace
+  bool longL;              // L > RFI_MAX_COUNT: its own sums (int64 records of time
+                           // chunks) and FP64 tridiagonal launches, the batched clip
 };
 
 struct EigClass {
@@ -98,8 +100,9 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
     if (!it.blk) return fail(RFI_E_INVALID, "%s: item %d has no block", who, i);
     ItemPlan ip{};
     ip.idx = i;
-    rfi_status st = validate_block(it.blk, it.t0, it.L, it.nsub, who, &ip.bp);
+    rfi_status st = validate_block(it.blk, it.t0, it.L, it.nsub, who, &ip.bp, RFI_MAX_COUNT_LONG);
     if (st != RFI_OK) return st;
+    ip.longL = it.L > RFI_MAX_COUNT;
     if (it.nsub == 0) continue;
     if (!it.stat || !it.status || !it.mask)
       return fail(RFI_E_INVALID, "%s: item %d has a NULL output", who, i);
@@ -119,7 +122,9 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
     if ((st = check_tune_entry(te, ip.nbeam, who)) != RFI_OK) return st;
     if (ccm_class(ip.nbeam, &ip.cc, &ip.ct) != hipSuccess)
       return fail(RFI_E_INVALID, "%s: item %d: no sums instance for %d beams", who, i, ip.nbeam);
-    ip.solver = res.solver;
+    // long sub-intervals: the FP64 tridiagonal solver on the int64 sums (as
+    // rfi_process_block; their cells read n L > 66,050 bytes each)
+    ip.solver = ip.longL ? RFI_EIG_TRIDIAG : res.solver;
     ip.precision = res.precision;
     const bool lane = res.solver == RFI_EIG_LANE || res.solver == RFI_EIG_LANE_TRI;
     ip.lane_cls = lane                            ? eig_lane_class(ip.nbeam)
@@ -147,6 +152,7 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
   std::map<std::tuple<int, int, int, int>, std::vector<int>> eig;
   for (int k = 0; k < n; ++k) {
     const ItemPlan& ip = bpn->plans[k];
+    if (ip.longL) continue;           // launched on its own (enqueue_long)
     ccm[ip.cc.key].push_back(k);
     const bool lane = ip.solver == RFI_EIG_LANE || ip.solver == RFI_EIG_LANE_TRI;
     eig[{ip.lane_cls, ip.solver, ip.precision, lane ? ip.wg : 0}].push_back(k);
@@ -178,8 +184,13 @@ rfi_status plan_batch(int nitem, const rfi_batch_item* items, const rfi_batch_pa
   bpn->desc_bytes = o;
   for (ItemPlan& ip : bpn->plans) {
     ip.sums_off = o;
-    o += up((size_t)ip.nbeam * ip.ncell * 4) + up((size_t)npair_of(ip.nbeam) * ip.ncell * 4) +
-         up((size_t)items[ip.idx].nsub * 4);
+    const int nsub = items[ip.idx].nsub;
+    if (ip.longL)   // int64 cell records, the int32 chunk scratch, counts
+      o += up((size_t)(ip.nbeam + npair_of(ip.nbeam)) * ip.ncell * 8) +
+           up(ccm_long_tmp_bytes(ip.nbeam, ip.nchan, nsub)) + up((size_t)nsub * 4);
+    else
+      o += up((size_t)ip.nbeam * ip.ncell * 4) + up((size_t)npair_of(ip.nbeam) * ip.ncell * 4) +
+           up((size_t)nsub * 4);
     ip.clip_off = o;
     o += up(clip_workspace_size(ip.ncell));
   }
@@ -308,12 +319,34 @@ hipError_t enqueue_eig(const BatchPlan& bpn, const void* desc, char* ws, hipStre
   return hipSuccess;
 }
 
+// The items with long sub-intervals: exact int64 sums of time chunks, then the
+// FP64 tridiagonal solver on them (the launches of rfi_process_block's long
+// route, on the batch's stream).
+hipError_t enqueue_long(const BatchPlan& bpn, char* ws, hipStream_t s) {
+  for (const ItemPlan& ip : bpn.plans) {
+    if (!ip.longL) continue;
+    const rfi_batch_item& it = bpn.items[ip.idx];
+    char* b = ws + ip.sums_off;
+    int64_t* rec = (int64_t*)b;
+    char* tmp = b + up((size_t)(ip.nbeam + npair_of(ip.nbeam)) * ip.ncell * 8);
+    int32_t* cnt = (int32_t*)(tmp + up(ccm_long_tmp_bytes(ip.nbeam, ip.nchan, it.nsub)));
+    hipError_t e = launch_ccm_long(ip.bp, ip.nbeam, ip.nchan, it.blk->row_stride, it.t0, it.L,
+                                   it.nsub, rec, cnt, tmp, s, &ip.ct);
+    if (e != hipSuccess) return e;
+    EigArgs a{ip.nbeam, it.nsub, ip.nchan, (const int32_t*)rec, nullptr, cnt, bpn.eig.max_sweeps,
+              1, nullptr, it.stat, it.v1, it.status, ip.ncell, 2};
+    if ((e = launch_eig_tri(a, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t enqueue_batch(const BatchPlan& bpn, const void* desc, char* ws, hipStream_t s) {
   const int n = (int)bpn.plans.size();
   if (n == 0) return hipSuccess;
   hipError_t e = enqueue_desc(bpn, desc, ws, s);
   if (e == hipSuccess) e = enqueue_ccm(bpn, desc, ws, s);
   if (e == hipSuccess) e = enqueue_eig(bpn, desc, ws, s);
+  if (e == hipSuccess) e = enqueue_long(bpn, ws, s);
   if (e != hipSuccess) return e;
   e = launch_clip_batch((const ClipJob*)(ws + bpn.flag_off), bpn.clip_jobs.data(), n, s);
   // per-beam stages, after every clip: their partial sums reuse each block's
@@ -440,6 +473,7 @@ rfi_status rfi_tune_batch(int32_t nitem, const rfi_batch_item* items, const rfi_
   std::map<int, std::vector<rfi_batch_item>> by_class;
   std::map<int, int> max_nbeam;
   for (const rfi::ItemPlan& ip : full.plans) {
+    if (ip.longL) continue;      // long sub-intervals take their own fixed route
     const int sc = rfi::shape_class(ip.nbeam);
     by_class[sc].push_back(items[ip.idx]);
     max_nbeam[sc] = std::max(max_nbeam[sc], ip.nbeam);

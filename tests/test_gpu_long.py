@@ -139,3 +139,71 @@ def test_long_process_block(dev):
         (ref.mu, ref.sigma, ref.thr, ref.iterations)
     cr = pipeline.cells(x, L, nsub, t0=50)
     assert np.abs(s - cr.stat.ravel()).max() <= 1e-12
+
+
+def test_long_items_in_batch(dev):
+    """A batch with a long-sub-interval item (L = 40,960, past the int32 bound)
+    beside an ordinary one: every item equals rfi_process_block on its block
+    alone bit for bit (statistic, status, mask, v1 and the per-beam mask of
+    the long item), the long item's statistic is within 1e-12 of the oracle,
+    and graph replays reproduce the eager batch."""
+    import torch
+    from paper_2512_16278_amd import rfi
+    nb_l, nchan_l, L_l, nsub_l, t0_l = 19, 40, 40960, 2, 50
+    x_l = _data(nb_l, nsub_l * L_l + 100, nchan_l, 11)
+    buf_l = upload(x_l, dev)
+    blk_l = rfi.make_block(buf_l, nchan_l)
+    nb_s, nchan_s, L_s, nsub_s = 7, 64, 512, 8
+    x_s = _data(nb_s, nsub_s * L_s, nchan_s, 12)
+    buf_s = upload(x_s, dev)
+    blk_s = rfi.make_block(buf_s, nchan_s)
+
+    def outputs(nb, ncell, long_item):
+        o = dict(stat=torch.full((ncell,), -1.0, dtype=torch.float64, device=dev),
+                 status=torch.full((ncell,), 0xEE, dtype=torch.uint8, device=dev),
+                 mask=torch.full((ncell,), 9, dtype=torch.uint8, device=dev))
+        if long_item:
+            o["v1"] = torch.full((nb, ncell), -9.0, dtype=torch.float32, device=dev)
+            o["beam_mask"] = torch.full((nb, ncell), 9, dtype=torch.uint8, device=dev)
+        return o
+
+    items = [dict(blk=blk_l, t0=t0_l, L=L_l, nsub=nsub_l, **outputs(nb_l, nsub_l * nchan_l, True)),
+             dict(blk=blk_s, t0=0, L=L_s, nsub=nsub_s, **outputs(nb_s, nsub_s * nchan_s, False))]
+    bt = rfi.Batch(items)
+    ws = torch.empty(bt.workspace_size(), dtype=torch.uint8, device=dev)
+    say("batch with a long item")
+    bt.run(ws)
+    torch.cuda.synchronize()
+    eager = [{k: v.clone() for k, v in it.items() if torch.is_tensor(v)} for it in items]
+
+    # each block alone through the whole-block call
+    for it, (x, nb, nchan) in zip(items, ((x_l, nb_l, nchan_l), (x_s, nb_s, nchan_s))):
+        ncell = it["nsub"] * nchan
+        ref = outputs(nb, ncell, "v1" in it)
+        p = rfi.process_params(it["L"], it["nsub"], t0=it["t0"],
+                               beam_mask=ref.get("beam_mask"))
+        pws = torch.empty(rfi.rfi_process_workspace_size(nb, nchan, p), dtype=torch.uint8,
+                          device=dev)
+        say("whole-block call", nb, nchan, it["L"])
+        rfi.rfi_process_block(it["blk"], p, ref["stat"], ref["status"], ref["mask"], pws,
+                              v1=ref.get("v1"))
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(ref[k], it[k]), (it["L"], k)
+
+    cr = pipeline.cells(x_l, L_l, nsub_l, t0=t0_l)
+    assert np.abs(items[0]["stat"].cpu().numpy() - cr.stat.ravel()).max() <= 1e-12
+
+    g = bt.graph(ws)
+    for rep in range(3):
+        for it in items:
+            for k, v in it.items():
+                if torch.is_tensor(v):
+                    v.fill_(7)
+        say("graph replay", rep)
+        g.launch()
+        torch.cuda.synchronize()
+        for it, ref in zip(items, eager):
+            for k in ref:
+                assert torch.equal(ref[k], it[k]), (rep, k)
+    g.close()
