@@ -116,6 +116,14 @@ __device__ __forceinline__ int64_t pidx(int a, int b, int n) {
   return (int64_t)a * n - (int64_t)a * (a - 1) / 2 + (b - a);
 }
 
+// 1 / sqrt(x) for x > 0 to about 1 ulp: the hardware estimate and one Newton
+// step, r (3 - x r^2) / 2 (the correctly rounded division and square root
+// cost tens of instructions each, 2 n of them per cell).
+__device__ __forceinline__ double rsqrt64(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  return r * fma(-0.5 * x * r, r, 1.5);
+}
+
 // Build the FP32 correlation matrix of one cell from its exact sums:
 // N_ab = cnt S_ab - S_a S_b in int64, r_ab = N_ab / sqrt(N_aa N_bb).
 // Padding indices (>= n) get an identity row and column.
@@ -309,7 +317,7 @@ __device__ __forceinline__ void orthonormalise(float (&v)[N], float (&u)[N]) {
   float nv = 0.f;
 #pragma unroll
   for (int i = 0; i < N; ++i) nv += v[i] * v[i];
-  const float sv = 1.0f / sqrtf(nv);
+  const float sv = __builtin_amdgcn_rsqf(nv);
   float vu = 0.f;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -322,7 +330,7 @@ __device__ __forceinline__ void orthonormalise(float (&v)[N], float (&u)[N]) {
     u[i] -= vu * v[i];
     nu += u[i] * u[i];
   }
-  const float su = nu > 0.f ? 1.0f / sqrtf(nu) : 0.f;
+  const float su = nu > 0.f ? __builtin_amdgcn_rsqf(nu) : 0.f;
 #pragma unroll
   for (int i = 0; i < N; ++i) u[i] *= su;
 }
@@ -374,11 +382,13 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
     });
     const float x0 = A[Sym<N>::idx(k + 1, k)];
     const float mu2 = fmaf(x0, x0, s2);
-    const float mu = sqrtf(mu2);
+    // hardware square root and reciprocals (about 1 ulp): the FP32 reduction
+    // only has to span the subspace the FP64 Ritz pass refines
+    const float mu = __builtin_amdgcn_sqrtf(mu2);
     const bool refl = s2 > 0.f;
-    const float v0 = x0 <= 0.f ? x0 - mu : -s2 / (x0 + mu);
-    const float beta = refl ? -v0 / mu : 0.f;
-    const float iv0 = refl ? 1.0f / v0 : 0.f;
+    const float v0 = x0 <= 0.f ? x0 - mu : -s2 * __builtin_amdgcn_rcpf(x0 + mu);
+    const float beta = refl ? -v0 * __builtin_amdgcn_rcpf(mu) : 0.f;
+    const float iv0 = refl ? __builtin_amdgcn_rcpf(v0) : 0.f;
     float v[N], w[N];
     static_for<k + 1, N>([&](auto I) {
       constexpr int i = RFI_CI(I);
@@ -433,7 +443,8 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
   static_for<0, N>([&](auto I) {
     constexpr int i = RFI_CI(I);
     if (i < n) {
-      const float rad = sqrtf(e2[i]) + (i + 1 < N ? sqrtf(e2[(i + 1) % N]) : 0.f);
+      const float rad = __builtin_amdgcn_sqrtf(e2[i]) +
+                        (i + 1 < N ? __builtin_amdgcn_sqrtf(e2[(i + 1) % N]) : 0.f);
       glo = fminf(glo, dg[i] - rad);
       ghi = fmaxf(ghi, dg[i] + rad);
       dmax = fmaxf(dmax, dg[i]);
@@ -504,7 +515,7 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
       }
       ok = ok && (i >= n || d > 0.f);
       l[i] = li;
-      id[i] = i < n ? 1.0f / fmaxf(d, 1e-30f) : 0.f;
+      id[i] = i < n ? __builtin_amdgcn_rcpf(fmaxf(d, 1e-30f)) : 0.f;
     });
     start_vectors<N>(n, v, u);
     for (int it = 0; it < 3; ++it) {
@@ -591,7 +602,7 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
       });
       ok = ok && d > 0.f;
       // the diagonal of B is not read again: it keeps 1 / R_jj
-      const float rj = 1.0f / sqrtf(fmaxf(d, 1e-30f));
+      const float rj = __builtin_amdgcn_rsqf(fmaxf(d, 1e-30f));
       A[Sym<N>::idx(j, j)] = rj;
       static_for<j + 1, N>([&](auto I) {
         constexpr int i = RFI_CI(I);
@@ -678,7 +689,7 @@ __device__ __forceinline__ void ritz_fp64(const EigArgs& g, int64_t ncell, int64
       constexpr int a = RFI_CI(Ai);
       const double Sa = (double)S[a];
       const double Naa = fma(cd, (double)Sdg[a], -Sa * Sa);
-      d[a] = (a < n && Naa > 0.0) ? 1.0 / sqrt(Naa) : 0.0;
+      d[a] = (a < n && Naa > 0.0) ? rsqrt64(Naa) : 0.0;
       const double va = (double)v[a], ua = (double)u[a];
       h11 += va * va;
       h12 += va * ua;
