@@ -282,10 +282,12 @@ def test_serve_tune_table(dev):
     """A session given a tune table runs every stream with its entry's launch
     choices: tile, ring depth and XCD grouping of the sums are bit-exact with
     the defaults; another solver gives identical masks and statistics within
-    its accuracy (1e-12 for the per-lane Jacobi, whose FP64 refinement is
-    exact to rounding; 1e-10 for the FP32 wave Jacobi, whose lambda_1 is the
-    FP64 Rayleigh quotient of its FP32 vector, error quadratic in that
-    vector's). Entries outside the allowed ranges fail rfi_stream_open."""
+    the two solvers' accuracies: up to 20 beams the per-lane Jacobi (within
+    about 3e-14 of FP64) against the default per-lane Householder, whose Ritz
+    subspace carries the rounding of its FP32 reduction (within 3e-12 of
+    FP64), so 1e-11; above, 1e-10 for the FP32 wave Jacobi, whose lambda_1 is
+    the FP64 Rayleigh quotient of its FP32 vector, error quadratic in that
+    vector's. Entries outside the allowed ranges fail rfi_stream_open."""
     from paper_2512_16278_amd import rfi
     t = rfi.rfi_tune_table()
     ents = [_entry(2, 15, stages=2, group=512, solver=rfi.RFI_EIG_LANE, wg=64),
@@ -312,7 +314,7 @@ def test_serve_tune_table(dev):
             if same_solver or sa.size == 0:
                 assert np.array_equal(sa, sm), nb
             else:
-                assert np.abs(sa - sm).max() <= (1e-12 if nb <= 20 else 1e-10), nb
+                assert np.abs(sa - sm).max() <= (1e-11 if nb <= 20 else 1e-10), nb
             assert np.array_equal(a[3][1], m[3][1]), nb
             assert np.array_equal(a[3][2], m[3][2]), nb
     # out-of-range entries are rejected when a stream of that shape opens
