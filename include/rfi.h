@@ -582,7 +582,10 @@ typedef struct {
 
 typedef struct {
   int32_t nbeam, nchan;  /* block shape of this stream */
-  int32_t L;             /* samples per sub-interval, 1..RFI_MAX_COUNT */
+  int32_t L;             /* samples per sub-interval, 1..RFI_MAX_COUNT_LONG; above
+                            RFI_MAX_COUNT the sums (the carry's too) are int64 and the
+                            eigen stage is the FP64 tridiagonal solver, as in
+                            rfi_process_block */
   int32_t eig_precision; /* 32 (0 = 32) or 64 */
   int32_t max_sweeps;    /* 0 = 12 */
   int32_t max_iter;      /* clip fits, 0 = 50 */

@@ -47,25 +47,27 @@ int max_split(int nsub, int nchan) {
 }
 
 // rec64[cell][row] = sum over the P chunk records (and the remainder record
-// when rem) of that cell; count[k] = L
+// when rem) of that cell; count[k] = L. With accumulate the sums and counts
+// are added to what the records and counts hold.
 __global__ __launch_bounds__(kWidenThreads) void widen_kernel(const int32_t* __restrict__ rec32,
                                                               int64_t* __restrict__ rec64,
                                                               int nsub, int nchan, int nrow,
                                                               int P, int rem,
                                                               int32_t* __restrict__ count,
-                                                              int L) {
+                                                              int L, int accumulate) {
   const int64_t per_sub = (int64_t)nchan * nrow;         // values of one sub-interval
   const int64_t n = (int64_t)nsub * per_sub;
   const int64_t i = (int64_t)blockIdx.x * kWidenThreads + threadIdx.x;
   if (count && blockIdx.x == 0)
-    for (int k = threadIdx.x; k < nsub; k += kWidenThreads) count[k] = L;
+    for (int k = threadIdx.x; k < nsub; k += kWidenThreads)
+      count[k] = accumulate ? count[k] + L : L;
   if (i >= n) return;
   const int64_t k = i / per_sub, w = i % per_sub;
   const int32_t* src = rec32 + k * P * per_sub + w;
   int64_t acc = 0;
   for (int j = 0; j < P; ++j) acc += src[(int64_t)j * per_sub];
   if (rem) acc += rec32[(int64_t)nsub * P * per_sub + i];
-  rec64[i] = acc;
+  rec64[i] = accumulate ? rec64[i] + acc : acc;
 }
 
 }  // namespace
@@ -78,7 +80,7 @@ size_t ccm_long_tmp_bytes(int nbeam, int nchan, int nsub) {
 
 hipError_t launch_ccm_long(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int64_t* rec, int32_t* count, void* tmp,
-                           hipStream_t s, const CcmTune* t) {
+                           hipStream_t s, const CcmTune* t, int accumulate) {
   if (nsub == 0) return hipSuccess;
   const int nrow = nbeam + npair_of(nbeam);
   const int P = split_for(L, nsub, nchan);
@@ -102,7 +104,7 @@ hipError_t launch_ccm_long(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
   const int64_t nval = (int64_t)nsub * (int64_t)per_sub;
   const unsigned grid = (unsigned)((nval + kWidenThreads - 1) / kWidenThreads);
   hipLaunchKernelGGL(widen_kernel, dim3(grid), dim3(kWidenThreads), 0, s, rec32, rec, nsub, nchan,
-                     nrow, P, rem, count, L);
+                     nrow, P, rem, count, L, accumulate);
   return hipGetLastError();
 }
 

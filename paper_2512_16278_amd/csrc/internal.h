@@ -66,11 +66,12 @@ hipError_t launch_ccm_valu(const BeamPtrs& bp, int nbeam, int nchan, int64_t row
 
 // Sums of sub-intervals longer than RFI_MAX_COUNT (up to RFI_MAX_COUNT_LONG):
 // int64 cell records rec[cell * (nbeam + npair) + row] (rows b, then nbeam +
-// pair), count[k] = L; tmp: ccm_long_tmp_bytes of device scratch.
+// pair), count[k] = L (accumulate: both added to what rec and count hold);
+// tmp: ccm_long_tmp_bytes of device scratch.
 size_t ccm_long_tmp_bytes(int nbeam, int nchan, int nsub);
 hipError_t launch_ccm_long(const BeamPtrs& bp, int nbeam, int nchan, int64_t row_stride,
                            int64_t t0, int L, int nsub, int64_t* rec, int32_t* count, void* tmp,
-                           hipStream_t s, const CcmTune* t = nullptr);
+                           hipStream_t s, const CcmTune* t = nullptr, int accumulate = 0);
 
 struct EigArgs {
   int nbeam, nsub, nchan;

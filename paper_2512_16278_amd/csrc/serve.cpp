@@ -58,7 +58,8 @@ struct StreamCtx {
   rfi_stream_config cfg{};
   uint8_t* protect = nullptr;        // device copy of the preserved-channel flags
   rfi_stream_state* state = nullptr; // device
-  int32_t* carry = nullptr;          // device: sum_x [nbeam][nchan], sum_xy [npair][nchan], count
+  int32_t* carry = nullptr;          // device: sum_x [nbeam][nchan], sum_xy [npair][nchan], count;
+                                     // long sub-intervals: int64 records [nchan][nbeam + npair], count
   int64_t carry_samples = 0;         // samples in the carry after the last admitted block
   hipEvent_t last = nullptr;         // completion of the stream's last admitted block
   bool has_last = false;
@@ -67,13 +68,19 @@ struct StreamCtx {
   bool tuned = false;                // te holds the session's tune entry for nbeam
   rfi_tune_entry te{};
   const rfi_tune_entry* tune() const { return tuned ? &te : nullptr; }
+  // sub-intervals past the int32 bound: the carry's sums are int64 cell
+  // records, summed by the long route (time chunks widened into int64)
+  bool longL() const { return cfg.L > RFI_MAX_COUNT; }
+  size_t carry_rows() const { return (size_t)(cfg.nbeam + npair_of(cfg.nbeam)) * cfg.nchan; }
   int32_t* carry_sx() const { return carry; }
   int32_t* carry_sxy() const { return carry + (size_t)cfg.nbeam * cfg.nchan; }
+  int64_t* carry_rec() const { return (int64_t*)carry; }
   int32_t* carry_cnt() const {
-    return carry + (size_t)(cfg.nbeam + npair_of(cfg.nbeam)) * cfg.nchan;
+    return longL() ? (int32_t*)(carry_rec() + carry_rows()) : carry + carry_rows();
   }
   size_t carry_bytes() const {
-    return ((size_t)(cfg.nbeam + npair_of(cfg.nbeam)) * cfg.nchan + 1) * sizeof(int32_t);
+    return longL() ? carry_rows() * sizeof(int64_t) + sizeof(int32_t)
+                   : (carry_rows() + 1) * sizeof(int32_t);
   }
 };
 
@@ -266,6 +273,9 @@ rfi_status plan_block(const StreamCtx& st, int64_t nsamp, BlockPlan* b, const ch
   b->pl.flag_ws = up(clip_workspace_size((int64_t)b->nsub * st.cfg.nchan));
   b->pl.ws_bytes = b->pl.flag_ws + (size_t)b->pl.nslot * b->pl.slot;
   b->ws = b->pl.ws_bytes;
+  // the carry of a long sub-interval is summed through the int32 chunk
+  // scratch of the long route, placed after the pipeline's workspace
+  if (st.longL()) b->ws += up(ccm_long_tmp_bytes(st.cfg.nbeam, st.cfg.nchan, 1));
   const size_t ncell = (size_t)b->nsub * st.cfg.nchan;
   b->res = ncell ? up(ncell * 8) + up(ncell) + up(ncell) : 0;
   if (ncell && st.cfg.beam_stage)
@@ -325,14 +335,18 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
   // stream-order wait and the allocations above change no state)
   *launched = true;
   // 1. complete (or extend) the carried sub-interval
+  void* ltmp = (char*)sl.ws + b.pl.ws_bytes;     // long carries only
   if (b.carry_add > 0) {
-    e = launch_ccm_mfma(bp, n, F, stride, 0, (int)b.carry_add, 1, st.carry_sx(), st.carry_sxy(),
-                        st.carry_cnt(), 1, 0, s, &b.pl.ct);
+    e = st.longL() ? launch_ccm_long(bp, n, F, stride, 0, (int)b.carry_add, 1, st.carry_rec(),
+                                     st.carry_cnt(), ltmp, s, &b.pl.ct, 1)
+                   : launch_ccm_mfma(bp, n, F, stride, 0, (int)b.carry_add, 1, st.carry_sx(),
+                                     st.carry_sxy(), st.carry_cnt(), 1, 0, s, &b.pl.ct);
     if (e != hipSuccess) return dev(e, "rfi_submit: carry sums");
   }
   if (b.carried) {
-    EigArgs a{n, 1, F, st.carry_sx(), st.carry_sxy(), st.carry_cnt(), b.pl.eig.max_sweeps, 1,
-              nullptr, r->stat, r->v1, r->cstat, (int64_t)b.nsub * F};
+    EigArgs a{n, 1, F, st.longL() ? (const int32_t*)st.carry_rec() : st.carry_sx(),
+              st.longL() ? nullptr : st.carry_sxy(), st.carry_cnt(), b.pl.eig.max_sweeps, 1,
+              nullptr, r->stat, r->v1, r->cstat, (int64_t)b.nsub * F, st.longL() ? 2 : 0};
     e = launch_eig(a, b.pl.eig, s, b.pl.eig_wg ? b.pl.eig_wg : 256);
     if (e != hipSuccess) return dev(e, "rfi_submit: carry eigen stage");
   }
@@ -348,8 +362,11 @@ rfi_status rfi_session::enqueue(rfi::Request* r, rfi::Slot& sl, rfi::StreamCtx& 
   }
   // 3. new carry
   if (b.rem > 0) {
-    e = launch_ccm_mfma(bp, n, F, stride, b.t_full + (int64_t)b.nfull * L, (int)b.rem, 1,
-                        st.carry_sx(), st.carry_sxy(), st.carry_cnt(), 0, 0, s, &b.pl.ct);
+    const int64_t tr = b.t_full + (int64_t)b.nfull * L;
+    e = st.longL() ? launch_ccm_long(bp, n, F, stride, tr, (int)b.rem, 1, st.carry_rec(),
+                                     st.carry_cnt(), ltmp, s, &b.pl.ct, 0)
+                   : launch_ccm_mfma(bp, n, F, stride, tr, (int)b.rem, 1, st.carry_sx(),
+                                     st.carry_sxy(), st.carry_cnt(), 0, 0, s, &b.pl.ct);
     if (e != hipSuccess) return dev(e, "rfi_submit: new carry");
   }
   // 4. clip, pooled with the stream state
@@ -611,8 +628,8 @@ rfi_status rfi_stream_open(rfi_session* s, const rfi_stream_config* c, int32_t* 
   if (cfg.eig_precision == 0) cfg.eig_precision = 32;
   if (cfg.max_sweeps == 0) cfg.max_sweeps = 12;
   if (cfg.max_iter == 0) cfg.max_iter = 50;
-  if (cfg.L < 1 || cfg.L > RFI_MAX_COUNT)
-    return fail(RFI_E_INVALID, "%s: L %d outside 1..%d", who, cfg.L, RFI_MAX_COUNT);
+  if (cfg.L < 1 || cfg.L > RFI_MAX_COUNT_LONG)
+    return fail(RFI_E_INVALID, "%s: L %d outside 1..%d", who, cfg.L, RFI_MAX_COUNT_LONG);
   if (!(cfg.kappa >= 0.0)) return fail(RFI_E_INVALID, "%s: kappa must be >= 0", who);
   if (cfg.beam_stage != 0 && cfg.beam_stage != 1)
     return fail(RFI_E_INVALID, "%s: beam_stage must be 0 or 1", who);
@@ -679,7 +696,7 @@ rfi_status rfi_submit(rfi_session* s, int32_t stream_id, const rfi_block* blk, u
                 blk->nbeam, blk->nchan, st.cfg.nbeam, st.cfg.nchan);
   if (blk->nsamp < 0) return fail(RFI_E_INVALID, "%s: nsamp < 0", who);
   rfi::BeamPtrs bp;
-  rfi_status rs = rfi::validate_block(blk, 0, st.cfg.L, 0, who, &bp);
+  rfi_status rs = rfi::validate_block(blk, 0, st.cfg.L, 0, who, &bp, RFI_MAX_COUNT_LONG);
   if (rs != RFI_OK) return rs;
   if (rfi::input_bytes(*blk) > s->budget)
     return fail(RFI_E_BUDGET, "%s: block of %lld bytes exceeds the budget of %lld", who,

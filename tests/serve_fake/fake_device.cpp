@@ -388,6 +388,17 @@ hipError_t launch_ccm_mfma(const BeamPtrs&, int, int, int64_t, int64_t, int L, i
   return hipSuccess;
 }
 
+size_t ccm_long_tmp_bytes(int, int, int) { return 256; }
+
+hipError_t launch_ccm_long(const BeamPtrs&, int, int, int64_t, int64_t, int L, int nsub, int64_t*,
+                           int32_t* count, void* tmp, hipStream_t s, const CcmTune*,
+                           int accumulate) {
+  if (take(g_fail_launch)) return hipErrorLaunchFailure;
+  if (nsub != 1 || !tmp) g_errors++;
+  work(s, [=] { count[0] = accumulate ? count[0] + L : L; });
+  return hipSuccess;
+}
+
 hipError_t launch_eig(const EigArgs& a, const rfi_eig_params&, hipStream_t s, int) {
   if (take(g_fail_launch)) return hipErrorLaunchFailure;
   const EigArgs g = a;

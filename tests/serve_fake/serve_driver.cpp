@@ -177,6 +177,46 @@ void order_and_carries() {
   std::printf("ok order_and_carries\n");
 }
 
+// Sub-intervals past the int32 bound: the carry is summed by the long route
+// (int64 records, counts after them), opened, extended, completed and opened
+// again; an ordinary stream runs beside it.
+void long_carries() {
+  fake_set_work_us(50);
+  rfi_session* s = make_session(2, 0);
+  CHECK(s);
+  const int Ls[2] = {RFI_MAX_COUNT + 7, 24};
+  int ids[2];
+  Expect ex[2] = {{Ls[0]}, {Ls[1]}};
+  for (int i = 0; i < 2; ++i) CHECK((ids[i] = open_stream(s, Ls[i])) > 0);
+  const int64_t sizes[2][5] = {{40000, 20000, 8000, 2, 70000}, {50, 3, 24, 100, 7}};
+  std::vector<std::unique_ptr<Block>> blocks;
+  std::vector<uint64_t> tickets;
+  std::vector<Expect::One> exp;
+  std::vector<int> sid;
+  uint32_t seed = 900;
+  for (int k = 0; k < 5; ++k)
+    for (int i = 0; i < 2; ++i) {
+      blocks.emplace_back(new Block(sizes[i][k], seed++));
+      uint64_t t = 0;
+      CHECK(rfi_submit(s, ids[i], &blocks.back()->blk, seed, &t) == RFI_OK);
+      tickets.push_back(t);
+      exp.push_back(ex[i].next(sizes[i][k]));
+      sid.push_back(i);
+    }
+  for (size_t k = 0; k < tickets.size(); ++k) {
+    rfi_result r{};
+    CHECK(rfi_wait(s, tickets[k], -1, &r) == RFI_OK);
+    CHECK(check_result(s, r, *blocks[k], exp[k], Ls[sid[k]]));
+  }
+  // one past the long bound is refused
+  rfi_stream_config c{NB, NC, RFI_MAX_COUNT_LONG + 1, 32, 12, 50, 3.0, nullptr, 0, 0, 1.0};
+  int32_t id = -1;
+  CHECK(rfi_stream_open(s, &c, &id) == RFI_E_INVALID);
+  rfi_session_destroy(s);
+  CHECK(fake_errors() == 0);
+  std::printf("ok long_carries\n");
+}
+
 void budget_and_no_head_of_line() {
   fake_set_work_us(3000);
   const int64_t big = (int64_t)NB * 2048 * STRIDE, small = (int64_t)NB * 256 * STRIDE;
@@ -403,6 +443,7 @@ void many_threads() {
 
 int main() {
   order_and_carries();
+  long_carries();
   budget_and_no_head_of_line();
   cancel_and_close();
   export_import();
