@@ -158,6 +158,23 @@ def counters(kernel: str, out_md: str, runs: list) -> None:
         lines.append(f"- VALU instructions per wave: {per['SQ_INSTS_VALU'] / per['SQ_WAVES']:.4g}")
         if "SQ_INSTS_LDS" in per:
             lines.append(f"- LDS instructions per wave: {per['SQ_INSTS_LDS'] / per['SQ_WAVES']:.4g}")
+    if "SQ_WAVES" in per and "SQ_WAVE_CYCLES" in per:
+        wc = per["SQ_WAVE_CYCLES"] / per["SQ_WAVES"]
+        lines.append(f"- wave lifetime (SQ_WAVE_CYCLES / SQ_WAVES, quad cycles): {wc:.4g}")
+        for c, what in (("SQ_ACTIVE_INST_VALU", "issuing VALU"),
+                        ("SQ_WAIT_ANY", "waiting on any counter (memory, LDS, scalar)"),
+                        ("SQ_WAIT_INST_ANY", "waiting on an instruction dependency")):
+            if c in per:
+                lines.append(f"- share of the wave lifetime {what} ({c}): "
+                             f"{per[c] / per['SQ_WAVES'] / wc:.3f}")
+        if "SQ_INSTS_SALU" in per:
+            lines.append(f"- SALU instructions per wave: {per['SQ_INSTS_SALU'] / per['SQ_WAVES']:.4g}")
+        if "SQ_INSTS_VMEM_RD" in per:
+            lines.append(f"- vector memory reads per wave: "
+                         f"{per['SQ_INSTS_VMEM_RD'] / per['SQ_WAVES']:.4g}")
+    if "SQ_INSTS_VALU_FMA_F32" in per and "SQ_WAVES" in per:
+        lines.append(f"- FP32 FMA instructions per wave: "
+                     f"{per['SQ_INSTS_VALU_FMA_F32'] / per['SQ_WAVES']:.4g}")
     if "SQ_INSTS_VALU_FMA_F64" in per:
         f64 = (2 * per["SQ_INSTS_VALU_FMA_F64"] + per.get("SQ_INSTS_VALU_ADD_F64", 0) +
                per.get("SQ_INSTS_VALU_MUL_F64", 0)) * 64
