@@ -290,6 +290,45 @@ __device__ __forceinline__ int lane_sturm(const float (&dg)[N], const float (&e2
   return c;
 }
 
+// The same count when every index is a beam (n == N): no padding selects.
+template <int N>
+__device__ __forceinline__ int lane_sturm_full(const float (&dg)[N], const float (&e2)[N],
+                                               float x) {
+  float q = 1.0f;
+  int c = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    float t = fmaf(-e2[i], __builtin_amdgcn_rcpf(q), dg[i] - x);
+    if (fabsf(t) < 1e-30f) t = -1e-30f;
+    q = t;
+    c += t < 0.f;
+  }
+  return c;
+}
+
+// Halvings of the Sturm bracket of lambda_1: the FP32 value to working
+// precision, or, when the FP64 refinement follows, only far enough to place
+// the inverse iteration's shift just above lambda_1 (2^-16 of the bracket;
+// the shift adds 2e-5 lambda_1 to its upper end).
+constexpr int kPassFull = 26;
+constexpr int kPassShift = 16;
+
+template <int N>
+__device__ __forceinline__ void bisect_lam1(const float (&dg)[N], const float (&e2)[N], int n,
+                                            int it0, int it1, float& lo, float& hi) {
+  if (n == N) {
+    for (int it = it0; it < it1; ++it) {
+      const float mid = 0.5f * (lo + hi);
+      if (lane_sturm_full<N>(dg, e2, mid) >= N) hi = mid; else lo = mid;
+    }
+  } else {
+    for (int it = it0; it < it1; ++it) {
+      const float mid = 0.5f * (lo + hi);
+      if (lane_sturm<N>(dg, e2, n, mid) >= n) hi = mid; else lo = mid;
+    }
+  }
+}
+
 template <int N>
 __device__ __forceinline__ void ritz_fp64(const EigArgs& g, int64_t ncell, int64_t cell, int n,
                                           int64_t cnt, float lam1, bool have_v, float (&v)[N],
@@ -455,11 +494,9 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
   glo -= 1e-6f * span;
   ghi += 1e-6f * span;
   float lo = fmaxf(glo, dmax - 1e-6f * span), hi = ghi;
-  for (int it = 0; it < 26; ++it) {
-    const float mid = 0.5f * (lo + hi);
-    if (lane_sturm<N>(dg, e2, n, mid) >= n) hi = mid; else lo = mid;
-  }
-  const float lam1 = 0.5f * (lo + hi);
+  const int npass = g.refine ? kPassShift : kPassFull;
+  bisect_lam1<N>(dg, e2, n, 0, npass, lo, hi);
+  float lam1 = 0.5f * (lo + hi);
   uint8_t st = degenerate ? RFI_CELL_DEGENERATE : 0;
 
   if (g.eigvals) {
@@ -499,7 +536,8 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
   float v[N], u[N];
   bool have_v = false;
   if (g.refine || g.v1) {
-    const float sigma = lam1 * (1.0f + 2e-5f) + 1e-6f;
+    // hi bounds lambda_1 from above (Sturm count n there)
+    const float sigma = hi * (1.0f + 2e-5f) + 1e-6f;
     // B = sigma I - T = L D L^T: pivots d_i (kept as 1 / d_i) and multipliers
     // l_i = B(i, i - 1) / d_{i-1} = -off_{i-1} / d_{i-1}; indices >= n (the
     // decoupled padding) get l = 1 / d = 0, so their components stay zero
@@ -517,6 +555,12 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
       l[i] = li;
       id[i] = i < n ? __builtin_amdgcn_rcpf(fmaxf(d, 1e-30f)) : 0.f;
     });
+    if (!ok && g.refine) {
+      // no refinement for this cell: its lambda_1 is the FP32 one, to
+      // working precision
+      bisect_lam1<N>(dg, e2, n, kPassShift, kPassFull, lo, hi);
+      lam1 = 0.5f * (lo + hi);
+    }
     start_vectors<N>(n, v, u);
     for (int it = 0; it < 3; ++it) {
       // L y = x (forward), y / d, then L^T z = y (backward), in place
