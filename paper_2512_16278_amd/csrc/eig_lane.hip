@@ -116,6 +116,78 @@ __device__ __forceinline__ int64_t pidx(int a, int b, int n) {
   return (int64_t)a * n - (int64_t)a * (a - 1) / 2 + (b - a);
 }
 
+// Where a lane finds the raw sums of its cell: S_a (row a of sum_x), S_aa and
+// S_ab (rows of sum_xy); pair k is (a, b) = UpperPair<N>(k). Padding indices
+// (>= n) read a clamped valid row. RowsDirect forms each row's address from
+// the arrays; RowsTable reads it from a per-workgroup table in LDS, filled
+// once, which spares every load the 64-bit scalar address arithmetic (about
+// ten scalar instructions each, 2 n + n (n - 1) / 2 loads per pass).
+template <int N>
+struct RowsDirect {
+  const int32_t* sx;
+  const int32_t* sxy;
+  int64_t ncell;
+  int n;
+  __device__ __forceinline__ int32_t S(int a, uint32_t off4) const {
+    return lane_row(sx, a < n ? a : 0, ncell, off4);
+  }
+  __device__ __forceinline__ int32_t Sdg(int a, uint32_t off4) const {
+    const int aa = a < n ? a : 0;
+    return lane_row(sxy, pidx(aa, aa, n), ncell, off4);
+  }
+  __device__ __forceinline__ int32_t pair(int a, int b, int, uint32_t off4) const {
+    return lane_row(sxy, b < n ? pidx(a, b, n) : 0, ncell, off4);   // b < n implies a < n
+  }
+};
+
+template <int N>
+struct RowTab {
+  static constexpr int K = 2 * N + N * (N - 1) / 2;   // S rows, S_aa rows, pairs
+};
+
+__device__ __forceinline__ int32_t lane_at(uint64_t row, uint32_t off4) {
+  typedef const __attribute__((address_space(1))) int32_t gint32;
+  return *(gint32*)((const char*)(uintptr_t)row + off4);
+}
+
+template <int N>
+struct RowsTable {
+  const uint64_t* tab;   // LDS, RowTab<N>::K row addresses
+  __device__ __forceinline__ int32_t S(int a, uint32_t off4) const { return lane_at(tab[a], off4); }
+  __device__ __forceinline__ int32_t Sdg(int a, uint32_t off4) const {
+    return lane_at(tab[N + a], off4);
+  }
+  __device__ __forceinline__ int32_t pair(int, int, int k, uint32_t off4) const {
+    return lane_at(tab[2 * N + k], off4);
+  }
+};
+
+// The table of a launch over one block (the same rows as RowsDirect reads),
+// filled by the workgroup's threads; the caller synchronises.
+template <int N>
+__device__ __forceinline__ void fill_rows(const EigArgs& g, uint64_t* tab) {
+  const int n = g.nbeam;
+  const int64_t ncell = (int64_t)g.nsub * g.nchan;
+  for (int e = threadIdx.x; e < RowTab<N>::K; e += blockDim.x) {
+    const int32_t* base;
+    int64_t row;
+    if (e < N) {
+      base = g.sum_x;
+      row = e < n ? e : 0;
+    } else if (e < 2 * N) {
+      const int aa = e - N < n ? e - N : 0;
+      base = g.sum_xy;
+      row = pidx(aa, aa, n);
+    } else {
+      const int k = e - 2 * N;
+      const int a = UpperPair<N>::row(k), b = UpperPair<N>::col(k);
+      base = g.sum_xy;
+      row = b < n ? pidx(a, b, n) : 0;
+    }
+    tab[e] = (uint64_t)(uintptr_t)(base + row * ncell);
+  }
+}
+
 // 1 / sqrt(x) for x > 0 to about 1 ulp: the hardware estimate and one Newton
 // step, r (3 - x r^2) / 2 (the correctly rounded division and square root
 // cost tens of instructions each, 2 n of them per cell).
@@ -127,10 +199,9 @@ __device__ __forceinline__ double rsqrt64(double x) {
 // Build the FP32 correlation matrix of one cell from its exact sums:
 // N_ab = cnt S_ab - S_a S_b in int64, r_ab = N_ab / sqrt(N_aa N_bb).
 // Padding indices (>= n) get an identity row and column.
-template <int N>
-__device__ __forceinline__ void load_corr32(const EigArgs& g, int64_t ncell, int64_t cell,
-                                            int n, int64_t cnt, float (&A)[Sym<N>::NP],
-                                            bool& degenerate) {
+template <int N, class Rows>
+__device__ __forceinline__ void load_corr32(const Rows& rows, int64_t cell, int n, int64_t cnt,
+                                            float (&A)[Sym<N>::NP], bool& degenerate) {
   // N_ab = cnt S_ab - S_a S_b is formed exactly in FP64: cnt S_ab < 2^47 and
   // S_a S_b < 2^48 are integers held exactly, and the FMA's one rounding is
   // exact too (|N_ab| < 2^48 < 2^53) -- cheaper than int64 arithmetic.
@@ -141,10 +212,9 @@ __device__ __forceinline__ void load_corr32(const EigArgs& g, int64_t ncell, int
   const uint32_t off4 = (uint32_t)cell * 4u;
   static_for<0, N>([&](auto Ai) {
     constexpr int a = RFI_CI(Ai);
-    const int aa = a < n ? a : 0;                    // clamped: always a valid address
-    S[a] = lane_row(g.sum_x, aa, ncell, off4);
+    S[a] = rows.S(a, off4);                          // clamped: always a valid address
     const double Sa = (double)S[a];
-    const double Saa = (double)lane_row(g.sum_xy, pidx(aa, aa, n), ncell, off4);
+    const double Saa = (double)rows.Sdg(a, off4);
     const double Naa = fma(cd, Saa, -Sa * Sa);
     dinv[a] = (a < n && Naa > 0.0) ? __builtin_amdgcn_rsqf((float)Naa) : 0.f;
     degenerate |= (a < n && Naa <= 0.0);
@@ -155,8 +225,8 @@ __device__ __forceinline__ void load_corr32(const EigArgs& g, int64_t ncell, int
     if constexpr (row_group_start<N, kRowGroup>(a)) __builtin_amdgcn_sched_barrier(0);
     static_for<a + 1, N>([&](auto Bi) {
       constexpr int b = RFI_CI(Bi);
-      const int64_t p = b < n ? pidx(a, b, n) : 0;   // b < n implies a < n
-      const double Sab = (double)lane_row(g.sum_xy, p, ncell, off4);
+      constexpr int k = a * N - a * (a + 1) / 2 + (b - a - 1);   // pair index in row order
+      const double Sab = (double)rows.pair(a, b, k, off4);
       const double Nab = fma(cd, Sab, -(double)S[a] * (double)S[b]);
       // no select on b < n: padding has dinv[b] = 0, and + 0 turns its -0
       // into +0, so the load stays unconditional and is issued with its group
@@ -224,7 +294,7 @@ __device__ __forceinline__ void jacobi_cell(const EigArgs& g, int64_t cell) {
   uint8_t st = 0;
   float A[Sym<N>::NP];
   bool degenerate;
-  load_corr32<N>(g, ncell, cell, n, cnt, A, degenerate);
+  load_corr32<N>(RowsDirect<N>{g.sum_x, g.sum_xy, ncell, n}, cell, n, cnt, A, degenerate);
   if (degenerate) st |= RFI_CELL_DEGENERATE;
 
   int sweep = 0;
@@ -329,8 +399,8 @@ __device__ __forceinline__ void bisect_lam1(const float (&dg)[N], const float (&
   }
 }
 
-template <int N>
-__device__ __forceinline__ void ritz_fp64(const EigArgs& g, int64_t ncell, int64_t cell, int n,
+template <int N, class Rows>
+__device__ __forceinline__ void ritz_fp64(const EigArgs& g, const Rows& rows, int64_t cell, int n,
                                           int64_t cnt, float lam1, bool have_v, float (&v)[N],
                                           float (&u)[N], uint8_t st);
 
@@ -384,8 +454,8 @@ __device__ __forceinline__ void orthonormalise(float (&v)[N], float (&u)[N]) {
 // an O(n) LDL^T factor and O(n) solves), the two vectors go back to C's basis
 // through the stored reflectors, Q y = H_0 H_1 ... y, and the FP64 Ritz pass
 // over the exact sums gives lambda_1 and the statistic (ritz_fp64).
-template <int N>
-__device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
+template <int N, class Rows>
+__device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell, const Rows& rows) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
   const int n = g.nbeam;
   const int64_t cnt = g.count[cell / g.nchan];
@@ -400,7 +470,7 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
   }
   float A[Sym<N>::NP];
   bool degenerate;
-  load_corr32<N>(g, ncell, cell, n, cnt, A, degenerate);
+  load_corr32<N>(rows, cell, n, cnt, A, degenerate);
 
   // The tridiagonal T stays in the matrix's own registers: its diagonal in
   // A(i, i) (final once step i - 1 is done) and its squared couplings in
@@ -604,7 +674,7 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell) {
     have_v = ok;
     if (!ok) st |= RFI_CELL_REFINE_FAILED;
   }
-  ritz_fp64<N>(g, ncell, cell, n, cnt, lam1, have_v, v, u, st);
+  ritz_fp64<N>(g, rows, cell, n, cnt, lam1, have_v, v, u, st);
 }
 
 // Kernel 2 of the Jacobi path: block inverse iteration and the FP64 Ritz value
@@ -633,7 +703,7 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
   if (g.refine || g.v1) {
     float A[Sym<N>::NP];
     bool dg;
-    load_corr32<N>(g, ncell, cell, n, cnt, A, dg);
+    load_corr32<N>(RowsDirect<N>{g.sum_x, g.sum_xy, ncell, n}, cell, n, cnt, A, dg);
     const float sigma = lam1 * (1.0f + 2e-5f) + 1e-6f;
     bool ok = true;
     static_for<0, N>([&](auto J) {
@@ -688,7 +758,8 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
     have_v = ok;
     if (!ok) st |= RFI_CELL_REFINE_FAILED;
   }
-  ritz_fp64<N>(g, ncell, cell, n, cnt, lam1, have_v, v, u, st);
+  ritz_fp64<N>(g, RowsDirect<N>{g.sum_x, g.sum_xy, ncell, n}, cell, n, cnt, lam1, have_v, v, u,
+               st);
 }
 
 // The FP64 part of the refinement: ||C||_F^2 from the exact sums and the
@@ -696,8 +767,8 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
 // vectors spanning nearly the eigenvectors of lambda_1 and lambda_2; unused
 // when !have_v, and then lambda_1 stays the FP32 lam1). Writes stat, status
 // and v1 (the Ritz vector).
-template <int N>
-__device__ __forceinline__ void ritz_fp64(const EigArgs& g, int64_t ncell, int64_t cell, int n,
+template <int N, class Rows>
+__device__ __forceinline__ void ritz_fp64(const EigArgs& g, const Rows& rows, int64_t cell, int n,
                                           int64_t cnt, float lam1, bool have_v, float (&v)[N],
                                           float (&u)[N], uint8_t st) {
   // FP64 pass over the exact sums: ||C||_F^2 and the projections of C on
@@ -724,9 +795,8 @@ __device__ __forceinline__ void ritz_fp64(const EigArgs& g, int64_t ncell, int64
     }
     static_for<0, N>([&](auto Ai) {
       constexpr int a = RFI_CI(Ai);
-      const int aa = a < n ? a : 0;
-      S[a] = lane_row(g.sum_x, aa, ncell, off4);
-      Sdg[a] = lane_row(g.sum_xy, pidx(aa, aa, n), ncell, off4);
+      S[a] = rows.S(a, off4);
+      Sdg[a] = rows.Sdg(a, off4);
     });
     __builtin_amdgcn_sched_barrier(0);
     static_for<0, N>([&](auto Ai) {
@@ -754,8 +824,7 @@ __device__ __forceinline__ void ritz_fp64(const EigArgs& g, int64_t ncell, int64
       static_for<k0, k1>([&](auto Ki) {
         constexpr int k = RFI_CI(Ki);
         constexpr int a = UpperPair<N>::row(k), b = UpperPair<N>::col(k);
-        const int64_t p = b < n ? pidx(a, b, n) : 0;   // b < n implies a < n
-        R[k - k0] = lane_row(g.sum_xy, p, ncell, off4);
+        R[k - k0] = rows.pair(a, b, k, off4);
       });
       __builtin_amdgcn_sched_barrier(0);
       static_for<k0, k1>([&](auto Ki) {
@@ -848,8 +917,11 @@ __global__ __launch_bounds__(256, 2) void eig_lane_jacobi(EigArgs g) {
 
 template <int N>
 __global__ __launch_bounds__(256, 1) void eig_lane_tri(EigArgs g) {
+  __shared__ uint64_t tab[RowTab<N>::K];
+  fill_rows<N>(g, tab);
+  __syncthreads();
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell < (int64_t)g.nsub * g.nchan) lanetri_cell<N>(g, cell);
+  if (cell < (int64_t)g.nsub * g.nchan) lanetri_cell<N>(g, cell, RowsTable<N>{tab});
 }
 
 template <int N>
@@ -888,7 +960,8 @@ __global__ __launch_bounds__(256, 1) void eig_lane_tri_batch(const EigArgs* item
   if (c >= total) return;
   const int i = find_item(cell0, nitem, c);
   const EigArgs g = items[i];
-  lanetri_cell<N>(g, c - cell0[i]);
+  lanetri_cell<N>(g, c - cell0[i],
+                  RowsDirect<N>{g.sum_x, g.sum_xy, (int64_t)g.nsub * g.nchan, g.nbeam});
 }
 
 template <int N>
