@@ -572,18 +572,27 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell, con
   if (g.eigvals) {
     // eigenvalue j (ascending) by bisection, then |lambda| descending
     float ev[N], key[N];
-    static_for<0, N>([&](auto J) {
-      constexpr int j = RFI_CI(J);
-      float a = glo, b = ghi;
-      if (j < n) {
-        for (int it = 0; it < 28; ++it) {
-          const float mid = 0.5f * (a + b);
-          if (lane_sturm<N>(dg, e2, n, mid) > j) b = mid; else a = mid;
+    // (the count without padding selects when the beams fill the instance)
+    auto bisect_all = [&](auto full) {
+      static_for<0, N>([&](auto J) {
+        constexpr int j = RFI_CI(J);
+        float a = glo, b = ghi;
+        if (j < n) {
+          for (int it = 0; it < 28; ++it) {
+            const float mid = 0.5f * (a + b);
+            const int c = decltype(full)::value ? lane_sturm_full<N>(dg, e2, mid)
+                                                : lane_sturm<N>(dg, e2, n, mid);
+            if (c > j) b = mid; else a = mid;
+          }
         }
-      }
-      ev[j] = 0.5f * (a + b);
-      key[j] = j < n ? fabsf(ev[j]) : -1.0f;
-    });
+        ev[j] = 0.5f * (a + b);
+        key[j] = j < n ? fabsf(ev[j]) : -1.0f;
+      });
+    };
+    if (n == N)
+      bisect_all(std::integral_constant<bool, true>{});
+    else
+      bisect_all(std::integral_constant<bool, false>{});
 #pragma unroll
     for (int pass = 0; pass < N; ++pass) {
 #pragma unroll
