@@ -378,10 +378,10 @@ __device__ __forceinline__ int lane_sturm_full(const float (&dg)[N], const float
 
 // Halvings of the Sturm bracket of lambda_1: the FP32 value to working
 // precision, or, when the FP64 refinement follows, only far enough to place
-// the inverse iteration's shift just above lambda_1 (2^-16 of the bracket;
+// the inverse iteration's shift just above lambda_1 (2^-12 of the bracket;
 // the shift adds 2e-5 lambda_1 to its upper end).
 constexpr int kPassFull = 26;
-constexpr int kPassShift = 16;
+constexpr int kPassShift = 12;
 
 template <int N>
 __device__ __forceinline__ void bisect_lam1(const float (&dg)[N], const float (&e2)[N], int n,
