@@ -279,8 +279,8 @@ __device__ __forceinline__ bool jacobi_sweep(float (&A)[Sym<N>::NP]) {
 // Kernel 1: correlation matrix and cyclic Jacobi. Writes the FP32 dominant
 // eigenvalue into stat[] (consumed by kernel 2), the optional sorted
 // eigenvalues, and the status bits of this stage.
-template <int N>
-__device__ __forceinline__ void jacobi_cell(const EigArgs& g, int64_t cell) {
+template <int N, class Rows>
+__device__ __forceinline__ void jacobi_cell(const EigArgs& g, int64_t cell, const Rows& rows) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
   const int n = g.nbeam;
   const int64_t cnt = g.count[cell / g.nchan];
@@ -294,7 +294,7 @@ __device__ __forceinline__ void jacobi_cell(const EigArgs& g, int64_t cell) {
   uint8_t st = 0;
   float A[Sym<N>::NP];
   bool degenerate;
-  load_corr32<N>(RowsDirect<N>{g.sum_x, g.sum_xy, ncell, n}, cell, n, cnt, A, degenerate);
+  load_corr32<N>(rows, cell, n, cnt, A, degenerate);
   if (degenerate) st |= RFI_CELL_DEGENERATE;
 
   int sweep = 0;
@@ -689,8 +689,8 @@ __device__ __forceinline__ void lanetri_cell(const EigArgs& g, int64_t cell, con
 // Kernel 2 of the Jacobi path: block inverse iteration and the FP64 Ritz value
 // of lambda_1; writes the statistic lambda_1^2 / ||C||_F^2, v1 and the
 // remaining status bits.
-template <int N>
-__device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
+template <int N, class Rows>
+__device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell, const Rows& rows) {
   const int64_t ncell = (int64_t)g.nsub * g.nchan;
   const int n = g.nbeam;
   const int64_t cnt = g.count[cell / g.nchan];
@@ -712,7 +712,7 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
   if (g.refine || g.v1) {
     float A[Sym<N>::NP];
     bool dg;
-    load_corr32<N>(RowsDirect<N>{g.sum_x, g.sum_xy, ncell, n}, cell, n, cnt, A, dg);
+    load_corr32<N>(rows, cell, n, cnt, A, dg);
     const float sigma = lam1 * (1.0f + 2e-5f) + 1e-6f;
     bool ok = true;
     static_for<0, N>([&](auto J) {
@@ -767,8 +767,7 @@ __device__ __forceinline__ void refine_cell(const EigArgs& g, int64_t cell) {
     have_v = ok;
     if (!ok) st |= RFI_CELL_REFINE_FAILED;
   }
-  ritz_fp64<N>(g, RowsDirect<N>{g.sum_x, g.sum_xy, ncell, n}, cell, n, cnt, lam1, have_v, v, u,
-               st);
+  ritz_fp64<N>(g, rows, cell, n, cnt, lam1, have_v, v, u, st);
 }
 
 // The FP64 part of the refinement: ||C||_F^2 from the exact sums and the
@@ -918,10 +917,16 @@ __device__ __forceinline__ void ritz_fp64(const EigArgs& g, const Rows& rows, in
   }
 }
 
+// The single-block kernels read their sums through the workgroup's table of
+// row addresses (RowsTable); the batched ones, whose workgroups can hold cells
+// of several blocks, form the addresses per lane (RowsDirect).
 template <int N>
 __global__ __launch_bounds__(256, 2) void eig_lane_jacobi(EigArgs g) {
+  __shared__ uint64_t tab[RowTab<N>::K];
+  fill_rows<N>(g, tab);
+  __syncthreads();
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell < (int64_t)g.nsub * g.nchan) jacobi_cell<N>(g, cell);
+  if (cell < (int64_t)g.nsub * g.nchan) jacobi_cell<N>(g, cell, RowsTable<N>{tab});
 }
 
 template <int N>
@@ -935,8 +940,11 @@ __global__ __launch_bounds__(256, 1) void eig_lane_tri(EigArgs g) {
 
 template <int N>
 __global__ __launch_bounds__(256, 1) void eig_lane_refine(EigArgs g) {
+  __shared__ uint64_t tab[RowTab<N>::K];
+  fill_rows<N>(g, tab);
+  __syncthreads();
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell < (int64_t)g.nsub * g.nchan) refine_cell<N>(g, cell);
+  if (cell < (int64_t)g.nsub * g.nchan) refine_cell<N>(g, cell, RowsTable<N>{tab});
 }
 
 // Batched: the cells of several blocks (one EigArgs each, in device memory)
@@ -958,7 +966,8 @@ __global__ __launch_bounds__(256, 2) void eig_lane_jacobi_batch(const EigArgs* i
   if (c >= total) return;
   const int i = find_item(cell0, nitem, c);
   const EigArgs g = items[i];
-  jacobi_cell<N>(g, c - cell0[i]);
+  jacobi_cell<N>(g, c - cell0[i],
+                 RowsDirect<N>{g.sum_x, g.sum_xy, (int64_t)g.nsub * g.nchan, g.nbeam});
 }
 
 template <int N>
@@ -981,7 +990,8 @@ __global__ __launch_bounds__(256, 1) void eig_lane_refine_batch(const EigArgs* i
   if (c >= total) return;
   const int i = find_item(cell0, nitem, c);
   const EigArgs g = items[i];
-  refine_cell<N>(g, c - cell0[i]);
+  refine_cell<N>(g, c - cell0[i],
+                 RowsDirect<N>{g.sum_x, g.sum_xy, (int64_t)g.nsub * g.nchan, g.nbeam});
 }
 
 template <int N>
